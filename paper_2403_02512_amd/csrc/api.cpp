@@ -1,0 +1,1256 @@
+// C-ABI entry points of libqsv: context/state lifetime, validation, lowering
+// of planned passes into kernel launches, expectation values and the adjoint
+// Jacobian (paper Sec. 2.1-2.2; the adjoint method of Jones & Gacon cited in
+// Sec. 2.1 and Sec. 3.1.1).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+
+#include "qsv_internal.h"
+
+using namespace qsv;
+
+// ------------------------------------------------------------------ errors
+
+namespace {
+thread_local std::string g_thread_err;
+
+struct QsvError : std::runtime_error {
+    qsv_status st;
+    QsvError(qsv_status s, const std::string& m) : std::runtime_error(m), st(s) {}
+};
+
+[[noreturn]] void fail(qsv_status s, const std::string& m) { throw QsvError(s, m); }
+
+void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) fail(QSV_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIPCHK(x) hip_check((x), #x)
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+}  // namespace
+
+struct qsv_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    int64_t opt_fusion = 1, opt_tile_bits = 0, opt_tile_bits_adj = 0, opt_low_bits = 0, opt_profile = 0,
+            opt_nontemporal = 0;
+    DevBuf ops, coef, words, partials, slots, pgroups, pterms, ws0, ws1;
+    void* pin = nullptr;
+    size_t pin_bytes = 0;
+    hipEvent_t pin_ev = nullptr;
+    bool pin_pending = false;
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> ev_pool;
+    int64_t st_launch[KK_COUNT] = {0};
+    double st_ms[KK_COUNT] = {0}, st_bytes[KK_COUNT] = {0};
+};
+
+struct qsv_state {
+    qsv_ctx* ctx;
+    int n;
+    qsv_dtype dt;
+    void* ptr;
+    bool owned;
+};
+
+namespace {
+
+template <typename F>
+qsv_status guard(qsv_ctx* ctx, F&& f) {
+    try {
+        f();
+        return QSV_OK;
+    } catch (const QsvError& e) {
+        g_thread_err = e.what();
+        if (ctx) ctx->err = e.what();
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        g_thread_err = "host allocation failed";
+        if (ctx) ctx->err = g_thread_err;
+        return QSV_ERR_OOM;
+    } catch (const std::exception& e) {
+        g_thread_err = e.what();
+        if (ctx) ctx->err = e.what();
+        return QSV_ERR_ARG;
+    }
+}
+
+void set_device(qsv_ctx* c) { HIPCHK(hipSetDevice(c->device)); }
+
+void ensure(qsv_ctx* c, DevBuf& b, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    if (b.bytes >= bytes) return;
+    if (b.p) {
+        HIPCHK(hipStreamSynchronize(c->stream));
+        HIPCHK(hipFree(b.p));
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    const size_t want = std::max(bytes, (size_t)4096);
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(QSV_ERR_OOM, "device allocation of " + std::to_string(want) + " bytes failed");
+    }
+    b.bytes = want;
+}
+
+void release(DevBuf& b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+// Stage host data into pinned memory and copy it to the device buffers, all
+// asynchronous on the context stream.  The pinned area is reused only after
+// the previous copies out of it completed.
+struct Upload {
+    DevBuf* dst;
+    const void* src;
+    size_t bytes;
+};
+void upload(qsv_ctx* c, std::initializer_list<Upload> ups) {
+    size_t total = 0;
+    for (auto& u : ups) total += (u.bytes + 255) & ~(size_t)255;
+    if (c->pin_pending) {
+        HIPCHK(hipEventSynchronize(c->pin_ev));
+        c->pin_pending = false;
+    }
+    if (c->pin_bytes < total) {
+        if (c->pin) HIPCHK(hipHostFree(c->pin));
+        c->pin = nullptr;
+        const size_t want = std::max(total, (size_t)1 << 20);
+        if (hipHostMalloc(&c->pin, want, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            c->pin_bytes = 0;
+            fail(QSV_ERR_OOM, "pinned host allocation failed");
+        }
+        c->pin_bytes = want;
+    }
+    size_t off = 0;
+    for (auto& u : ups) {
+        if (!u.bytes) continue;
+        ensure(c, *u.dst, u.bytes);
+        char* p = (char*)c->pin + off;
+        std::memcpy(p, u.src, u.bytes);
+        HIPCHK(hipMemcpyAsync(u.dst->p, p, u.bytes, hipMemcpyHostToDevice, c->stream));
+        off += (u.bytes + 255) & ~(size_t)255;
+    }
+    HIPCHK(hipEventRecord(c->pin_ev, c->stream));
+    c->pin_pending = true;
+}
+
+hipEvent_t get_event(qsv_ctx* c) {
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+}
+
+// Times one launch when profiling is on.
+struct Timed {
+    qsv_ctx* c;
+    int kind;
+    double bytes;
+    hipEvent_t a = nullptr;
+    Timed(qsv_ctx* c_, int k, double by) : c(c_), kind(k), bytes(by) {
+        if (c->opt_profile) {
+            a = get_event(c);
+            HIPCHK(hipEventRecord(a, c->stream));
+        }
+    }
+    void done(hipError_t launch_err) {
+        hip_check(launch_err, qsv::kKernelNames[kind]);
+        if (a) {
+            hipEvent_t b = get_event(c);
+            HIPCHK(hipEventRecord(b, c->stream));
+            c->recs.push_back({kind, a, b, bytes});
+            a = nullptr;
+        }
+    }
+};
+
+void flush_stats(qsv_ctx* c) {
+    if (c->recs.empty()) return;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (auto& r : c->recs) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+        c->st_launch[r.kind] += 1;
+        c->st_ms[r.kind] += ms;
+        c->st_bytes[r.kind] += r.bytes;
+        c->ev_pool.push_back(r.a);
+        c->ev_pool.push_back(r.b);
+    }
+    c->recs.clear();
+}
+
+// ------------------------------------------------------------------ validation
+
+void validate_ops_impl(int n, const qsv_op* ops, size_t n_ops, size_t n_params, size_t n_mat, const double* params,
+                       const double* matrices) {
+    if (n < 1 || n > QSV_MAX_QUBITS) fail(QSV_ERR_ARG, "n_qubits out of range");
+    if (n_ops && !ops) fail(QSV_ERR_ARG, "ops is NULL");
+    for (size_t i = 0; i < n_ops; ++i) {
+        const qsv_op& o = ops[i];
+        const std::string at = " (op " + std::to_string(i) + ")";
+        const int own = gate_own_wires(o.gate);
+        if (own < 0) fail(QSV_ERR_UNSUPPORTED, "unknown gate id " + std::to_string(o.gate) + at);
+        if (o.n_wires < 1 || o.n_wires > QSV_MAX_OP_WIRES || o.n_wires > n)
+            fail(QSV_ERR_WIRE, "bad wire count" + at);
+        if (o.n_ctrls < 0 || o.n_ctrls >= o.n_wires) fail(QSV_ERR_WIRE, "bad control count" + at);
+        if (o.n_ctrls < 32 && (o.ctrl_values >> o.n_ctrls) != 0) fail(QSV_ERR_ARG, "ctrl_values has bits beyond n_ctrls" + at);
+        const int k = o.n_wires - o.n_ctrls;
+        if (own > 0 && k != own) fail(QSV_ERR_WIRE, "gate takes " + std::to_string(own) + " own wires" + at);
+        if (o.gate == QSV_GATE_UNITARY && k > 6) fail(QSV_ERR_UNSUPPORTED, "QubitUnitary wider than 6 wires" + at);
+        for (int a = 0; a < o.n_wires; ++a) {
+            if (o.wires[a] < 0 || o.wires[a] >= n) fail(QSV_ERR_WIRE, "wire out of range" + at);
+            for (int b = 0; b < a; ++b)
+                if (o.wires[a] == o.wires[b]) fail(QSV_ERR_WIRE, "repeated wire" + at);
+        }
+        for (int s = 0; s < gate_n_angles(o.gate); ++s) {
+            if (o.param[s] < -1 || (o.param[s] >= 0 && (size_t)o.param[s] >= n_params))
+                fail(QSV_ERR_PARAM, "parameter index out of range" + at);
+            if (o.param[s] >= 0 && !params) fail(QSV_ERR_ARG, "params is NULL" + at);
+        }
+        if (o.gate == QSV_GATE_UNITARY) {
+            const size_t d = (size_t)1 << (2 * k);
+            if (!matrices) fail(QSV_ERR_ARG, "matrices is NULL" + at);
+            if (o.matrix_offset < 0 || (size_t)o.matrix_offset + d > n_mat)
+                fail(QSV_ERR_PARAM, "matrix_offset out of range" + at);
+        }
+    }
+}
+
+void validate_obs_impl(int n, const qsv_pauli_sum* obs, size_t n_obs) {
+    if (n_obs && !obs) fail(QSV_ERR_ARG, "observables are NULL");
+    const uint64_t all = n >= 64 ? ~0ull : ((1ull << n) - 1);
+    for (size_t o = 0; o < n_obs; ++o) {
+        const qsv_pauli_sum& h = obs[o];
+        if (h.n_terms < 0) fail(QSV_ERR_ARG, "negative term count");
+        if (h.n_terms && (!h.coeff || !h.x_mask || !h.z_mask)) fail(QSV_ERR_ARG, "observable arrays are NULL");
+        for (int64_t t = 0; t < h.n_terms; ++t)
+            if ((h.x_mask[t] | h.z_mask[t]) & ~all) fail(QSV_ERR_WIRE, "Pauli mask beyond n_qubits");
+    }
+}
+
+qsv_ctx* state_ctx(qsv_state* s) {
+    if (!s) fail(QSV_ERR_ARG, "state is NULL");
+    return s->ctx;
+}
+
+size_t elem_bytes(qsv_dtype d) { return d == QSV_C128 ? 16 : 8; }
+
+// ------------------------------------------------------------------ lowering
+
+struct Step {
+    enum Type { TILE, GATE1, DIAG1, GATE2, GATEK } type = TILE;
+    // tile
+    TileArgs ta{};
+    int grid = 1, nthr = 1, R = 1;
+    size_t lds = 0;
+    int nslots = 0, slot_base = 0;
+    // streaming gate
+    Expand ex{};
+    uint64_t n_items = 0, setmask = 0, tbit = 0, b0 = 0, b1 = 0;
+    int cls = 0, k = 0;
+    int32_t tb[6] = {0};
+    Mat2 m2{};
+    Mat4 m4{};
+    int64_t coff = 0;
+    double dre = 0, dim = 0;
+    double bytes = 0;
+};
+
+struct Program {
+    std::vector<TOp> tops;
+    std::vector<cd> coef;
+    std::vector<uint64_t> words;
+    std::vector<Step> steps;
+    std::vector<std::pair<int, double>> slot_param;  // global slot -> (param, coef)
+    size_t max_partials = 0;
+};
+
+int classify1(const std::vector<cd>& m) {
+    if (m[1] == 0.0 && m[2] == 0.0) return MC_DIAG;
+    if (m[0] == 0.0 && m[3] == 0.0) return MC_ANTI;
+    return MC_DENSE;
+}
+
+int classify2(const std::vector<cd>& m) {
+    bool diag = true;
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c)
+            if (r != c && m[r * 4 + c] != 0.0) diag = false;
+    if (diag) return MC_DIAG;
+    bool mid = m[0] == 1.0 && m[15] == 1.0;
+    for (int j = 0; j < 4 && mid; ++j) {
+        if (j != 0 && (m[0 * 4 + j] != 0.0 || m[j * 4 + 0] != 0.0)) mid = false;
+        if (j != 3 && (m[3 * 4 + j] != 0.0 || m[j * 4 + 3] != 0.0)) mid = false;
+    }
+    return mid ? MC_MID : MC_DENSE;
+}
+
+std::vector<cd> maybe_dag(const std::vector<cd>& m, int dim, bool d) {
+    if (!d) return m;
+    std::vector<cd> o(m.size());
+    for (int r = 0; r < dim; ++r)
+        for (int c = 0; c < dim; ++c) o[(size_t)c * dim + r] = std::conj(m[(size_t)r * dim + c]);
+    return o;
+}
+
+uint64_t wire_bit(int n, int w) { return 1ull << (n - 1 - w); }
+
+uint64_t deposit(uint64_t v, const int* sb, int nb) {
+    uint64_t o = 0;
+    for (int j = 0; j < nb; ++j)
+        if ((v >> j) & 1) o |= 1ull << sb[j];
+    return o;
+}
+
+uint64_t parity_bits_host(uint64_t x, const std::vector<uint64_t>& z) {
+    uint64_t p = 0;
+    for (size_t j = 0; j < z.size(); ++j) p |= (uint64_t)(__builtin_popcountll(x & z[j]) & 1) << j;
+    return p;
+}
+
+int tile_grid(uint64_t n_tiles) { return (int)std::min<uint64_t>(n_tiles, 4096); }
+
+// Lower one planned pass into a k_tile step.
+void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item>& items, const Pass& pass, int n,
+                bool two, bool dagger, size_t eb) {
+    Step st;
+    st.type = Step::TILE;
+    int sb[16], b = 0;
+    for (int bit = 0; bit < n; ++bit)
+        if ((pass.S >> bit) & 1) sb[b++] = bit;
+    int rank[64];
+    for (int j = 0; j < b; ++j) rank[sb[j]] = j;
+    const int nthr_log2 = std::min(b, 8);
+    const int nthr = 1 << nthr_log2, R = 1 << (b - nthr_log2);
+    if (R > (1 << TILE_MAX_R_LOG2)) fail(QSV_ERR_UNSUPPORTED, "tile too large");
+    TileArgs& a = st.ta;
+    std::memset(&a, 0, sizeof a);
+    a.outer = make_expand(std::vector<int>(sb, sb + b));
+    a.n_tiles = 1ull << (n - b);
+    for (int r = 0; r < R; ++r) a.offhi[r] = deposit((uint64_t)r << nthr_log2, sb, b);
+    for (int j = 0; j < b; ++j) a.sb[j] = sb[j];
+    a.b = b;
+    a.nthr_log2 = nthr_log2;
+    a.op0 = (int)P.tops.size();
+    st.nthr = nthr;
+    st.R = R;
+    st.grid = tile_grid(a.n_tiles);
+    st.slot_base = (int)P.slot_param.size();
+
+    // order: inside each run of diagonal items, inner products first, then
+    // un-applies (diagonal matrices commute); merge Z-parity rotations of
+    // equal angle and inner products of equal (param, coefficient).
+    std::vector<int> order;
+    {
+        size_t i = 0;
+        const auto& it = pass.items;
+        while (i < it.size()) {
+            if (items[it[i]].xbits) {
+                order.push_back(it[i]);
+                ++i;
+                continue;
+            }
+            size_t j = i;
+            while (j < it.size() && !items[it[j]].xbits) ++j;
+            for (size_t q = i; q < j; ++q)
+                if (items[it[q]].dot) order.push_back(it[q]);
+            for (size_t q = i; q < j; ++q)
+                if (!items[it[q]].dot) order.push_back(it[q]);
+            i = j;
+        }
+    }
+
+    int nslots = 0;
+    auto controls = [&](const Factor& f, TOp& op, bool local_ok) {
+        op.lcmask = op.lcval = 0;
+        op.gcmask = op.gcval = 0;
+        for (int j = 0; j < f.nc; ++j) {
+            const uint64_t bit = wire_bit(n, f.cw[j]);
+            const int p = n - 1 - f.cw[j];
+            if (local_ok && ((pass.S >> p) & 1)) {
+                op.lcmask |= 1u << rank[p];
+                if (f.cv[j]) op.lcval |= 1u << rank[p];
+            } else {
+                op.gcmask |= bit;
+                if (f.cv[j]) op.gcval |= bit;
+            }
+        }
+    };
+    // Z-parity groups: emit with host-precomputed per-thread / per-r parity masks
+    auto emit_zgroup = [&](int kind, const std::vector<uint64_t>& z, double angle, int slot) {
+        TOp op;
+        std::memset(&op, 0, sizeof op);
+        op.kind = kind;
+        op.m = (int)z.size();
+        op.slot = slot;
+        op.woff = (int64_t)P.words.size();
+        for (auto x : z) P.words.push_back(x);
+        for (int t = 0; t < nthr; ++t) P.words.push_back(parity_bits_host(deposit((uint64_t)t, sb, nthr_log2), z));
+        for (int r = 0; r < R; ++r) P.words.push_back(parity_bits_host(a.offhi[r], z));
+        op.coff = (int64_t)P.coef.size();
+        if (kind == OP_ZPHASE) {
+            const int m = (int)z.size();
+            for (int cnt = 0; cnt <= m; ++cnt) P.coef.push_back(std::exp(cd(0.0, -0.5 * angle * (m - 2 * cnt))));
+        }
+        P.tops.push_back(op);
+    };
+
+    size_t q = 0;
+    while (q < order.size()) {
+        const Item& it = items[order[q]];
+        const Factor& f = F[it.f];
+        const int dim = 1 << f.k;
+        if (it.dot && !it.xbits && f.zrot) {
+            // group of Z-parity generators with one (param, coef)
+            std::vector<uint64_t> z;
+            size_t e = q;
+            while (e < order.size() && z.size() < 64) {
+                const Item& jt = items[order[e]];
+                const Factor& g = F[jt.f];
+                if (!(jt.dot && !jt.xbits && g.zrot && g.param == f.param && g.coef == f.coef)) break;
+                uint64_t zm = 0;
+                for (int i = 0; i < g.k; ++i) zm |= wire_bit(n, g.tw[i]);
+                z.push_back(zm);
+                ++e;
+            }
+            P.slot_param.push_back({f.param, f.coef});
+            emit_zgroup(OP_DOTZSUM, z, 0.0, nslots++);
+            q = e;
+            continue;
+        }
+        if (!it.dot && !it.xbits && f.zrot) {
+            const double ang = dagger ? -f.zangle : f.zangle;
+            std::vector<uint64_t> z;
+            size_t e = q;
+            while (e < order.size() && z.size() < 64) {
+                const Item& jt = items[order[e]];
+                const Factor& g = F[jt.f];
+                if (!(!jt.dot && !jt.xbits && g.zrot && (dagger ? -g.zangle : g.zangle) == ang)) break;
+                uint64_t zm = 0;
+                for (int i = 0; i < g.k; ++i) zm |= wire_bit(n, g.tw[i]);
+                z.push_back(zm);
+                ++e;
+            }
+            emit_zgroup(OP_ZPHASE, z, ang, -1);
+            q = e;
+            continue;
+        }
+        TOp op;
+        std::memset(&op, 0, sizeof op);
+        op.k = f.k;
+        op.slot = -1;
+        op.coff = (int64_t)P.coef.size();
+        if (!it.xbits) {
+            // diagonal on global bits (targets and controls anywhere)
+            if (f.k > 6) fail(QSV_ERR_UNSUPPORTED, "diagonal factor wider than 6 targets");
+            op.kind = it.dot ? OP_DOTDIAG : OP_DIAG;
+            for (int i = 0; i < f.k; ++i) op.tb[i] = n - 1 - f.tw[i];
+            controls(f, op, false);
+            const std::vector<cd>& src = it.dot ? f.g : f.m;
+            for (int j = 0; j < dim; ++j) {
+                const cd d = src[(size_t)j * dim + j];
+                P.coef.push_back((!it.dot && dagger) ? std::conj(d) : d);
+            }
+        } else {
+            if (f.k > 6) fail(QSV_ERR_UNSUPPORTED, "factor wider than 6 targets");
+            for (int i = 0; i < f.k; ++i) op.tb[i] = rank[n - 1 - f.tw[i]];
+            controls(f, op, true);
+            const std::vector<cd> mm = it.dot ? f.g : maybe_dag(f.m, dim, dagger);
+            if (it.dot) {
+                op.kind = f.k == 1 ? OP_DOT1 : (f.k == 2 ? OP_DOT2 : OP_DOTK);
+            } else {
+                op.kind = f.k == 1 ? OP_APPLY1 : (f.k == 2 ? OP_APPLY2 : OP_APPLYK);
+                op.cls = f.k == 1 ? classify1(mm) : (f.k == 2 ? classify2(mm) : MC_DENSE);
+            }
+            for (auto& x : mm) P.coef.push_back(x);
+        }
+        if (it.dot) {
+            op.slot = nslots++;
+            P.slot_param.push_back({f.param, f.coef});
+        }
+        P.tops.push_back(op);
+        ++q;
+    }
+    a.nops = (int)P.tops.size() - a.op0;
+    a.nslots = nslots;
+    st.nslots = nslots;
+    st.lds = (size_t)tile_lds_bytes(b, two, (int)eb, nslots);
+    st.bytes = (double)(two ? 4 : 2) * (double)((uint64_t)1 << n) * (double)eb;
+    P.max_partials = std::max(P.max_partials, (size_t)nslots * st.grid);
+    P.steps.push_back(st);
+}
+
+// Lower a one-factor forward pass into a streaming kernel when one fits.
+bool lower_single(Program& P, const Factor& f, int n, size_t eb) {
+    const int dim = 1 << f.k;
+    std::vector<int> pos;
+    uint64_t setmask = 0;
+    for (int j = 0; j < f.nc; ++j) {
+        pos.push_back(n - 1 - f.cw[j]);
+        if (f.cv[j]) setmask |= wire_bit(n, f.cw[j]);
+    }
+    for (int i = 0; i < f.k; ++i) pos.push_back(n - 1 - f.tw[i]);
+    std::sort(pos.begin(), pos.end());
+    const double N = (double)((uint64_t)1 << n);
+    Step st;
+    st.n_items = (uint64_t)1 << (n - (int)pos.size());
+    st.ex = make_expand(pos);
+    st.setmask = setmask;
+    const double frac = std::ldexp(1.0, -f.nc);
+    if (f.k == 1) {
+        const int cls = classify1(f.m);
+        st.tbit = wire_bit(n, f.tw[0]);
+        if (cls == MC_DIAG && f.m[0] == 1.0) {
+            st.type = Step::DIAG1;
+            st.setmask |= st.tbit;
+            st.dre = f.m[3].real();
+            st.dim = f.m[3].imag();
+            st.bytes = N * eb * frac;  // read + write of half the (controlled) vector
+        } else {
+            st.type = Step::GATE1;
+            st.cls = cls;
+            for (int j = 0; j < 4; ++j) {
+                st.m2.re[j] = f.m[j].real();
+                st.m2.im[j] = f.m[j].imag();
+            }
+            st.bytes = 2.0 * N * eb * frac;
+        }
+    } else if (f.k == 2) {
+        st.type = Step::GATE2;
+        st.cls = classify2(f.m);
+        st.b0 = wire_bit(n, f.tw[0]);
+        st.b1 = wire_bit(n, f.tw[1]);
+        for (int j = 0; j < 16; ++j) {
+            st.m4.re[j] = f.m[j].real();
+            st.m4.im[j] = f.m[j].imag();
+        }
+        st.bytes = (st.cls == MC_MID ? 1.0 : 2.0) * N * eb * frac;
+    } else if (f.k <= 5) {
+        st.type = Step::GATEK;
+        st.k = f.k;
+        for (int i = 0; i < f.k; ++i) st.tb[i] = n - 1 - f.tw[i];
+        st.coff = (int64_t)P.coef.size();
+        for (int j = 0; j < dim * dim; ++j) P.coef.push_back(f.m[j]);
+        st.bytes = 2.0 * N * eb * frac;
+    } else {
+        return false;
+    }
+    P.steps.push_back(st);
+    return true;
+}
+
+PlanOptions plan_opts(int64_t tile_bits, int64_t low_bits, int64_t fusion, qsv_dtype dt, bool two) {
+    PlanOptions o;
+    const bool c128 = dt == QSV_C128;
+    int b = (int)tile_bits;
+    if (b <= 0) b = two ? (c128 ? 11 : 12) : (c128 ? 12 : 13);
+    o.b = std::min(b, 8 + TILE_MAX_R_LOG2);
+    o.low = low_bits > 0 ? (int)low_bits : (c128 ? 4 : 5);
+    o.fusion = fusion != 0;
+    return o;
+}
+
+PlanOptions plan_opts(qsv_ctx* c, qsv_dtype dt, bool two) {
+    return plan_opts(two ? c->opt_tile_bits_adj : c->opt_tile_bits, c->opt_low_bits, c->opt_fusion, dt, two);
+}
+
+Program build_program(const PlanOptions& po, const std::vector<Factor>& F, const std::vector<Item>& items, int n,
+                      qsv_dtype dt, bool two, bool dagger) {
+    Program P;
+    const size_t eb = elem_bytes(dt);
+    std::vector<Pass> passes = plan_passes(items, n, po);
+    for (const Pass& p : passes) {
+        if (!two && p.items.size() == 1 && !items[p.items[0]].dot) {
+            if (lower_single(P, F[items[p.items[0]].f], n, eb)) continue;
+        }
+        lower_tile(P, F, items, p, n, two, dagger, eb);
+    }
+    return P;
+}
+
+template <typename T>
+struct DevT {};
+
+// Launch every step of a program on (phi, lam).  Slot sums land in
+// slots + slot_offset + step.slot_base.
+void run_program(qsv_ctx* c, const Program& P, qsv_dtype dt, int n, void* phi, void* lam, double* slots,
+                 int slot_offset) {
+    const bool c128 = dt == QSV_C128;
+    const size_t cb = c128 ? 16 : 8;
+    for (const Step& st : P.steps) {
+        if (st.type == Step::TILE) {
+            Timed t(c, lam ? KK_TILE2 : KK_TILE1, st.bytes);
+            hipError_t e = c128 ? launch_tile<double>(c->stream, lam != nullptr, phi, lam, st.ta, (const TOp*)c->ops.p,
+                                                      c->coef.p, (const uint64_t*)c->words.p, (double*)c->partials.p,
+                                                      st.grid, st.nthr, st.R, st.lds)
+                                : launch_tile<float>(c->stream, lam != nullptr, phi, lam, st.ta, (const TOp*)c->ops.p,
+                                                     c->coef.p, (const uint64_t*)c->words.p, (double*)c->partials.p,
+                                                     st.grid, st.nthr, st.R, st.lds);
+            t.done(e);
+            if (st.nslots) {
+                Timed tr(c, KK_REDUCE, 8.0 * st.nslots * st.grid);
+                tr.done(launch_reduce(c->stream, (const double*)c->partials.p, st.grid, st.nslots,
+                                      slots + slot_offset + st.slot_base));
+            }
+            continue;
+        }
+        const int kind = st.type == Step::GATE1 ? KK_GATE1
+                         : st.type == Step::DIAG1 ? KK_DIAG1
+                         : st.type == Step::GATE2 ? KK_GATE2 : KK_GATEK;
+        Timed t(c, kind, st.bytes);
+        hipError_t e = hipSuccess;
+        switch (st.type) {
+        case Step::GATE1:
+            e = c128 ? launch_gate1<double>(c->stream, phi, st.n_items, st.ex, st.setmask, st.tbit, st.cls, st.m2)
+                     : launch_gate1<float>(c->stream, phi, st.n_items, st.ex, st.setmask, st.tbit, st.cls, st.m2);
+            break;
+        case Step::DIAG1:
+            e = c128 ? launch_diag1<double>(c->stream, phi, st.n_items, st.ex, st.setmask, st.dre, st.dim)
+                     : launch_diag1<float>(c->stream, phi, st.n_items, st.ex, st.setmask, st.dre, st.dim);
+            break;
+        case Step::GATE2:
+            e = c128 ? launch_gate2<double>(c->stream, phi, st.n_items, st.ex, st.setmask, st.b0, st.b1, st.cls, st.m4)
+                     : launch_gate2<float>(c->stream, phi, st.n_items, st.ex, st.setmask, st.b0, st.b1, st.cls, st.m4);
+            break;
+        case Step::GATEK:
+            e = c128 ? launch_gatek<double>(c->stream, phi, st.n_items, st.ex, st.setmask, st.k, st.tb,
+                                            (const char*)c->coef.p + st.coff * cb)
+                     : launch_gatek<float>(c->stream, phi, st.n_items, st.ex, st.setmask, st.k, st.tb,
+                                           (const char*)c->coef.p + st.coff * cb);
+            break;
+        default:
+            break;
+        }
+        t.done(e);
+    }
+}
+
+// Host coefficient table in the state's precision.
+std::vector<char> coef_bytes(const std::vector<cd>& coef, qsv_dtype dt) {
+    std::vector<char> out;
+    if (dt == QSV_C128) {
+        out.resize(coef.size() * 16);
+        std::memcpy(out.data(), coef.data(), out.size());
+    } else {
+        out.resize(coef.size() * 8);
+        float* f = (float*)out.data();
+        for (size_t i = 0; i < coef.size(); ++i) {
+            f[2 * i] = (float)coef[i].real();
+            f[2 * i + 1] = (float)coef[i].imag();
+        }
+    }
+    return out;
+}
+
+// Pauli sums -> grouped device tables (one entry range per observable).
+struct PauliTables {
+    std::vector<PauliGroupDev> groups;
+    std::vector<PauliTermDev> terms;
+    std::vector<std::pair<int, int>> obs_groups;  // (first group, count)
+    std::vector<int> n_x_groups;                  // groups with x != 0
+};
+
+void add_pauli(PauliTables& T, const qsv_pauli_sum& h, double scale) {
+    std::map<uint64_t, std::vector<int64_t>> by_x;
+    for (int64_t t = 0; t < h.n_terms; ++t) by_x[h.x_mask[t]].push_back(t);
+    const int g0 = (int)T.groups.size();
+    int nx = 0;
+    for (auto& kv : by_x) {
+        PauliGroupDev g;
+        g.x = kv.first;
+        g.t0 = (int)T.terms.size();
+        g.nt = (int)kv.second.size();
+        if (g.x) ++nx;
+        for (int64_t t : kv.second) {
+            const uint64_t z = h.z_mask[t];
+            const int ny = __builtin_popcountll(g.x & z) & 3;
+            // i^ny
+            const double c = h.coeff[t] * scale;
+            PauliTermDev tm;
+            tm.z = z;
+            tm.wre = ny == 0 ? c : (ny == 2 ? -c : 0.0);
+            tm.wim = ny == 1 ? c : (ny == 3 ? -c : 0.0);
+            T.terms.push_back(tm);
+        }
+        T.groups.push_back(g);
+    }
+    T.obs_groups.push_back({g0, (int)T.groups.size() - g0});
+    T.n_x_groups.push_back(nx);
+}
+
+// expval (or lambda) of observable o into slots[out_slot]
+void run_pauli(qsv_ctx* c, qsv_dtype dt, int n, const PauliTables& T, int o, const void* psi, void* lam, double* slot) {
+    const uint64_t N = 1ull << n;
+    const int grid = pauli_grid(N);
+    const double eb = (double)elem_bytes(dt);
+    const double bytes = (1.0 + T.n_x_groups[o] + (lam ? 1.0 : 0.0)) * (double)N * eb;
+    ensure(c, c->partials, (size_t)grid * 8);
+    const PauliGroupDev* g = (const PauliGroupDev*)c->pgroups.p + T.obs_groups[o].first;
+    const PauliTermDev* tm = (const PauliTermDev*)c->pterms.p;
+    Timed t(c, lam ? KK_PAULI_LAMBDA : KK_PAULI, bytes);
+    t.done(dt == QSV_C128 ? launch_pauli<double>(c->stream, lam != nullptr, psi, lam, N, g, T.obs_groups[o].second, tm,
+                                                 (double*)c->partials.p, grid)
+                          : launch_pauli<float>(c->stream, lam != nullptr, psi, lam, N, g, T.obs_groups[o].second, tm,
+                                                (double*)c->partials.p, grid));
+    Timed tr(c, KK_REDUCE, 8.0 * grid);
+    tr.done(launch_reduce(c->stream, (const double*)c->partials.p, grid, 1, slot));
+}
+
+void upload_program(qsv_ctx* c, const Program& P, qsv_dtype dt, const PauliTables* T) {
+    std::vector<char> cf = coef_bytes(P.coef, dt);
+    if (T)
+        upload(c, {{&c->ops, P.tops.data(), P.tops.size() * sizeof(TOp)},
+                   {&c->coef, cf.data(), cf.size()},
+                   {&c->words, P.words.data(), P.words.size() * 8},
+                   {&c->pgroups, T->groups.data(), T->groups.size() * sizeof(PauliGroupDev)},
+                   {&c->pterms, T->terms.data(), T->terms.size() * sizeof(PauliTermDev)}});
+    else
+        upload(c, {{&c->ops, P.tops.data(), P.tops.size() * sizeof(TOp)},
+                   {&c->coef, cf.data(), cf.size()},
+                   {&c->words, P.words.data(), P.words.size() * 8}});
+    ensure(c, c->partials, std::max<size_t>(P.max_partials, 1) * 8);
+}
+
+std::vector<Factor> forward_factors(const qsv_op* ops, size_t n_ops, const double* params, const double* matrices,
+                                    bool decompose) {
+    std::vector<Factor> F;
+    for (size_t i = 0; i < n_ops; ++i) {
+        const size_t f0 = F.size();
+        op_factors(ops[i], params, matrices, decompose, F);
+        for (size_t j = f0; j < F.size(); ++j) F[j].src_op = (int)i;
+    }
+    return F;
+}
+
+// Reverse sweep items: for each factor from the last, its generator inner
+// product (if it carries a trainable angle) and then its un-apply.
+std::vector<Item> adjoint_items(const std::vector<Factor>& F, int n) {
+    std::vector<Item> items;
+    for (int i = (int)F.size() - 1; i >= 0; --i) {
+        if (F[i].has_dot) items.push_back(make_item(F[i], true, i, n));
+        items.push_back(make_item(F[i], false, i, n));
+    }
+    return items;
+}
+
+std::vector<Item> forward_items(const std::vector<Factor>& F, int n) {
+    std::vector<Item> items;
+    for (size_t i = 0; i < F.size(); ++i) items.push_back(make_item(F[i], false, (int)i, n));
+    return items;
+}
+
+// The adjoint sweep for one combined observable set.  rows: n_rows Pauli
+// sums; each gets its own lambda and sweep (or one combined lambda for the
+// VJP).  out_rows[r * n_params + p] receives d<H_r>/dp, expv[r] = <H_r>.
+void adjoint_impl(qsv_state* s, const qsv_op* ops, size_t n_ops, const double* params, size_t n_params,
+                  const double* matrices, const std::vector<const qsv_pauli_sum*>& rows,
+                  const std::vector<double>& row_scale_vjp, bool vjp, double* out, double* expv, uint32_t flags) {
+    qsv_ctx* c = s->ctx;
+    const int n = s->n;
+    const uint64_t N = 1ull << n;
+    const size_t eb = elem_bytes(s->dt);
+    const size_t n_rows = vjp ? 1 : rows.size();
+    if ((flags & QSV_ADJ_INPLACE) && n_rows > 1)
+        fail(QSV_ERR_ARG, "QSV_ADJ_INPLACE needs a single observable (or the VJP form)");
+
+    std::vector<Factor> F = forward_factors(ops, n_ops, params, matrices, true);
+    std::vector<Item> items = adjoint_items(F, n);
+    Program P = build_program(plan_opts(c, s->dt, true), F, items, n, s->dt, true, true);
+    const size_t nslot = P.slot_param.size();
+
+    PauliTables T;
+    if (vjp) {
+        // lambda = sum_o cot_o H_o psi: one table with scaled coefficients
+        std::vector<double> co;
+        std::vector<uint64_t> xs, zs;
+        for (size_t o = 0; o < rows.size(); ++o)
+            for (int64_t t = 0; t < rows[o]->n_terms; ++t) {
+                co.push_back(rows[o]->coeff[t] * row_scale_vjp[o]);
+                xs.push_back(rows[o]->x_mask[t]);
+                zs.push_back(rows[o]->z_mask[t]);
+            }
+        qsv_pauli_sum h{(int64_t)co.size(), co.data(), xs.data(), zs.data()};
+        add_pauli(T, h, 1.0);
+        for (auto* r : rows) add_pauli(T, *r, 1.0);  // for the expvals
+    } else {
+        for (auto* r : rows) add_pauli(T, *r, 1.0);
+    }
+    upload_program(c, P, s->dt, &T);
+
+    // workspace: lambda, and phi unless the state itself is consumed
+    const bool inplace = (flags & QSV_ADJ_INPLACE) != 0;
+    ensure(c, c->ws0, N * eb);
+    if (!inplace) ensure(c, c->ws1, N * eb);
+    void* lam = c->ws0.p;
+    void* phi = inplace ? s->ptr : c->ws1.p;
+    const size_t n_ev = vjp ? rows.size() : n_rows;
+    ensure(c, c->slots, (n_rows * nslot + n_ev + 1) * 8);
+    double* slots = (double*)c->slots.p;
+    double* evslots = slots + n_rows * nslot;
+
+    if (vjp && expv)
+        for (size_t o = 0; o < rows.size(); ++o) run_pauli(c, s->dt, n, T, (int)(o + 1), s->ptr, nullptr, evslots + o);
+    for (size_t r = 0; r < n_rows; ++r) {
+        run_pauli(c, s->dt, n, T, (int)r, s->ptr, lam, vjp ? slots + n_rows * nslot + rows.size() : evslots + r);
+        if (!inplace) {
+            Timed t(c, KK_COPY, 2.0 * N * eb);
+            t.done(hipMemcpyAsync(phi, s->ptr, N * eb, hipMemcpyDeviceToDevice, c->stream));
+        }
+        run_program(c, P, s->dt, n, phi, lam, slots, (int)(r * nslot));
+    }
+    std::vector<double> host(n_rows * nslot + n_ev + 1);
+    HIPCHK(hipMemcpyAsync(host.data(), slots, host.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (size_t r = 0; r < n_rows; ++r) {
+        double* row = out + r * n_params;
+        std::fill(row, row + n_params, 0.0);
+        for (size_t q = 0; q < nslot; ++q) row[P.slot_param[q].first] += P.slot_param[q].second * host[r * nslot + q];
+    }
+    if (expv) {
+        for (size_t o = 0; o < n_ev; ++o) expv[o] = host[n_rows * nslot + o];
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ helpers used by kernels' callers
+
+Expand qsv::make_expand(const std::vector<int>& pos) {
+    Expand e;
+    std::memset(&e, 0, sizeof e);
+    const int m = (int)pos.size();
+    if (m + 1 > 16) fail(QSV_ERR_UNSUPPORTED, "too many inserted bits");
+    auto ones_below = [](int p) -> uint64_t { return p >= 64 ? ~0ull : ((1ull << p) - 1); };
+    if (m == 0) {
+        e.m[0] = ~0ull;
+        e.nm = 1;
+        return e;
+    }
+    e.m[0] = ones_below(pos[0]);
+    for (int i = 1; i < m; ++i) e.m[i] = ones_below(pos[i]) & ~ones_below(pos[i - 1] + 1);
+    e.m[m] = ~ones_below(pos[m - 1] + 1);
+    e.nm = m + 1;
+    return e;
+}
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+const char* qsv_version(void) { return "qsv 0.1.0 (gfx950)"; }
+
+const char* qsv_status_string(int st) {
+    switch (st) {
+    case QSV_OK: return "ok";
+    case QSV_ERR_ARG: return "invalid argument";
+    case QSV_ERR_WIRE: return "invalid wire";
+    case QSV_ERR_DTYPE: return "dtype mismatch";
+    case QSV_ERR_OOM: return "out of memory";
+    case QSV_ERR_HIP: return "HIP runtime error";
+    case QSV_ERR_UNSUPPORTED: return "unsupported";
+    case QSV_ERR_PARAM: return "invalid parameter index";
+    default: return "unknown status";
+    }
+}
+
+const char* qsv_thread_last_error(void) { return g_thread_err.c_str(); }
+
+int qsv_device_count(void) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return n;
+}
+
+int qsv_kernel_kinds(void) { return KK_COUNT; }
+const char* qsv_kernel_name(int kind) { return kind >= 0 && kind < KK_COUNT ? kKernelNames[kind] : ""; }
+
+qsv_status qsv_ctx_create(int device, void* hip_stream, qsv_ctx** out) {
+    return guard(nullptr, [&] {
+        if (!out) fail(QSV_ERR_ARG, "out is NULL");
+        *out = nullptr;
+        int nd = qsv_device_count();
+        if (device < 0 || device >= nd) fail(QSV_ERR_ARG, "no HIP device " + std::to_string(device));
+        std::unique_ptr<qsv_ctx> c(new qsv_ctx);
+        c->device = device;
+        set_device(c.get());
+        if (hip_stream) {
+            c->stream = (hipStream_t)hip_stream;
+        } else {
+            HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+            c->own_stream = true;
+        }
+        HIPCHK(hipEventCreateWithFlags(&c->pin_ev, hipEventDisableTiming));
+        *out = c.release();
+    });
+}
+
+void qsv_ctx_destroy(qsv_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (DevBuf* b : {&c->ops, &c->coef, &c->words, &c->partials, &c->slots, &c->pgroups, &c->pterms, &c->ws0, &c->ws1})
+        release(*b);
+    if (c->pin) (void)hipHostFree(c->pin);
+    for (auto& r : c->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->pin_ev) (void)hipEventDestroy(c->pin_ev);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char* qsv_last_error(const qsv_ctx* c) { return c ? c->err.c_str() : g_thread_err.c_str(); }
+
+qsv_status qsv_ctx_set_stream(qsv_ctx* c, void* hip_stream) {
+    return guard(c, [&] {
+        if (!c) fail(QSV_ERR_ARG, "ctx is NULL");
+        set_device(c);
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (c->own_stream) HIPCHK(hipStreamDestroy(c->stream));
+        if (hip_stream) {
+            c->stream = (hipStream_t)hip_stream;
+            c->own_stream = false;
+        } else {
+            HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+            c->own_stream = true;
+        }
+    });
+}
+
+qsv_status qsv_ctx_synchronize(qsv_ctx* c) {
+    return guard(c, [&] {
+        if (!c) fail(QSV_ERR_ARG, "ctx is NULL");
+        set_device(c);
+        HIPCHK(hipStreamSynchronize(c->stream));
+    });
+}
+
+qsv_status qsv_ctx_set_option(qsv_ctx* c, int option, int64_t v) {
+    return guard(c, [&] {
+        if (!c) fail(QSV_ERR_ARG, "ctx is NULL");
+        switch (option) {
+        case QSV_OPT_FUSION: c->opt_fusion = v != 0; break;
+        case QSV_OPT_TILE_BITS:
+            if (v < 0 || v > 8 + TILE_MAX_R_LOG2) fail(QSV_ERR_ARG, "tile bits out of range");
+            c->opt_tile_bits = v;
+            break;
+        case QSV_OPT_TILE_BITS_ADJ:
+            if (v < 0 || v > 8 + TILE_MAX_R_LOG2) fail(QSV_ERR_ARG, "tile bits out of range");
+            c->opt_tile_bits_adj = v;
+            break;
+        case QSV_OPT_LOW_BITS:
+            if (v < 0 || v > 8) fail(QSV_ERR_ARG, "low bits out of range");
+            c->opt_low_bits = v;
+            break;
+        case QSV_OPT_PROFILE: c->opt_profile = v != 0; break;
+        case QSV_OPT_NONTEMPORAL: c->opt_nontemporal = v != 0; break;
+        default: fail(QSV_ERR_ARG, "unknown option");
+        }
+    });
+}
+
+qsv_status qsv_ctx_get_option(qsv_ctx* c, int option, int64_t* v) {
+    return guard(c, [&] {
+        if (!c || !v) fail(QSV_ERR_ARG, "NULL argument");
+        switch (option) {
+        case QSV_OPT_FUSION: *v = c->opt_fusion; break;
+        case QSV_OPT_TILE_BITS: *v = c->opt_tile_bits; break;
+        case QSV_OPT_TILE_BITS_ADJ: *v = c->opt_tile_bits_adj; break;
+        case QSV_OPT_LOW_BITS: *v = c->opt_low_bits; break;
+        case QSV_OPT_PROFILE: *v = c->opt_profile; break;
+        case QSV_OPT_NONTEMPORAL: *v = c->opt_nontemporal; break;
+        default: fail(QSV_ERR_ARG, "unknown option");
+        }
+    });
+}
+
+qsv_status qsv_ctx_workspace_bytes(qsv_ctx* c, size_t* out) {
+    return guard(c, [&] {
+        if (!c || !out) fail(QSV_ERR_ARG, "NULL argument");
+        size_t t = 0;
+        for (DevBuf* b : {&c->ops, &c->coef, &c->words, &c->partials, &c->slots, &c->pgroups, &c->pterms, &c->ws0, &c->ws1})
+            t += b->bytes;
+        *out = t;
+    });
+}
+
+qsv_status qsv_ctx_release_workspace(qsv_ctx* c) {
+    return guard(c, [&] {
+        if (!c) fail(QSV_ERR_ARG, "ctx is NULL");
+        set_device(c);
+        HIPCHK(hipStreamSynchronize(c->stream));
+        release(c->ws0);
+        release(c->ws1);
+        release(c->partials);
+    });
+}
+
+qsv_status qsv_ctx_kernel_stats(qsv_ctx* c, int kind, int64_t* launches, double* ms, double* bytes) {
+    return guard(c, [&] {
+        if (!c) fail(QSV_ERR_ARG, "ctx is NULL");
+        if (kind < 0 || kind >= KK_COUNT) fail(QSV_ERR_ARG, "bad kernel kind");
+        set_device(c);
+        flush_stats(c);
+        if (launches) *launches = c->st_launch[kind];
+        if (ms) *ms = c->st_ms[kind];
+        if (bytes) *bytes = c->st_bytes[kind];
+    });
+}
+
+qsv_status qsv_ctx_reset_stats(qsv_ctx* c) {
+    return guard(c, [&] {
+        if (!c) fail(QSV_ERR_ARG, "ctx is NULL");
+        set_device(c);
+        flush_stats(c);
+        for (int k = 0; k < KK_COUNT; ++k) {
+            c->st_launch[k] = 0;
+            c->st_ms[k] = 0;
+            c->st_bytes[k] = 0;
+        }
+    });
+}
+
+qsv_status qsv_state_create(qsv_ctx* c, int n, qsv_dtype dt, qsv_state** out) {
+    return guard(c, [&] {
+        if (!c || !out) fail(QSV_ERR_ARG, "NULL argument");
+        *out = nullptr;
+        if (n < 1 || n > QSV_MAX_QUBITS) fail(QSV_ERR_ARG, "n_qubits out of range");
+        if (dt != QSV_C64 && dt != QSV_C128) fail(QSV_ERR_DTYPE, "unknown dtype");
+        set_device(c);
+        const size_t bytes = ((size_t)1 << n) * elem_bytes(dt);
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            fail(QSV_ERR_OOM, "state allocation of " + std::to_string(bytes) + " bytes failed");
+        }
+        std::unique_ptr<qsv_state> s(new qsv_state{c, n, dt, p, true});
+        Timed t(c, KK_INIT, (double)bytes);
+        t.done(dt == QSV_C128 ? launch_init<double>(c->stream, p, 1ull << n, 0)
+                              : launch_init<float>(c->stream, p, 1ull << n, 0));
+        *out = s.release();
+    });
+}
+
+qsv_status qsv_state_wrap(qsv_ctx* c, int n, qsv_dtype dt, void* dev_ptr, qsv_state** out) {
+    return guard(c, [&] {
+        if (!c || !out || !dev_ptr) fail(QSV_ERR_ARG, "NULL argument");
+        *out = nullptr;
+        if (n < 1 || n > QSV_MAX_QUBITS) fail(QSV_ERR_ARG, "n_qubits out of range");
+        if (dt != QSV_C64 && dt != QSV_C128) fail(QSV_ERR_DTYPE, "unknown dtype");
+        if ((uintptr_t)dev_ptr % elem_bytes(dt)) fail(QSV_ERR_ARG, "device pointer misaligned");
+        *out = new qsv_state{c, n, dt, dev_ptr, false};
+    });
+}
+
+void qsv_state_destroy(qsv_state* s) {
+    if (!s) return;
+    if (s->owned && s->ptr) {
+        (void)hipSetDevice(s->ctx->device);
+        (void)hipStreamSynchronize(s->ctx->stream);
+        (void)hipFree(s->ptr);
+    }
+    delete s;
+}
+
+int qsv_state_n_qubits(const qsv_state* s) { return s ? s->n : 0; }
+void* qsv_state_device_ptr(const qsv_state* s) { return s ? s->ptr : nullptr; }
+
+qsv_status qsv_state_reset(qsv_state* s, uint64_t basis) {
+    qsv_ctx* c = s ? s->ctx : nullptr;
+    return guard(c, [&] {
+        state_ctx(s);
+        if (basis >> s->n) fail(QSV_ERR_ARG, "basis index out of range");
+        set_device(c);
+        const uint64_t N = 1ull << s->n;
+        Timed t(c, KK_INIT, (double)(N * elem_bytes(s->dt)));
+        t.done(s->dt == QSV_C128 ? launch_init<double>(c->stream, s->ptr, N, basis)
+                                 : launch_init<float>(c->stream, s->ptr, N, basis));
+    });
+}
+
+qsv_status qsv_state_copy(qsv_state* dst, const qsv_state* src) {
+    qsv_ctx* c = dst ? dst->ctx : nullptr;
+    return guard(c, [&] {
+        if (!dst || !src) fail(QSV_ERR_ARG, "NULL state");
+        if (dst->n != src->n) fail(QSV_ERR_ARG, "qubit counts differ");
+        if (dst->dt != src->dt) fail(QSV_ERR_DTYPE, "dtypes differ");
+        set_device(c);
+        const size_t bytes = ((size_t)1 << dst->n) * elem_bytes(dst->dt);
+        Timed t(c, KK_COPY, 2.0 * bytes);
+        t.done(hipMemcpyAsync(dst->ptr, src->ptr, bytes, hipMemcpyDeviceToDevice, c->stream));
+    });
+}
+
+qsv_status qsv_state_to_host(const qsv_state* s, void* host) {
+    qsv_ctx* c = s ? s->ctx : nullptr;
+    return guard(c, [&] {
+        if (!s || !host) fail(QSV_ERR_ARG, "NULL argument");
+        set_device(c);
+        const size_t bytes = ((size_t)1 << s->n) * elem_bytes(s->dt);
+        HIPCHK(hipStreamSynchronize(c->stream));
+        HIPCHK(hipMemcpy(host, s->ptr, bytes, hipMemcpyDeviceToHost));
+    });
+}
+
+qsv_status qsv_state_from_host(qsv_state* s, const void* host) {
+    qsv_ctx* c = s ? s->ctx : nullptr;
+    return guard(c, [&] {
+        if (!s || !host) fail(QSV_ERR_ARG, "NULL argument");
+        set_device(c);
+        const size_t bytes = ((size_t)1 << s->n) * elem_bytes(s->dt);
+        HIPCHK(hipStreamSynchronize(c->stream));
+        HIPCHK(hipMemcpy(s->ptr, host, bytes, hipMemcpyHostToDevice));
+    });
+}
+
+qsv_status qsv_validate_ops(int n, const qsv_op* ops, size_t n_ops, size_t n_params, size_t n_mat) {
+    return guard(nullptr, [&] {
+        // parameters/matrices presence is checked by the hot-path calls
+        static const double dummy = 0.0;
+        validate_ops_impl(n, ops, n_ops, n_params, n_mat, &dummy, &dummy);
+    });
+}
+
+qsv_status qsv_validate_obs(int n, const qsv_pauli_sum* obs, size_t n_obs) {
+    return guard(nullptr, [&] {
+        if (n < 1 || n > QSV_MAX_QUBITS) fail(QSV_ERR_ARG, "n_qubits out of range");
+        validate_obs_impl(n, obs, n_obs);
+    });
+}
+
+qsv_status qsv_plan_stats(int n, qsv_dtype dt, const qsv_op* ops, size_t n_ops, const double* params,
+                          size_t n_params, const double* matrices, size_t n_mat, int adjoint, int tile_bits,
+                          int low_bits, int fusion, int64_t* n_passes, int64_t* n_tile_passes,
+                          int64_t* n_kernel_ops, double* alg_bytes) {
+    return guard(nullptr, [&] {
+        validate_ops_impl(n, ops, n_ops, n_params, n_mat, params, matrices);
+        if (dt != QSV_C64 && dt != QSV_C128) fail(QSV_ERR_DTYPE, "unknown dtype");
+        if (tile_bits < 0 || tile_bits > 8 + TILE_MAX_R_LOG2 || low_bits < 0 || low_bits > 8)
+            fail(QSV_ERR_ARG, "tile options out of range");
+        const bool two = adjoint != 0;
+        std::vector<Factor> F = forward_factors(ops, n_ops, params, matrices, two);
+        std::vector<Item> items = two ? adjoint_items(F, n) : forward_items(F, n);
+        Program P = build_program(plan_opts(tile_bits, low_bits, fusion, dt, two), F, items, n, dt, two, two);
+        int64_t tiles = 0;
+        double bytes = 0;
+        for (const Step& st : P.steps) {
+            tiles += st.type == Step::TILE;
+            bytes += st.bytes;
+        }
+        if (n_passes) *n_passes = (int64_t)P.steps.size();
+        if (n_tile_passes) *n_tile_passes = tiles;
+        if (n_kernel_ops) *n_kernel_ops = (int64_t)P.tops.size();
+        if (alg_bytes) *alg_bytes = bytes;
+    });
+}
+
+qsv_status qsv_apply(qsv_state* s, const qsv_op* ops, size_t n_ops, const double* params, size_t n_params,
+                     const double* matrices, size_t n_mat) {
+    qsv_ctx* c = s ? s->ctx : nullptr;
+    return guard(c, [&] {
+        state_ctx(s);
+        validate_ops_impl(s->n, ops, n_ops, n_params, n_mat, params, matrices);
+        if (!n_ops) return;
+        set_device(c);
+        std::vector<Factor> F = forward_factors(ops, n_ops, params, matrices, false);
+        std::vector<Item> items = forward_items(F, s->n);
+        Program P = build_program(plan_opts(c, s->dt, false), F, items, s->n, s->dt, false, false);
+        upload_program(c, P, s->dt, nullptr);
+        run_program(c, P, s->dt, s->n, s->ptr, nullptr, nullptr, 0);
+    });
+}
+
+qsv_status qsv_expval(qsv_state* s, const qsv_pauli_sum* obs, size_t n_obs, double* out) {
+    qsv_ctx* c = s ? s->ctx : nullptr;
+    return guard(c, [&] {
+        state_ctx(s);
+        validate_obs_impl(s->n, obs, n_obs);
+        if (n_obs && !out) fail(QSV_ERR_ARG, "out is NULL");
+        if (!n_obs) return;
+        set_device(c);
+        PauliTables T;
+        for (size_t o = 0; o < n_obs; ++o) add_pauli(T, obs[o], 1.0);
+        upload(c, {{&c->pgroups, T.groups.data(), T.groups.size() * sizeof(PauliGroupDev)},
+                   {&c->pterms, T.terms.data(), T.terms.size() * sizeof(PauliTermDev)}});
+        ensure(c, c->slots, n_obs * 8);
+        for (size_t o = 0; o < n_obs; ++o) run_pauli(c, s->dt, s->n, T, (int)o, s->ptr, nullptr, (double*)c->slots.p + o);
+        HIPCHK(hipMemcpyAsync(out, c->slots.p, n_obs * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    });
+}
+
+qsv_status qsv_adjoint_jacobian(qsv_state* s, const qsv_op* ops, size_t n_ops, const double* params, size_t n_params,
+                                const double* matrices, size_t n_mat, const qsv_pauli_sum* obs, size_t n_obs,
+                                double* jac, double* expval, uint32_t flags) {
+    qsv_ctx* c = s ? s->ctx : nullptr;
+    return guard(c, [&] {
+        state_ctx(s);
+        validate_ops_impl(s->n, ops, n_ops, n_params, n_mat, params, matrices);
+        validate_obs_impl(s->n, obs, n_obs);
+        if (n_obs == 0) return;
+        if (n_params && !jac) fail(QSV_ERR_ARG, "jac is NULL");
+        if (flags & ~QSV_ADJ_INPLACE) fail(QSV_ERR_ARG, "unknown flags");
+        set_device(c);
+        std::vector<const qsv_pauli_sum*> rows;
+        for (size_t o = 0; o < n_obs; ++o) rows.push_back(&obs[o]);
+        std::vector<double> jtmp(n_obs * std::max<size_t>(n_params, 1));
+        adjoint_impl(s, ops, n_ops, params, n_params, matrices, rows, {}, false, jtmp.data(), expval, flags);
+        if (n_params) std::memcpy(jac, jtmp.data(), n_obs * n_params * 8);
+    });
+}
+
+qsv_status qsv_adjoint_vjp(qsv_state* s, const qsv_op* ops, size_t n_ops, const double* params, size_t n_params,
+                           const double* matrices, size_t n_mat, const qsv_pauli_sum* obs, size_t n_obs,
+                           const double* cot, double* grad, double* expval, uint32_t flags) {
+    qsv_ctx* c = s ? s->ctx : nullptr;
+    return guard(c, [&] {
+        state_ctx(s);
+        validate_ops_impl(s->n, ops, n_ops, n_params, n_mat, params, matrices);
+        validate_obs_impl(s->n, obs, n_obs);
+        if (n_obs == 0) return;
+        if (!cot) fail(QSV_ERR_ARG, "cotangent is NULL");
+        if (n_params && !grad) fail(QSV_ERR_ARG, "grad is NULL");
+        if (flags & ~QSV_ADJ_INPLACE) fail(QSV_ERR_ARG, "unknown flags");
+        set_device(c);
+        std::vector<const qsv_pauli_sum*> rows;
+        std::vector<double> sc;
+        for (size_t o = 0; o < n_obs; ++o) {
+            rows.push_back(&obs[o]);
+            sc.push_back(cot[o]);
+        }
+        std::vector<double> g(std::max<size_t>(n_params, 1));
+        adjoint_impl(s, ops, n_ops, params, n_params, matrices, rows, sc, true, g.data(), expval, flags);
+        if (n_params) std::memcpy(grad, g.data(), n_params * 8);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,721 @@
+// HIP kernels of the qsv hot path for gfx950 (CDNA4, wave64).
+//
+//  k_init    psi = |basis>                                    (write-only stream)
+//  k_gate1   2x2 on amplitude pairs at the target's bit stride, optionally
+//            controlled (paper Alg. 1 / Alg. 2): classes dense, diagonal,
+//            anti-diagonal
+//  k_diag1   one phase on the amplitudes whose target and control bits are
+//            fixed (PhaseShift/Z/S/T and their controlled forms touch half
+//            the vector: Listing 1's "arr[i1] *= s")
+//  k_gate2   4x4 on amplitude quads (Ising gates, SWAP, Givens rotations)
+//  k_gatek   2^k x 2^k on 2^k-tuples, k = 3..5, one tuple per thread
+//  k_tile    LDS-staged pass: a tile of 2^b amplitudes spanning b index bits
+//            (always including the lowest ones, for coalescing) takes a whole
+//            list of gates, diagonal phase layers and adjoint inner products
+//            per HBM round trip; one or two vectors (phi, lambda)
+//  k_pauli   Pauli-sum expectation value / lambda = H psi, FP64 accumulation
+//            and wavefront-shuffle block reductions
+//  k_reduce  deterministic FP64 reduction of per-block partials
+//
+// Index conventions: wire w is index bit n-1-w; matrix index bit k-1-i
+// belongs to target i.
+#include "qsv_internal.h"
+
+namespace qsv {
+
+const char* const kKernelNames[KK_COUNT] = {"init",  "gate1", "diag1",        "gate2",        "gatek", "tile1",
+                                            "tile2", "pauli_expval", "pauli_lambda", "reduce", "copy"};
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// a * b + c
+template <typename T>
+__device__ __forceinline__ cx<T> cmad(cx<T> a, cx<T> b, cx<T> c) {
+    return {c.re + a.re * b.re - a.im * b.im, c.im + a.re * b.im + a.im * b.re};
+}
+// Im(conj(l) * v) in FP64
+template <typename T>
+__device__ __forceinline__ double im_conj_mul(cx<T> l, cx<T> v) {
+    return (double)l.re * (double)v.im - (double)l.im * (double)v.re;
+}
+
+__device__ __forceinline__ uint64_t expand_idx(uint64_t k, const Expand& e) {
+    uint64_t r = k & e.m[0];
+    for (int i = 1; i < e.nm; ++i) r |= (k << i) & e.m[i];
+    return r;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Adds the block-wide sum of v to *dst (one thread writes).  Every thread of
+// the block must call it; fixed summation order, so results are reproducible.
+__device__ __forceinline__ void block_add(double v, double* red, double* dst, int tid, int nthr) {
+    if (nthr >= 64) {
+        v = wave_sum(v);
+        if ((tid & 63) == 0) red[tid >> 6] = v;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+            for (int w = 0; w < (nthr >> 6); ++w) s += red[w];
+            *dst += s;
+        }
+    } else {
+        red[tid] = v;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+            for (int w = 0; w < nthr; ++w) s += red[w];
+            *dst += s;
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T>
+struct M2T {
+    cx<T> a, b, c, d;
+};
+template <typename T>
+__device__ __forceinline__ M2T<T> to_t(const Mat2& m) {
+    return {{(T)m.re[0], (T)m.im[0]}, {(T)m.re[1], (T)m.im[1]}, {(T)m.re[2], (T)m.im[2]}, {(T)m.re[3], (T)m.im[3]}};
+}
+
+// ------------------------------------------------------------------ init
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_init(cx<T>* __restrict__ psi, uint64_t N, uint64_t basis) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+        cx<T> v;
+        v.re = i == basis ? T(1) : T(0);
+        v.im = T(0);
+        psi[i] = v;
+    }
+}
+
+template <typename T>
+hipError_t launch_init(hipStream_t s, void* psi, uint64_t N, uint64_t basis) {
+    uint64_t blocks = (N + 1023) / 1024;
+    if (blocks > (1u << 20)) blocks = 1u << 20;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(k_init<T>, dim3((unsigned)blocks), dim3(256), 0, s, (cx<T>*)psi, N, basis);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ single-qubit streaming kernels
+
+constexpr int G1_ITEMS = 2;
+
+template <typename T, int CLS>
+__global__ __launch_bounds__(256) void k_gate1(cx<T>* __restrict__ psi, uint64_t n_items, Expand ex,
+                                               uint64_t setmask, uint64_t tbit, Mat2 mat) {
+    const M2T<T> m = to_t<T>(mat);
+    const uint64_t k0 = (uint64_t)blockIdx.x * (256 * G1_ITEMS) + threadIdx.x;
+    uint64_t i0[G1_ITEMS];
+    cx<T> a0[G1_ITEMS], a1[G1_ITEMS];
+#pragma unroll
+    for (int r = 0; r < G1_ITEMS; ++r) {
+        const uint64_t k = k0 + (uint64_t)r * 256;
+        i0[r] = k < n_items ? (expand_idx(k, ex) | setmask) : ~0ull;
+        if (k < n_items) {
+            a0[r] = psi[i0[r]];
+            a1[r] = psi[i0[r] | tbit];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < G1_ITEMS; ++r) {
+        if (i0[r] == ~0ull) continue;
+        cx<T> b0, b1;
+        if (CLS == MC_DENSE) {
+            b0 = cmad(m.a, a0[r], cmul(m.b, a1[r]));
+            b1 = cmad(m.c, a0[r], cmul(m.d, a1[r]));
+        } else if (CLS == MC_DIAG) {
+            b0 = cmul(m.a, a0[r]);
+            b1 = cmul(m.d, a1[r]);
+        } else {  // anti-diagonal
+            b0 = cmul(m.b, a1[r]);
+            b1 = cmul(m.c, a0[r]);
+        }
+        psi[i0[r]] = b0;
+        psi[i0[r] | tbit] = b1;
+    }
+}
+
+template <typename T>
+hipError_t launch_gate1(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex, uint64_t setmask,
+                        uint64_t tbit, int cls, const Mat2& m) {
+    const uint64_t blocks = (n_items + 256 * G1_ITEMS - 1) / (256 * G1_ITEMS);
+    dim3 g((unsigned)blocks), b(256);
+    if (cls == MC_DIAG)
+        hipLaunchKernelGGL((k_gate1<T, MC_DIAG>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, tbit, m);
+    else if (cls == MC_ANTI)
+        hipLaunchKernelGGL((k_gate1<T, MC_ANTI>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, tbit, m);
+    else
+        hipLaunchKernelGGL((k_gate1<T, MC_DENSE>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, tbit, m);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag1(cx<T>* __restrict__ psi, uint64_t n_items, Expand ex,
+                                               uint64_t setmask, double dre, double dim) {
+    const cx<T> d = {(T)dre, (T)dim};
+    const uint64_t k0 = (uint64_t)blockIdx.x * (256 * 4) + threadIdx.x;
+    uint64_t idx[4];
+    cx<T> a[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint64_t k = k0 + (uint64_t)r * 256;
+        idx[r] = k < n_items ? (expand_idx(k, ex) | setmask) : ~0ull;
+        if (k < n_items) a[r] = psi[idx[r]];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (idx[r] != ~0ull) psi[idx[r]] = cmul(d, a[r]);
+}
+
+template <typename T>
+hipError_t launch_diag1(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex, uint64_t setmask,
+                        double dre, double dim) {
+    const uint64_t blocks = (n_items + 1023) / 1024;
+    hipLaunchKernelGGL(k_diag1<T>, dim3((unsigned)blocks), dim3(256), 0, s, (cx<T>*)psi, n_items, ex, setmask,
+                       dre, dim);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ two-qubit streaming kernel
+
+template <typename T, int CLS>
+__global__ __launch_bounds__(256) void k_gate2(cx<T>* __restrict__ psi, uint64_t n_items, Expand ex,
+                                               uint64_t setmask, uint64_t b0, uint64_t b1, Mat4 mat) {
+    const uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= n_items) return;
+    const uint64_t i = expand_idx(k, ex) | setmask;
+    const uint64_t idx[4] = {i, i | b1, i | b0, i | b0 | b1};
+    if (CLS == MC_MID) {  // only |01>, |10> mix; |00>, |11> untouched
+        const cx<T> x1 = psi[idx[1]], x2 = psi[idx[2]];
+        const cx<T> m11 = {(T)mat.re[5], (T)mat.im[5]}, m12 = {(T)mat.re[6], (T)mat.im[6]};
+        const cx<T> m21 = {(T)mat.re[9], (T)mat.im[9]}, m22 = {(T)mat.re[10], (T)mat.im[10]};
+        psi[idx[1]] = cmad(m11, x1, cmul(m12, x2));
+        psi[idx[2]] = cmad(m21, x1, cmul(m22, x2));
+        return;
+    }
+    cx<T> a[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a[j] = psi[idx[j]];
+    if (CLS == MC_DIAG) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) psi[idx[j]] = cmul(cx<T>{(T)mat.re[j * 5], (T)mat.im[j * 5]}, a[j]);
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        cx<T> acc = {T(0), T(0)};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc = cmad(cx<T>{(T)mat.re[r * 4 + j], (T)mat.im[r * 4 + j]}, a[j], acc);
+        psi[idx[r]] = acc;
+    }
+}
+
+template <typename T>
+hipError_t launch_gate2(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex, uint64_t setmask, uint64_t b0,
+                        uint64_t b1, int cls, const Mat4& m) {
+    const uint64_t blocks = (n_items + 255) / 256;
+    dim3 g((unsigned)blocks), b(256);
+    if (cls == MC_MID)
+        hipLaunchKernelGGL((k_gate2<T, MC_MID>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, b0, b1, m);
+    else if (cls == MC_DIAG)
+        hipLaunchKernelGGL((k_gate2<T, MC_DIAG>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, b0, b1, m);
+    else
+        hipLaunchKernelGGL((k_gate2<T, MC_DENSE>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, b0, b1, m);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ k-qubit streaming kernel
+
+struct TBits {
+    int32_t tb[6];
+};
+
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_gatek(cx<T>* __restrict__ psi, uint64_t n_items, Expand ex,
+                                               uint64_t setmask, TBits tb, const cx<T>* __restrict__ mat) {
+    constexpr int D = 1 << K;
+    const uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= n_items) return;
+    const uint64_t base = expand_idx(k, ex) | setmask;
+    uint64_t off[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        uint64_t o = 0;
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if ((j >> (K - 1 - i)) & 1) o |= 1ull << tb.tb[i];
+        off[j] = o;
+    }
+    cx<T> a[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) a[j] = psi[base | off[j]];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        cx<T> acc = {T(0), T(0)};
+#pragma unroll
+        for (int j = 0; j < D; ++j) acc = cmad(mat[r * D + j], a[j], acc);
+        psi[base | off[r]] = acc;
+    }
+}
+
+template <typename T>
+hipError_t launch_gatek(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex, uint64_t setmask, int k,
+                        const int32_t* tbits, const void* mat) {
+    TBits tb;
+    for (int i = 0; i < 6; ++i) tb.tb[i] = i < k ? tbits[i] : 0;
+    const uint64_t blocks = (n_items + 255) / 256;
+    dim3 g((unsigned)blocks), b(256);
+    const cx<T>* m = (const cx<T>*)mat;
+    switch (k) {
+    case 3: hipLaunchKernelGGL((k_gatek<T, 3>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, tb, m); break;
+    case 4: hipLaunchKernelGGL((k_gatek<T, 4>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, tb, m); break;
+    case 5: hipLaunchKernelGGL((k_gatek<T, 5>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, tb, m); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ LDS-tiled fused pass
+
+// One op of a tile pass.  tp/tl: the phi/lambda tiles in LDS (tl only when
+// TWO).  The thread owns tile elements t = tid + r * nthr, r < R; pair and
+// quad ops address any element of the tile.
+template <typename T, bool TWO, int R>
+struct TileCtx {
+    cx<T>* tp;
+    cx<T>* tl;
+    double* red;
+    double* sacc;
+    const cx<T>* coef;
+    const uint64_t* words;
+    uint64_t base, offlo;
+    const uint64_t* offhi;
+    int tid, nthr;
+};
+
+template <typename T, bool TWO, int R>
+__device__ __forceinline__ void tile_apply1(const TileCtx<T, TWO, R>& c, const TOp& op) {
+    const int q = op.tb[0];
+    const uint32_t qb = 1u << q, lo = qb - 1;
+    const cx<T> m0 = c.coef[op.coff], m1 = c.coef[op.coff + 1], m2 = c.coef[op.coff + 2], m3 = c.coef[op.coff + 3];
+    const int half = (c.nthr * R) >> 1;
+    const int cls = op.cls;
+    for (int p = c.tid; p < half; p += c.nthr) {
+        const uint32_t t0 = (((uint32_t)p & ~lo) << 1) | ((uint32_t)p & lo), t1 = t0 | qb;
+        if ((t0 & op.lcmask) != op.lcval) continue;
+#pragma unroll
+        for (int v = 0; v < (TWO ? 2 : 1); ++v) {
+            cx<T>* t = v ? c.tl : c.tp;
+            const cx<T> a0 = t[t0], a1 = t[t1];
+            if (cls == MC_DIAG) {
+                t[t0] = cmul(m0, a0);
+                t[t1] = cmul(m3, a1);
+            } else if (cls == MC_ANTI) {
+                t[t0] = cmul(m1, a1);
+                t[t1] = cmul(m2, a0);
+            } else {
+                t[t0] = cmad(m0, a0, cmul(m1, a1));
+                t[t1] = cmad(m2, a0, cmul(m3, a1));
+            }
+        }
+    }
+}
+
+template <typename T, bool TWO, int R>
+__device__ __forceinline__ void tile_apply2(const TileCtx<T, TWO, R>& c, const TOp& op) {
+    const uint32_t b0 = 1u << op.tb[0], b1 = 1u << op.tb[1];
+    const uint32_t plo = b0 < b1 ? b0 : b1, phi = b0 < b1 ? b1 : b0;
+    const int quarter = (c.nthr * R) >> 2;
+    const cx<T>* m = c.coef + op.coff;
+    const int cls = op.cls;
+    for (int p = c.tid; p < quarter; p += c.nthr) {
+        uint32_t t = (((uint32_t)p & ~(plo - 1)) << 1) | ((uint32_t)p & (plo - 1));
+        t = ((t & ~(phi - 1)) << 1) | (t & (phi - 1));
+        if ((t & op.lcmask) != op.lcval) continue;
+        const uint32_t idx[4] = {t, t | b1, t | b0, t | b0 | b1};
+#pragma unroll
+        for (int v = 0; v < (TWO ? 2 : 1); ++v) {
+            cx<T>* tt = v ? c.tl : c.tp;
+            if (cls == MC_MID) {
+                const cx<T> x1 = tt[idx[1]], x2 = tt[idx[2]];
+                tt[idx[1]] = cmad(m[5], x1, cmul(m[6], x2));
+                tt[idx[2]] = cmad(m[9], x1, cmul(m[10], x2));
+            } else if (cls == MC_DIAG) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) tt[idx[j]] = cmul(m[j * 5], tt[idx[j]]);
+            } else {
+                cx<T> a[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) a[j] = tt[idx[j]];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    cx<T> acc = {T(0), T(0)};
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc = cmad(m[r * 4 + j], a[j], acc);
+                    tt[idx[r]] = acc;
+                }
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t spread_bits(int j, int k, const int32_t* tb) {
+    uint32_t o = 0;
+    for (int i = 0; i < k; ++i)
+        if ((j >> (k - 1 - i)) & 1) o |= 1u << tb[i];
+    return o;
+}
+
+// k >= 3 (and any k): every thread computes the new values of its own
+// elements, then all threads write back after a barrier.
+template <typename T, bool TWO, int R>
+__device__ __forceinline__ void tile_applyk(const TileCtx<T, TWO, R>& c, const TOp& op) {
+    const int k = op.k, dim = 1 << k;
+    uint32_t tmask = 0;
+    for (int i = 0; i < k; ++i) tmask |= 1u << op.tb[i];
+    int row[R];
+    uint32_t gb[R];
+    bool on[R];
+    cx<T> ap[R], al[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t t = c.tid + r * c.nthr;
+        int rw = 0;
+        for (int i = 0; i < k; ++i) rw = (rw << 1) | ((t >> op.tb[i]) & 1);
+        row[r] = rw;
+        gb[r] = t & ~tmask;
+        on[r] = (t & op.lcmask) == op.lcval;
+        ap[r] = {T(0), T(0)};
+        al[r] = {T(0), T(0)};
+    }
+    for (int j = 0; j < dim; ++j) {
+        const uint32_t sp = spread_bits(j, k, op.tb);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const cx<T> mm = c.coef[op.coff + row[r] * dim + j];
+            ap[r] = cmad(mm, c.tp[gb[r] | sp], ap[r]);
+            if (TWO) al[r] = cmad(mm, c.tl[gb[r] | sp], al[r]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!on[r]) continue;
+        const uint32_t t = c.tid + r * c.nthr;
+        c.tp[t] = ap[r];
+        if (TWO) c.tl[t] = al[r];
+    }
+}
+
+template <typename T, bool TWO, int R>
+__device__ __forceinline__ void tile_diag(const TileCtx<T, TWO, R>& c, const TOp& op) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint64_t g = c.base | c.offlo | c.offhi[r];
+        if ((g & op.gcmask) != op.gcval) continue;
+        int j = 0;
+        for (int i = 0; i < op.k; ++i) j = (j << 1) | (int)((g >> op.tb[i]) & 1);
+        const cx<T> d = c.coef[op.coff + j];
+        const int t = c.tid + r * c.nthr;
+        c.tp[t] = cmul(d, c.tp[t]);
+        if (TWO) c.tl[t] = cmul(d, c.tl[t]);
+    }
+}
+
+// parity masks of the op's z masks for this tile's base (uniform)
+__device__ __forceinline__ uint64_t parity_bits(uint64_t x, const uint64_t* z, int m) {
+    uint64_t p = 0;
+    for (int j = 0; j < m; ++j) p |= (uint64_t)(__popcll(x & z[j]) & 1) << j;
+    return p;
+}
+
+// Z-parity rotation group: the odd-parity bit mask of g = base|offlo|offhi[r]
+// is the XOR of the three parts' masks (parity is linear over GF(2)); the
+// per-thread and per-r parts are precomputed on the host.
+template <typename T, bool TWO, int R>
+__device__ __forceinline__ void tile_zphase(const TileCtx<T, TWO, R>& c, const TOp& op) {
+    const uint64_t* w = c.words + op.woff;
+    const uint64_t pb = parity_bits(c.base, w, op.m);
+    const uint64_t pl = w[op.m + c.tid] ^ pb;
+    const uint64_t* ph = w + op.m + c.nthr;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int cnt = __popcll(pl ^ ph[r]);
+        const cx<T> d = c.coef[op.coff + cnt];
+        const int t = c.tid + r * c.nthr;
+        c.tp[t] = cmul(d, c.tp[t]);
+        if (TWO) c.tl[t] = cmul(d, c.tl[t]);
+    }
+}
+
+template <typename T, bool TWO, int R>
+__device__ __forceinline__ void tile_dot(const TileCtx<T, TWO, R>& c, const TOp& op) {
+    if constexpr (TWO) {
+        double acc = 0.0;
+        const cx<T>* G = c.coef + op.coff;
+        if (op.kind == OP_DOT1) {
+            const uint32_t qb = 1u << op.tb[0], lo = qb - 1;
+            const int half = (c.nthr * R) >> 1;
+            for (int p = c.tid; p < half; p += c.nthr) {
+                const uint32_t t0 = (((uint32_t)p & ~lo) << 1) | ((uint32_t)p & lo), t1 = t0 | qb;
+                if ((t0 & op.lcmask) != op.lcval) continue;
+                const cx<T> p0 = c.tp[t0], p1 = c.tp[t1];
+                acc += im_conj_mul(c.tl[t0], cmad(G[0], p0, cmul(G[1], p1)));
+                acc += im_conj_mul(c.tl[t1], cmad(G[2], p0, cmul(G[3], p1)));
+            }
+        } else if (op.kind == OP_DOT2 || op.kind == OP_DOTK) {
+            const int k = op.k, dim = 1 << k;
+            uint32_t tmask = 0;
+            for (int i = 0; i < k; ++i) tmask |= 1u << op.tb[i];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint32_t t = c.tid + r * c.nthr;
+                if ((t & op.lcmask) != op.lcval) continue;
+                int rw = 0;
+                for (int i = 0; i < k; ++i) rw = (rw << 1) | ((t >> op.tb[i]) & 1);
+                const uint32_t gb = t & ~tmask;
+                cx<T> v = {T(0), T(0)};
+                for (int j = 0; j < dim; ++j) v = cmad(G[rw * dim + j], c.tp[gb | spread_bits(j, k, op.tb)], v);
+                acc += im_conj_mul(c.tl[t], v);
+            }
+        } else if (op.kind == OP_DOTDIAG) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint64_t g = c.base | c.offlo | c.offhi[r];
+                if ((g & op.gcmask) != op.gcval) continue;
+                int j = 0;
+                for (int i = 0; i < op.k; ++i) j = (j << 1) | (int)((g >> op.tb[i]) & 1);
+                const int t = c.tid + r * c.nthr;
+                acc += im_conj_mul(c.tl[t], cmul(G[j], c.tp[t]));
+            }
+        } else {  // OP_DOTZSUM: generator sum_j Z^{z_j}, eigenvalue m - 2 * (odd count)
+            const uint64_t* w = c.words + op.woff;
+            const uint64_t pb = parity_bits(c.base, w, op.m);
+            const uint64_t pl = w[op.m + c.tid] ^ pb;
+            const uint64_t* ph = w + op.m + c.nthr;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int cnt = __popcll(pl ^ ph[r]);
+                const int t = c.tid + r * c.nthr;
+                acc += (double)(op.m - 2 * cnt) * im_conj_mul(c.tl[t], c.tp[t]);
+            }
+        }
+        block_add(acc, c.red, c.sacc + op.slot, c.tid, c.nthr);
+    }
+}
+
+template <typename T, bool TWO, int LR>
+__global__ __launch_bounds__(256) void k_tile(cx<T>* __restrict__ phi, cx<T>* __restrict__ lam, const TileArgs a,
+                                              const TOp* __restrict__ ops, const cx<T>* __restrict__ coef,
+                                              const uint64_t* __restrict__ words, double* __restrict__ partials) {
+    constexpr int R = 1 << LR;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const int tsz = nthr * R;
+    TileCtx<T, TWO, R> c;
+    c.tp = reinterpret_cast<cx<T>*>(smem);
+    c.tl = c.tp + (TWO ? tsz : 0);
+    c.red = reinterpret_cast<double*>(smem + (TWO ? 2 : 1) * (size_t)tsz * sizeof(cx<T>));
+    c.sacc = c.red + 64;
+    c.coef = coef;
+    c.words = words;
+    c.offhi = a.offhi;
+    c.tid = tid;
+    c.nthr = nthr;
+    uint64_t offlo = 0;
+    for (int j = 0; j < a.nthr_log2; ++j) offlo |= (uint64_t)((tid >> j) & 1) << a.sb[j];
+    c.offlo = offlo;
+    for (int s = tid; s < a.nslots; s += nthr) c.sacc[s] = 0.0;
+
+    for (uint64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+        const uint64_t base = expand_idx(tile, a.outer);
+        c.base = base;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t g = base | offlo | a.offhi[r];
+            c.tp[tid + r * nthr] = phi[g];
+            if (TWO) c.tl[tid + r * nthr] = lam[g];
+        }
+        __syncthreads();
+        for (int oi = 0; oi < a.nops; ++oi) {
+            const TOp& op = ops[a.op0 + oi];
+            if ((op.kind <= OP_APPLYK || (op.kind >= OP_DOT1 && op.kind <= OP_DOTK)) &&
+                (base & op.gcmask) != op.gcval)
+                continue;  // outer controls fail for this whole tile (uniform)
+            switch (op.kind) {
+            case OP_APPLY1: tile_apply1(c, op); break;
+            case OP_APPLY2: tile_apply2(c, op); break;
+            case OP_APPLYK: tile_applyk(c, op); break;
+            case OP_DIAG: tile_diag(c, op); break;
+            case OP_ZPHASE: tile_zphase(c, op); break;
+            default: tile_dot(c, op); break;
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t g = base | offlo | a.offhi[r];
+            phi[g] = c.tp[tid + r * nthr];
+            if (TWO) lam[g] = c.tl[tid + r * nthr];
+        }
+        __syncthreads();
+    }
+    for (int s = tid; s < a.nslots; s += nthr) partials[(uint64_t)s * gridDim.x + blockIdx.x] = c.sacc[s];
+}
+
+int tile_lds_bytes(int b, bool two, int elem_bytes, int nslots) {
+    return (two ? 2 : 1) * (1 << b) * elem_bytes + 64 * 8 + nslots * 8;
+}
+
+template <typename T, bool TWO, int LR>
+static hipError_t launch_tile_lr(hipStream_t s, void* phi, void* lam, const TileArgs& a, const TOp* ops,
+                                 const void* coef, const uint64_t* words, double* partials, int grid, int nthr,
+                                 size_t lds) {
+    static bool attr_set = false;
+    if (lds > 65536 && !attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_tile<T, TWO, LR>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_tile<T, TWO, LR>), dim3(grid), dim3(nthr), lds, s, (cx<T>*)phi, (cx<T>*)lam, a, ops,
+                       (const cx<T>*)coef, words, partials);
+    return hipGetLastError();
+}
+
+template <typename T, bool TWO>
+static hipError_t launch_tile_two(hipStream_t s, void* phi, void* lam, const TileArgs& a, const TOp* ops,
+                                  const void* coef, const uint64_t* words, double* partials, int grid, int nthr,
+                                  int R, size_t lds) {
+    switch (R) {
+    case 1: return launch_tile_lr<T, TWO, 0>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
+    case 2: return launch_tile_lr<T, TWO, 1>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
+    case 4: return launch_tile_lr<T, TWO, 2>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
+    case 8: return launch_tile_lr<T, TWO, 3>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
+    case 16: return launch_tile_lr<T, TWO, 4>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
+    case 32: return launch_tile_lr<T, TWO, 5>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_tile(hipStream_t s, bool two, void* phi, void* lam, const TileArgs& a, const TOp* ops,
+                       const void* coef, const uint64_t* words, double* partials, int grid, int nthr, int R,
+                       size_t lds_bytes) {
+    if (two) return launch_tile_two<T, true>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, R, lds_bytes);
+    return launch_tile_two<T, false>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, R, lds_bytes);
+}
+
+// ------------------------------------------------------------------ Pauli sums
+
+// (P psi)_i = i^{nY} (-1)^{popcount((i ^ x) & z)} psi_{i ^ x}; terms sharing
+// an x mask share the load of psi_{i ^ x}.  Accumulation in FP64.
+template <typename T, bool WRITE>
+__global__ __launch_bounds__(256) void k_pauli(const cx<T>* __restrict__ psi, cx<T>* __restrict__ lam, uint64_t N,
+                                               const PauliGroupDev* __restrict__ groups, int n_groups,
+                                               const PauliTermDev* __restrict__ terms,
+                                               double* __restrict__ partials) {
+    __shared__ double red[64];
+    double dot = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += stride) {
+        const cx<T> pi = psi[i];
+        double ar = 0.0, ai = 0.0;
+        for (int g = 0; g < n_groups; ++g) {
+            const PauliGroupDev gr = groups[g];
+            const uint64_t src = i ^ gr.x;
+            const cx<T> ps = gr.x ? psi[src] : pi;
+            double sr = 0.0, si = 0.0;
+            for (int t = gr.t0; t < gr.t0 + gr.nt; ++t) {
+                const PauliTermDev tm = terms[t];
+                const bool neg = __popcll(src & tm.z) & 1;
+                sr += neg ? -tm.wre : tm.wre;
+                si += neg ? -tm.wim : tm.wim;
+            }
+            ar += sr * (double)ps.re - si * (double)ps.im;
+            ai += sr * (double)ps.im + si * (double)ps.re;
+        }
+        if (WRITE) lam[i] = cx<T>{(T)ar, (T)ai};
+        dot += (double)pi.re * ar + (double)pi.im * ai;
+    }
+    double tot = 0.0;
+    block_add(dot, red, &tot, threadIdx.x, 256);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+int pauli_grid(uint64_t N) {
+    uint64_t g = (N + 255) / 256;
+    if (g > 4096) g = 4096;
+    return (int)(g ? g : 1);
+}
+
+template <typename T>
+hipError_t launch_pauli(hipStream_t s, bool write_lambda, const void* psi, void* lam, uint64_t N,
+                        const PauliGroupDev* groups, int n_groups, const PauliTermDev* terms, double* partials,
+                        int grid) {
+    if (write_lambda)
+        hipLaunchKernelGGL((k_pauli<T, true>), dim3(grid), dim3(256), 0, s, (const cx<T>*)psi, (cx<T>*)lam, N, groups,
+                           n_groups, terms, partials);
+    else
+        hipLaunchKernelGGL((k_pauli<T, false>), dim3(grid), dim3(256), 0, s, (const cx<T>*)psi, (cx<T>*)lam, N,
+                           groups, n_groups, terms, partials);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ deterministic reduction
+
+__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ partials, int n_blocks,
+                                                double* __restrict__ out) {
+    __shared__ double red[64];
+    const int slot = blockIdx.x;
+    double s = 0.0;
+    for (int j = threadIdx.x; j < n_blocks; j += 256) s += partials[(uint64_t)slot * n_blocks + j];
+    double tot = 0.0;
+    block_add(s, red, &tot, threadIdx.x, 256);
+    if (threadIdx.x == 0) out[slot] = tot;
+}
+
+hipError_t launch_reduce(hipStream_t s, const double* partials, int n_blocks, int n_slots, double* out) {
+    if (n_slots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce, dim3(n_slots), dim3(256), 0, s, partials, n_blocks, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ instantiations
+
+#define QSV_INST(T)                                                                                              \
+    template hipError_t launch_init<T>(hipStream_t, void*, uint64_t, uint64_t);                                 \
+    template hipError_t launch_gate1<T>(hipStream_t, void*, uint64_t, const Expand&, uint64_t, uint64_t, int,   \
+                                        const Mat2&);                                                           \
+    template hipError_t launch_diag1<T>(hipStream_t, void*, uint64_t, const Expand&, uint64_t, double, double); \
+    template hipError_t launch_gate2<T>(hipStream_t, void*, uint64_t, const Expand&, uint64_t, uint64_t,        \
+                                        uint64_t, int, const Mat4&);                                            \
+    template hipError_t launch_gatek<T>(hipStream_t, void*, uint64_t, const Expand&, uint64_t, int,             \
+                                        const int32_t*, const void*);                                           \
+    template hipError_t launch_tile<T>(hipStream_t, bool, void*, void*, const TileArgs&, const TOp*,            \
+                                       const void*, const uint64_t*, double*, int, int, int, size_t);           \
+    template hipError_t launch_pauli<T>(hipStream_t, bool, const void*, void*, uint64_t, const PauliGroupDev*,  \
+                                        int, const PauliTermDev*, double*, int);
+
+QSV_INST(double)
+QSV_INST(float)
+
+}  // namespace qsv

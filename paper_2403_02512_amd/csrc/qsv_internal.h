@@ -1,0 +1,171 @@
+// Internal declarations of the qsv library (host runtime <-> HIP kernels).
+// Nothing here is part of the C ABI; see include/qsv.h for that.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "qsv.h"
+
+namespace qsv {
+
+using cd = std::complex<double>;
+
+// ------------------------------------------------------------------ device descriptors
+
+// Insert zero bits at sorted positions p_0 < .. < p_{m-1} of an index k:
+// r = (k & m[0]) | ((k << 1) & m[1]) | .. | ((k << m) & m[m]), where m[i]
+// keeps the output bits strictly between p_{i-1} and p_i (paper Alg. 2 and
+// its getMasks helper, read with the corrections listed in the design notes).
+struct Expand {
+    uint64_t m[16];
+    int32_t nm;  // number of masks = inserted positions + 1
+    int32_t pad;
+};
+
+Expand make_expand(const std::vector<int>& sorted_positions);
+
+enum TOpKind : int32_t {
+    OP_APPLY1 = 1,  // 2x2 on local tile bit tb[0]
+    OP_APPLY2,      // 4x4 on local tile bits tb[0] (msb), tb[1]
+    OP_APPLYK,      // 2^k x 2^k on local tile bits tb[0..k-1]
+    OP_DIAG,        // diagonal on global index bits tb[0..k-1]; table at coff
+    OP_ZPHASE,      // exp(-i a/2 sum_j Z^{z_j}) via a phase table over the odd-parity count
+    OP_DOT1,        // slot += Im <lam|G|phi> for G on local bit tb[0]
+    OP_DOT2,
+    OP_DOTK,
+    OP_DOTDIAG,     // slot += Im <lam|D|phi> for diagonal D on global bits
+    OP_DOTZSUM      // slot += Im <lam| sum_j Z^{z_j} |phi>
+};
+
+enum MatClass : int32_t { MC_DENSE = 0, MC_DIAG = 1, MC_ANTI = 2, MC_MID = 3 };
+
+struct TOp {
+    int32_t kind, cls, k, slot;
+    int32_t tb[6];
+    uint32_t lcmask, lcval;  // controls on local tile-index bits
+    uint64_t gcmask, gcval;  // controls on global index bits
+    int64_t coff;            // complex offset into the coefficient table
+    int64_t woff;            // u64 offset into the word table (ZPHASE/DOTZSUM)
+    int32_t m;               // number of parity masks (ZPHASE/DOTZSUM)
+    int32_t pad;
+};
+
+constexpr int TILE_MAX_R_LOG2 = 5;   // at most 32 elements per thread
+constexpr int TILE_THREADS = 256;
+
+struct TileArgs {
+    Expand outer;           // tile number -> base index (zeros at the tile bits)
+    uint64_t n_tiles;
+    uint64_t offhi[1 << TILE_MAX_R_LOG2];  // deposit of (r * nthr) into the tile bits
+    int32_t sb[16];         // tile bits, ascending (tile-local bit j <-> global bit sb[j])
+    int32_t b;              // tile bits
+    int32_t nthr_log2;
+    int32_t op0, nops;
+    int32_t nslots;
+    int32_t pad;
+};
+
+struct PauliGroupDev {
+    uint64_t x;
+    int32_t t0, nt;
+};
+struct PauliTermDev {
+    uint64_t z;
+    double wre, wim;  // coeff * i^{popcount(x & z)}
+};
+
+// ------------------------------------------------------------------ kernel families (profiling)
+
+enum KernelKind : int {
+    KK_INIT = 0, KK_GATE1, KK_DIAG1, KK_GATE2, KK_GATEK, KK_TILE1, KK_TILE2,
+    KK_PAULI, KK_PAULI_LAMBDA, KK_REDUCE, KK_COPY, KK_COUNT
+};
+extern const char* const kKernelNames[KK_COUNT];
+
+// ------------------------------------------------------------------ launchers (kernels.hip)
+// T is double (QSV_C128) or float (QSV_C64); every pointer is device memory.
+
+struct Mat2 { double re[4], im[4]; };
+struct Mat4 { double re[16], im[16]; };
+
+template <typename T> hipError_t launch_init(hipStream_t s, void* psi, uint64_t N, uint64_t basis);
+template <typename T> hipError_t launch_gate1(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex,
+                                              uint64_t setmask, uint64_t tbit, int cls, const Mat2& m);
+template <typename T> hipError_t launch_diag1(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex,
+                                              uint64_t setmask, double dre, double dim);
+template <typename T> hipError_t launch_gate2(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex,
+                                              uint64_t setmask, uint64_t b0, uint64_t b1, int cls, const Mat4& m);
+template <typename T> hipError_t launch_gatek(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex,
+                                              uint64_t setmask, int k, const int32_t* tbits, const void* mat);
+template <typename T> hipError_t launch_tile(hipStream_t s, bool two, void* phi, void* lam, const TileArgs& a,
+                                             const TOp* ops, const void* coef, const uint64_t* words,
+                                             double* partials, int grid, int nthr, int R, size_t lds_bytes);
+template <typename T> hipError_t launch_pauli(hipStream_t s, bool write_lambda, const void* psi, void* lam,
+                                              uint64_t N, const PauliGroupDev* groups, int n_groups,
+                                              const PauliTermDev* terms, double* partials, int grid);
+hipError_t launch_reduce(hipStream_t s, const double* partials, int n_blocks, int n_slots, double* out);
+
+int tile_lds_bytes(int b, bool two, int elem_bytes, int nslots);
+int pauli_grid(uint64_t N);
+
+// ------------------------------------------------------------------ host gate model (gates.cpp)
+
+// One unitary factor: matrix m (2^k x 2^k, first target = msb) on targets tw,
+// applied when every control wire cw[j] holds cv[j].
+struct Factor {
+    int k = 0;
+    int tw[8] = {0};
+    int nc = 0;
+    int cw[8] = {0};
+    int cv[8] = {0};
+    std::vector<cd> m;
+    // derivative of a trainable angle slot: contribution to d/dparams[param]
+    // is coef * Im<lam|G|phi> with G on the targets under the same controls
+    bool has_dot = false;
+    int param = -1;
+    double coef = 0.0;
+    std::vector<cd> g;
+    // exp(-i zangle/2 Z..Z) on the targets without controls (RZ, IsingZZ, MultiRZ)
+    bool zrot = false;
+    double zangle = 0.0;
+    int src_op = -1;
+};
+
+// Expand op into factors.  decompose: split Rot/U3/CRot into their one-angle
+// factors and attach derivative data (adjoint); otherwise one factor per op.
+void op_factors(const qsv_op& op, const double* params, const double* matrices, bool decompose,
+                std::vector<Factor>& out);
+
+int gate_own_wires(int gate);   // 0 = variable width; -1 = unknown gate
+int gate_n_angles(int gate);
+
+// ------------------------------------------------------------------ planner (plan.cpp)
+
+struct Item {
+    bool dot;        // generator inner product (else apply factor matrix)
+    int f;           // factor index
+    uint64_t xbits;  // index bits the item mixes (targets of a non-diagonal matrix)
+    uint64_t zbits;  // index bits it acts on diagonally (controls, diagonal targets)
+};
+
+struct Pass {
+    uint64_t S = 0;           // tile bits (global index bit mask)
+    std::vector<int> items;   // execution order
+};
+
+struct PlanOptions {
+    int b = 12;          // tile bits
+    int low = 4;         // coalescing low bits kept in every tile
+    bool fusion = true;
+    int max_scan = 2048; // look-ahead window of the greedy planner
+};
+
+std::vector<Pass> plan_passes(const std::vector<Item>& items, int n, const PlanOptions& opt);
+Item make_item(const Factor& f, bool dot, int fidx, int n);
+
+}  // namespace qsv

@@ -1,0 +1,249 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, element
+by element on the same seeded inputs.  Sizes span several LDS tiles (small
+tile options force many passes, outer controls and ragged plans at small n)."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_02512_amd import qsv
+from paper_2403_02512_amd import workloads as W
+from tests.gpu_helpers import (TOL, assert_state_close, gpu_run, jac_bound, obs_scale, oracle_state,
+                               reset_options)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = qsv.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(autouse=True)
+def _defaults(ctx):
+    reset_options(ctx)
+    yield
+
+
+DTYPES = [qsv.C128, qsv.C64]
+
+
+# ------------------------------------------------------------------ single gates (streaming kernels)
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("name", sorted(W.GATE_ARITY))
+def test_single_gate_every_placement(ctx, name, dt):
+    """Each gate alone (its own streaming kernel, or a one-op tile for wide
+    gates) on random states, every wire placement on 4 qubits and random
+    placements, controls and inverses at larger n."""
+    rng = np.random.default_rng(sum(map(ord, name)))
+    k, na = W.GATE_ARITY[name]
+    cases = []
+    kk = k or 3
+    for wires in itertools.permutations(range(4), kk):
+        cases.append((4, list(wires), 0, False))
+    for n in (kk, kk + 1, 7, 12, 15):
+        if n < kk:
+            continue
+        for _ in range(3):
+            nc = int(rng.integers(0, min(2, n - kk) + 1))
+            wires = list(rng.choice(n, size=kk + nc, replace=False))
+            cases.append((n, wires, nc, bool(rng.integers(2))))
+    for n, wires, nc, inv in cases:
+        slots = [(-1, float(rng.uniform(-4, 4))) for _ in range(na)]
+        mat = W.random_unitary(kk, rng) if name == "QubitUnitary" else None
+        cv = int(rng.integers(0, 1 << nc)) if nc else -1
+        o = W.op(name, wires, *slots, inverse=inv, n_ctrls=nc, ctrl_values=cv, matrix=mat)
+        psi0 = W.random_state(n, int(rng.integers(1 << 30)))
+        got = gpu_run(ctx, n, [o], [], dt, psi0)
+        ref = oracle_state(n, [o], [], psi0)
+        assert_state_close(got, ref, TOL[dt], f"{name} n={n} wires={wires} nc={nc} inv={inv}")
+
+
+# ------------------------------------------------------------------ fused random circuits
+
+TILE_OPTS = [
+    {},                                                        # defaults
+    {qsv.OPT_TILE_BITS: 5, qsv.OPT_LOW_BITS: 2},               # many small tiles, outer controls
+    {qsv.OPT_TILE_BITS: 8, qsv.OPT_LOW_BITS: 3},               # R = 1
+    {qsv.OPT_FUSION: 0},                                       # one kernel per gate
+]
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("opt", range(len(TILE_OPTS)))
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (5, 2), (8, 3), (11, 4), (14, 5), (16, 6)])
+def test_random_circuit_state(ctx, n, seed, opt, dt):
+    c = W.random_circuit(n, 80, seed=1000 + seed, n_params=9, p_ctrl=0.2, max_k=min(n, 5))
+    psi0 = W.random_state(n, seed)
+    got = gpu_run(ctx, n, c.ops, c.params, dt, psi0, TILE_OPTS[opt])
+    ref = oracle_state(n, c.ops, c.params, psi0)
+    assert_state_close(got, ref, TOL[dt] * (10 if dt == qsv.C64 else 1), f"n={n} seed={seed} opt={opt}")
+
+
+@pytest.mark.parametrize("n", [3, 9, 13])
+def test_wide_tiles_and_large_k(ctx, n):
+    """k = 5 and 6 dense unitaries (tile path for k = 6), diagonal MultiRZ of
+    every width, many controls."""
+    rng = np.random.default_rng(n)
+    ops = []
+    for _ in range(12):
+        k = int(rng.integers(1, min(6, n) + 1))
+        wires = list(rng.choice(n, size=k, replace=False))
+        ops.append(W.op("QubitUnitary", wires, matrix=W.random_unitary(k, rng)))
+        ops.append(W.op("MultiRZ", list(rng.choice(n, size=int(rng.integers(1, n + 1)), replace=False)),
+                        (-1, float(rng.uniform(-3, 3)))))
+    psi0 = W.random_state(n, 7)
+    for opts in ({}, {qsv.OPT_TILE_BITS: 6, qsv.OPT_LOW_BITS: 1}, {qsv.OPT_FUSION: 0}):
+        reset_options(ctx)
+        got = gpu_run(ctx, n, ops, [], qsv.C128, psi0, opts)
+        assert_state_close(got, oracle_state(n, ops, [], psi0), 1e-12, f"n={n} opts={opts}")
+
+
+def test_ghz_closed_form(ctx):
+    for n in (1, 2, 7, 20):
+        c = W.ghz(n)
+        got = gpu_run(ctx, n, c.ops, c.params)
+        want = np.zeros(1 << n, dtype=complex)
+        want[0] = want[-1] = 1 / np.sqrt(2)
+        if n == 1:
+            want = np.array([1, 1]) / np.sqrt(2)
+        assert_state_close(got, want, 1e-15, f"GHZ n={n}")
+
+
+def test_empty_circuit_and_reset(ctx):
+    st = qsv.State(ctx, 6)
+    qsv.apply(st, [], [])
+    ref = np.zeros(64, dtype=complex)
+    ref[0] = 1
+    assert np.array_equal(st.to_numpy(), ref)
+    st.reset(37)
+    ref[:] = 0
+    ref[37] = 1
+    assert np.array_equal(st.to_numpy(), ref)
+
+
+# ------------------------------------------------------------------ expectation values
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("n", [1, 2, 4, 9, 13, 17])
+def test_expval_random_pauli_sums(ctx, n, dt):
+    rng = np.random.default_rng(n)
+    psi = W.random_state(n, n + 100)
+    obs = W.random_observables(n, rng, n_obs=4, n_terms=7)
+    obs.append(W.PauliSum(np.array([0.7, -1.3]), ["Z" * n, "Y" * n]))
+    st = qsv.State(ctx, n, dt)
+    st.from_numpy(psi)
+    got = qsv.expval(st, obs)
+    ref = oracle.expval(psi.astype(np.complex64).astype(np.complex128) if dt == qsv.C64 else psi, obs)
+    err = np.abs(got - ref) / obs_scale(obs)
+    assert np.all(err <= TOL[dt]), err
+
+
+# ------------------------------------------------------------------ adjoint Jacobian
+
+@pytest.mark.parametrize("opt", range(3))
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (4, 2), (7, 3), (10, 4), (13, 5)])
+def test_adjoint_random_circuits(ctx, n, seed, opt):
+    c = W.random_circuit(n, 50, seed=2000 + seed, n_params=11, p_ctrl=0.2, max_k=min(n, 4))
+    obs = W.random_observables(n, np.random.default_rng(seed), n_obs=2, n_terms=4)
+    opts = [{}, {qsv.OPT_TILE_BITS_ADJ: 4, qsv.OPT_LOW_BITS: 2}, {qsv.OPT_FUSION: 0}][opt]
+    for k, v in opts.items():
+        ctx.set_option(k, v)
+    st = qsv.State(ctx, n)
+    qsv.apply(st, c.ops, c.params)
+    psi = st.to_numpy()
+    jac, ev = qsv.adjoint_jacobian(st, c.ops, c.params, obs)
+    np.testing.assert_array_equal(st.to_numpy(), psi)       # state preserved without INPLACE
+    ref_psi = oracle.apply(n, c.ops, c.params)
+    ref = oracle.adjoint_jacobian(ref_psi, c.ops, c.params, obs)
+    bound = jac_bound(c.ops, c.n_params, obs)
+    assert np.all(np.abs(jac - ref) <= 1e-12 * bound), np.max(np.abs(jac - ref) / bound)
+    assert np.all(np.abs(ev - oracle.expval(ref_psi, obs)) <= 1e-12 * obs_scale(obs))
+    # VJP with one sweep equals cotangent-weighted rows
+    cot = np.array([0.3, -1.7])
+    g, _ = qsv.adjoint_vjp(st, c.ops, c.params, obs, cot)
+    assert np.all(np.abs(g - cot @ ref) <= 1e-12 * (np.abs(cot) @ bound))
+
+
+def test_adjoint_inplace_returns_initial_state(ctx):
+    n = 9
+    c = W.random_circuit(n, 40, seed=77, n_params=6)
+    obs = W.random_observables(n, np.random.default_rng(1), n_obs=1, n_terms=3)
+    st = qsv.State(ctx, n)
+    qsv.apply(st, c.ops, c.params)
+    ref = oracle.adjoint_jacobian(oracle.apply(n, c.ops, c.params), c.ops, c.params, obs)
+    jac, _ = qsv.adjoint_jacobian(st, c.ops, c.params, obs, inplace=True)
+    assert np.all(np.abs(jac - ref) <= 1e-12 * jac_bound(c.ops, c.n_params, obs))
+    zero = np.zeros(1 << n, dtype=complex)
+    zero[0] = 1
+    assert_state_close(st.to_numpy(), zero, 1e-12, "state after in-place sweep")
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_config1_jacobian(ctx, dt):
+    c = W.config1()
+    st = qsv.State(ctx, c.n_qubits, dt)
+    qsv.apply(st, c.ops, c.params)
+    jac, ev = qsv.adjoint_jacobian(st, c.ops, c.params, c.observables)
+    psi = oracle.apply(c.n_qubits, c.ops, c.params)
+    ref = oracle.adjoint_jacobian(psi, c.ops, c.params, c.observables)
+    tol = 1e-12 if dt == qsv.C128 else 1e-5
+    assert np.max(np.abs(jac - ref)) <= tol * 2
+    assert abs(ev[0] - oracle.expval(psi, c.observables)[0]) <= tol
+
+
+@pytest.mark.parametrize("n", [8, 12, 16])
+def test_qaoa_reduced_width(ctx, n):
+    """QAOA MaxCut (config-3 generator) at reduced width: the Z-parity phase
+    groups and summed-generator inner products against the oracle's per-gate
+    loop."""
+    c = W.config3(n=n)
+    st = qsv.State(ctx, n)
+    qsv.apply(st, c.ops, c.params)
+    psi = oracle.apply(n, c.ops, c.params)
+    assert_state_close(st.to_numpy(), psi, 1e-12, "qaoa state")
+    jac, ev = qsv.adjoint_jacobian(st, c.ops, c.params, c.observables)
+    ref = oracle.adjoint_jacobian(psi, c.ops, c.params, c.observables)
+    assert np.all(np.abs(jac - ref) <= 1e-12 * jac_bound(c.ops, c.n_params, c.observables))
+    assert abs(ev[0] - oracle.expval(psi, c.observables)[0]) <= 1e-12 * len(c.edges)
+
+
+@pytest.mark.parametrize("n", [6, 11])
+def test_u3_brickwall_reduced_width(ctx, n):
+    c = W.config5(n=n, layers=6)
+    st = qsv.State(ctx, n)
+    qsv.apply(st, c.ops, c.params)
+    psi = oracle.apply(n, c.ops, c.params)
+    assert_state_close(st.to_numpy(), psi, 1e-12, "u3 state")
+    jac, _ = qsv.adjoint_jacobian(st, c.ops, c.params, c.observables)
+    ref = oracle.adjoint_jacobian(psi, c.ops, c.params, c.observables)
+    assert np.all(np.abs(jac - ref) <= 1e-12 * jac_bound(c.ops, c.n_params, c.observables))
+
+
+def test_torch_tensor_state(ctx):
+    import torch
+    n = 12
+    t = torch.zeros(1 << n, dtype=torch.complex128, device="cuda")
+    t[0] = 1
+    torch.cuda.synchronize()
+    c = W.random_circuit(n, 30, seed=5, n_params=4)
+    st = qsv.State(ctx, n, qsv.C128, tensor=t)
+    qsv.apply(st, c.ops, c.params)
+    ctx.synchronize()
+    np.testing.assert_allclose(t.cpu().numpy(), oracle.apply(n, c.ops, c.params), atol=1e-13)
+
+
+def test_invalid_call_leaves_state_untouched(ctx):
+    n = 5
+    st = qsv.State(ctx, n)
+    st.from_numpy(W.random_state(n, 3))
+    before = st.to_numpy()
+    with pytest.raises(qsv.QsvError):
+        qsv.apply(st, [W.op("RX", [0], (0, 1.0)), W.op("CNOT", [2, 9])], [0.3])
+    with pytest.raises(qsv.QsvError):
+        qsv.apply(st, [W.op("RX", [0], (3, 1.0))], [0.3])
+    np.testing.assert_array_equal(st.to_numpy(), before)
