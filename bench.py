@@ -60,6 +60,83 @@ def cpu_baseline(circ, k_ops: int = 10) -> dict:
                        f"in gates and terms")}
 
 
+def micro(n: int, reps: int = 5, dtype_name: str = "c128"):
+    """Per-kernel-class gate-apply bandwidth at n qubits: one JSON line per
+    (gate, wires) case with the algorithmic GB/s of its kernel (HIP events on
+    the launch stream) and the fraction of the 8 TB/s HBM peak."""
+    import torch
+    from paper_2403_02512_amd import qsv
+    from paper_2403_02512_amd import workloads as W
+
+    dt = qsv.C128 if dtype_name == "c128" else qsv.C64
+    dev = torch.device("cuda", 0)
+    ctx = qsv.Context(0, torch.cuda.current_stream(dev).cuda_stream)
+    psi = torch.empty(1 << n, dtype=torch.complex128 if dt == qsv.C128 else torch.complex64, device=dev)
+    st = qsv.State(ctx, n, dt, tensor=psi)
+    st.reset(0)
+    rng = np.random.default_rng(0)
+    w = lambda bit: n - 1 - bit          # wire of an index bit
+    cases = []
+    for b in (0, 1, 2, 3, 4, 5, 6, 7, 8, 12, 16, 20, 24, n - 1):
+        cases.append((f"RX bit{b}", [W.op("RX", [w(b)], (-1, 0.3))]))
+    for b in (0, n - 1):
+        cases.append((f"Hadamard bit{b}", [W.op("Hadamard", [w(b)])]))
+        cases.append((f"RZ bit{b}", [W.op("RZ", [w(b)], (-1, 0.3))]))
+        cases.append((f"PauliX bit{b}", [W.op("PauliX", [w(b)])]))
+        cases.append((f"PhaseShift bit{b}", [W.op("PhaseShift", [w(b)], (-1, 0.3))]))
+    for c, t in ((n - 1, 0), (0, n - 1), (13, 14)):
+        cases.append((f"CNOT ctrl{c} tgt{t}", [W.op("CNOT", [w(c), w(t)])]))
+        cases.append((f"CZ bits{c},{t}", [W.op("CZ", [w(c), w(t)])]))
+    cases.append(("Toffoli bits27,26->0", [W.op("Toffoli", [w(n - 1), w(n - 2), w(0)])]))
+    for a, b in ((0, 1), (0, n - 1), (13, 14), (n - 2, n - 1)):
+        cases.append((f"IsingXX bits{a},{b}", [W.op("IsingXX", [w(a), w(b)], (-1, 0.3))]))
+        cases.append((f"IsingZZ bits{a},{b}", [W.op("IsingZZ", [w(a), w(b)], (-1, 0.3))]))
+        cases.append((f"SWAP bits{a},{b}", [W.op("SWAP", [w(a), w(b)])]))
+        cases.append((f"SingleExcitation bits{a},{b}", [W.op("SingleExcitation", [w(a), w(b)], (-1, 0.3))]))
+    for k in (3, 4, 5, 6):
+        for lo in (True, False):
+            bits = list(range(k)) if lo else list(range(n - k, n))
+            cases.append((f"QubitUnitary k={k} {'low' if lo else 'high'} bits",
+                          [W.op("QubitUnitary", [w(b) for b in bits], matrix=W.random_unitary(k, rng))]))
+    cases.append(("fused 12 RX on bits 0-3,16-23", [W.op("RX", [w(b)], (-1, 0.1 * b)) for b in
+                                                    list(range(4)) + list(range(16, 24))]))
+    cases.append(("fused 28 RX layer", [W.op("RX", [w(b)], (-1, 0.1 * b)) for b in range(n)]))
+    q = W.config3(n=n)
+    cases.append(("QAOA forward (308 gates)", q.ops))
+    for name, ops in cases:
+        m = qsv.MarshalledOps(ops, q.params if ops is q.ops else np.zeros(0))
+        qsv.apply(st, ops, None, marshalled=m)
+        torch.cuda.synchronize()
+        ctx.set_option(qsv.OPT_PROFILE, 1)
+        ctx.reset_stats()
+        for _ in range(reps):
+            qsv.apply(st, ops, None, marshalled=m)
+        stats = ctx.kernel_stats()
+        ctx.set_option(qsv.OPT_PROFILE, 0)
+        tot_ms = sum(s["ms"] for s in stats.values()) / reps
+        tot_b = sum(s["bytes"] for s in stats.values()) / reps
+        kinds = {k: s["launches"] // reps for k, s in stats.items()}
+        gbs = tot_b / 1e9 / (tot_ms / 1e3)
+        print(json.dumps({"case": name, "n_qubits": n, "dtype": dtype_name, "kernels": kinds,
+                          "ms": round(tot_ms, 4), "alg_GB": round(tot_b / 1e9, 3), "GB_s": round(gbs, 1),
+                          "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4)}), flush=True)
+    # reference: torch's device-to-device copy kernel of the same state size
+    src = torch.empty_like(psi)
+    dst = torch.empty_like(psi)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    by = 2 * psi.numel() * psi.element_size()
+    print(json.dumps({"case": "torch copy_ (reference)", "ms": round(ms, 4), "alg_GB": by / 1e9,
+                      "GB_s": round(by / 1e9 / (ms / 1e3), 1), "frac_of_8TBs": round(by / 1e9 / (ms / 1e3) / 8000, 4)}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,11 +145,17 @@ def main():
     ap.add_argument("--n", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fusion", type=int, default=1)
+    ap.add_argument("--micro", action="store_true", help="per-kernel-class gate-apply bandwidth sweep")
+    ap.add_argument("--micro-dtype", default="c128", choices=["c128", "c64"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU state-vector "
               f"sharding is a design note, not part of this build", file=sys.stderr)
         sys.exit(2)
+
+    if args.micro:
+        micro(args.n, dtype_name=args.micro_dtype)
+        return
 
     import torch
     from paper_2403_02512_amd import qsv

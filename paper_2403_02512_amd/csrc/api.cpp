@@ -268,6 +268,7 @@ struct Step {
     int grid = 1, nthr = 1, R = 1;
     size_t lds = 0;
     int nslots = 0, slot_base = 0;
+    bool generic = false;  // the pass holds standalone (non-group) tile ops
     // streaming gate
     Expand ex{};
     uint64_t n_items = 0, setmask = 0, tbit = 0, b0 = 0, b1 = 0;
@@ -334,6 +335,17 @@ uint64_t parity_bits_host(uint64_t x, const std::vector<uint64_t>& z) {
 
 int tile_grid(uint64_t n_tiles) { return (int)std::min<uint64_t>(n_tiles, 4096); }
 
+// One lowered tile operation before grouping.
+struct Proto {
+    enum Kind { APPLY, DOT, DIAG, DOTDIAG, ZPHASE, DOTZSUM } kind;
+    int f = -1;                  // factor
+    std::vector<uint64_t> z;     // Z-parity masks (ZPHASE / DOTZSUM)
+    double angle = 0.0;          // ZPHASE
+    uint32_t tbits = 0;          // tile-local bits mixed (APPLY / DOT)
+    int k = 0;                   // targets
+    bool is_dot() const { return kind == DOT || kind == DOTDIAG || kind == DOTZSUM; }
+};
+
 // Lower one planned pass into a k_tile step.
 void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item>& items, const Pass& pass, int n,
                 bool two, bool dagger, size_t eb) {
@@ -362,8 +374,7 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
     st.slot_base = (int)P.slot_param.size();
 
     // order: inside each run of diagonal items, inner products first, then
-    // un-applies (diagonal matrices commute); merge Z-parity rotations of
-    // equal angle and inner products of equal (param, coefficient).
+    // un-applies (diagonal matrices commute)
     std::vector<int> order;
     {
         size_t i = 0;
@@ -384,7 +395,65 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
         }
     }
 
+    // protos, merging Z-parity rotations of equal angle and inner products of
+    // equal (param, coefficient)
+    std::vector<Proto> protos;
+    std::vector<std::pair<int, double>> proto_slot;  // for dot protos
+    auto zmask_of = [&](const Factor& g) {
+        uint64_t zm = 0;
+        for (int i = 0; i < g.k; ++i) zm |= wire_bit(n, g.tw[i]);
+        return zm;
+    };
+    size_t q = 0;
+    while (q < order.size()) {
+        const Item& it = items[order[q]];
+        const Factor& f = F[it.f];
+        Proto pr;
+        pr.f = it.f;
+        pr.k = f.k;
+        if (!it.xbits && f.zrot && (it.dot || true)) {
+            size_t e = q;
+            if (it.dot) {
+                pr.kind = Proto::DOTZSUM;
+                while (e < order.size() && pr.z.size() < 64) {
+                    const Item& jt = items[order[e]];
+                    const Factor& g = F[jt.f];
+                    if (!(jt.dot && !jt.xbits && g.zrot && g.param == f.param && g.coef == f.coef)) break;
+                    pr.z.push_back(zmask_of(g));
+                    ++e;
+                }
+            } else {
+                pr.kind = Proto::ZPHASE;
+                pr.angle = dagger ? -f.zangle : f.zangle;
+                while (e < order.size() && pr.z.size() < 64) {
+                    const Item& jt = items[order[e]];
+                    const Factor& g = F[jt.f];
+                    if (!(!jt.dot && !jt.xbits && g.zrot && (dagger ? -g.zangle : g.zangle) == pr.angle)) break;
+                    pr.z.push_back(zmask_of(g));
+                    ++e;
+                }
+            }
+            protos.push_back(pr);
+            q = e;
+            continue;
+        }
+        if (!it.xbits) {
+            if (f.k > 6) fail(QSV_ERR_UNSUPPORTED, "diagonal factor wider than 6 targets");
+            pr.kind = it.dot ? Proto::DOTDIAG : Proto::DIAG;
+        } else {
+            if (f.k > 6) fail(QSV_ERR_UNSUPPORTED, "factor wider than 6 targets");
+            pr.kind = it.dot ? Proto::DOT : Proto::APPLY;
+            for (int i = 0; i < f.k; ++i) pr.tbits |= 1u << rank[n - 1 - f.tw[i]];
+        }
+        protos.push_back(pr);
+        ++q;
+    }
+
+    const int GB = two ? GROUP_BITS_TWO : GROUP_BITS_ONE;
+    const bool grouped = b >= GB;
+    const int nsub = grouped ? (1 << (b - GB)) : 0;
     int nslots = 0;
+
     auto controls = [&](const Factor& f, TOp& op, bool local_ok) {
         op.lcmask = op.lcval = 0;
         op.gcmask = op.gcval = 0;
@@ -400,100 +469,148 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
             }
         }
     };
-    // Z-parity groups: emit with host-precomputed per-thread / per-r parity masks
-    auto emit_zgroup = [&](int kind, const std::vector<uint64_t>& z, double angle, int slot) {
+    // Emit one proto.  In a group (Q = group bits ascending, tile-local) the
+    // targets of local ops are positions in Q and Z-parity tables are indexed
+    // by subcube and element; standalone ops use the per-thread / per-r layout.
+    auto emit = [&](const Proto& pr, const std::vector<int>* Q, int& dslot) {
         TOp op;
         std::memset(&op, 0, sizeof op);
-        op.kind = kind;
-        op.m = (int)z.size();
-        op.slot = slot;
-        op.woff = (int64_t)P.words.size();
-        for (auto x : z) P.words.push_back(x);
-        for (int t = 0; t < nthr; ++t) P.words.push_back(parity_bits_host(deposit((uint64_t)t, sb, nthr_log2), z));
-        for (int r = 0; r < R; ++r) P.words.push_back(parity_bits_host(a.offhi[r], z));
+        op.k = pr.k;
+        op.slot = -1;
         op.coff = (int64_t)P.coef.size();
-        if (kind == OP_ZPHASE) {
-            const int m = (int)z.size();
-            for (int cnt = 0; cnt <= m; ++cnt) P.coef.push_back(std::exp(cd(0.0, -0.5 * angle * (m - 2 * cnt))));
+        if (pr.is_dot()) {
+            op.slot = nslots++;
+            const Factor& f = F[pr.f];
+            P.slot_param.push_back({f.param, f.coef});
+            if (Q) op.aux = dslot++;
         }
+        if (pr.kind == Proto::ZPHASE || pr.kind == Proto::DOTZSUM) {
+            op.kind = pr.kind == Proto::ZPHASE ? OP_ZPHASE : OP_DOTZSUM;
+            op.m = (int)pr.z.size();
+            op.woff = (int64_t)P.words.size();
+            for (auto x : pr.z) P.words.push_back(x);
+            if (Q) {
+                // per subcube: parity bits of the subcube's global offset;
+                // per element: of the element's offset inside the subcube
+                std::vector<int> nonq;
+                for (int j = 0; j < b; ++j)
+                    if (std::find(Q->begin(), Q->end(), j) == Q->end()) nonq.push_back(sb[j]);
+                for (int sc = 0; sc < nsub; ++sc) {
+                    uint64_t off = 0;
+                    for (size_t j = 0; j < nonq.size(); ++j)
+                        if ((sc >> j) & 1) off |= 1ull << nonq[j];
+                    P.words.push_back(parity_bits_host(off, pr.z));
+                }
+                for (int e = 0; e < (1 << GB); ++e) {
+                    uint64_t off = 0;
+                    for (int i = 0; i < GB; ++i)
+                        if ((e >> i) & 1) off |= 1ull << sb[(*Q)[i]];
+                    P.words.push_back(parity_bits_host(off, pr.z));
+                }
+            } else {
+                for (int t = 0; t < nthr; ++t)
+                    P.words.push_back(parity_bits_host(deposit((uint64_t)t, sb, nthr_log2), pr.z));
+                for (int r = 0; r < R; ++r) P.words.push_back(parity_bits_host(a.offhi[r], pr.z));
+            }
+            if (pr.kind == Proto::ZPHASE) {
+                const int m = (int)pr.z.size();
+                for (int cnt = 0; cnt <= m; ++cnt)
+                    P.coef.push_back(std::exp(cd(0.0, -0.5 * pr.angle * (m - 2 * cnt))));
+            }
+            P.tops.push_back(op);
+            return;
+        }
+        const Factor& f = F[pr.f];
+        const int dim = 1 << f.k;
+        const bool dot = pr.is_dot();
+        if (pr.kind == Proto::DIAG || pr.kind == Proto::DOTDIAG) {
+            op.kind = dot ? OP_DOTDIAG : OP_DIAG;
+            for (int i = 0; i < f.k; ++i) op.tb[i] = n - 1 - f.tw[i];
+            controls(f, op, false);
+            const std::vector<cd>& src = dot ? f.g : f.m;
+            for (int j = 0; j < dim; ++j) {
+                const cd d = src[(size_t)j * dim + j];
+                P.coef.push_back((!dot && dagger) ? std::conj(d) : d);
+            }
+            P.tops.push_back(op);
+            return;
+        }
+        controls(f, op, true);
+        const std::vector<cd> mm = dot ? f.g : maybe_dag(f.m, dim, dagger);
+        if (Q) {
+            for (int i = 0; i < f.k; ++i) {
+                const int tl = rank[n - 1 - f.tw[i]];
+                op.tb[i] = (int)(std::find(Q->begin(), Q->end(), tl) - Q->begin());
+            }
+        } else {
+            for (int i = 0; i < f.k; ++i) op.tb[i] = rank[n - 1 - f.tw[i]];
+        }
+        if (dot) {
+            op.kind = f.k == 1 ? OP_DOT1 : (f.k == 2 ? OP_DOT2 : OP_DOTK);
+        } else {
+            op.kind = f.k == 1 ? OP_APPLY1 : (f.k == 2 ? OP_APPLY2 : OP_APPLYK);
+            op.cls = f.k == 1 ? classify1(mm) : (f.k == 2 ? classify2(mm) : MC_DENSE);
+            if (Q && op.cls == MC_DIAG) op.cls = MC_DENSE;  // grouped kernels: dense / anti / mid
+        }
+        for (auto& x : mm) P.coef.push_back(x);
         P.tops.push_back(op);
     };
 
-    size_t q = 0;
-    while (q < order.size()) {
-        const Item& it = items[order[q]];
-        const Factor& f = F[it.f];
-        const int dim = 1 << f.k;
-        if (it.dot && !it.xbits && f.zrot) {
-            // group of Z-parity generators with one (param, coef)
-            std::vector<uint64_t> z;
-            size_t e = q;
-            while (e < order.size() && z.size() < 64) {
-                const Item& jt = items[order[e]];
-                const Factor& g = F[jt.f];
-                if (!(jt.dot && !jt.xbits && g.zrot && g.param == f.param && g.coef == f.coef)) break;
-                uint64_t zm = 0;
-                for (int i = 0; i < g.k; ++i) zm |= wire_bit(n, g.tw[i]);
-                z.push_back(zm);
+    st.generic = !grouped;
+    if (!grouped) {
+        int dummy = 0;
+        for (const Proto& pr : protos) emit(pr, nullptr, dummy);
+    } else {
+        // greedy groups: consecutive protos whose mixed bits fit in GB bits
+        size_t i = 0;
+        while (i < protos.size()) {
+            const Proto& p0 = protos[i];
+            if ((p0.kind == Proto::APPLY || p0.kind == Proto::DOT) && p0.k > 2) {
+                st.generic = true;
+                int dummy = 0;
+                emit(p0, nullptr, dummy);  // standalone k-qubit matrix
+                ++i;
+                continue;
+            }
+            uint32_t qmask = 0;
+            int ndots = 0;
+            size_t e = i;
+            while (e < protos.size()) {
+                const Proto& pr = protos[e];
+                if ((pr.kind == Proto::APPLY || pr.kind == Proto::DOT) && pr.k > 2) break;
+                const uint32_t nq = qmask | pr.tbits;
+                if (__builtin_popcount(nq) > GB) break;
+                if (pr.is_dot() && ndots == GROUP_MAX_DOTS) break;
+                qmask = nq;
+                ndots += pr.is_dot();
                 ++e;
             }
-            P.slot_param.push_back({f.param, f.coef});
-            emit_zgroup(OP_DOTZSUM, z, 0.0, nslots++);
-            q = e;
-            continue;
-        }
-        if (!it.dot && !it.xbits && f.zrot) {
-            const double ang = dagger ? -f.zangle : f.zangle;
-            std::vector<uint64_t> z;
-            size_t e = q;
-            while (e < order.size() && z.size() < 64) {
-                const Item& jt = items[order[e]];
-                const Factor& g = F[jt.f];
-                if (!(!jt.dot && !jt.xbits && g.zrot && (dagger ? -g.zangle : g.zangle) == ang)) break;
-                uint64_t zm = 0;
-                for (int i = 0; i < g.k; ++i) zm |= wire_bit(n, g.tw[i]);
-                z.push_back(zm);
-                ++e;
+            // pad Q with the highest free tile bits (keeps lanes on low bits)
+            for (int j = b - 1; __builtin_popcount(qmask) < GB && j >= 0; --j) qmask |= 1u << j;
+            std::vector<int> Q;
+            for (int j = 0; j < b; ++j)
+                if ((qmask >> j) & 1) Q.push_back(j);
+            TOp gop;
+            std::memset(&gop, 0, sizeof gop);
+            gop.kind = OP_GROUP;
+            gop.k = GB;
+            for (int t = 0; t < GB; ++t) gop.tb[t] = Q[t];
+            gop.m = (int)(e - i);
+            gop.slot = -1;
+            gop.woff = (int64_t)P.words.size();
+            for (int el = 0; el < (1 << GB); ++el) {
+                uint64_t off = 0;
+                for (int t = 0; t < GB; ++t)
+                    if ((el >> t) & 1) off |= 1ull << sb[Q[t]];
+                P.words.push_back(off);
             }
-            emit_zgroup(OP_ZPHASE, z, ang, -1);
-            q = e;
-            continue;
+            for (int j = 0; j < b; ++j)
+                if (!((qmask >> j) & 1)) P.words.push_back((uint64_t)sb[j]);
+            P.tops.push_back(gop);
+            int dslot = 0;
+            for (size_t x = i; x < e; ++x) emit(protos[x], &Q, dslot);
+            i = e;
         }
-        TOp op;
-        std::memset(&op, 0, sizeof op);
-        op.k = f.k;
-        op.slot = -1;
-        op.coff = (int64_t)P.coef.size();
-        if (!it.xbits) {
-            // diagonal on global bits (targets and controls anywhere)
-            if (f.k > 6) fail(QSV_ERR_UNSUPPORTED, "diagonal factor wider than 6 targets");
-            op.kind = it.dot ? OP_DOTDIAG : OP_DIAG;
-            for (int i = 0; i < f.k; ++i) op.tb[i] = n - 1 - f.tw[i];
-            controls(f, op, false);
-            const std::vector<cd>& src = it.dot ? f.g : f.m;
-            for (int j = 0; j < dim; ++j) {
-                const cd d = src[(size_t)j * dim + j];
-                P.coef.push_back((!it.dot && dagger) ? std::conj(d) : d);
-            }
-        } else {
-            if (f.k > 6) fail(QSV_ERR_UNSUPPORTED, "factor wider than 6 targets");
-            for (int i = 0; i < f.k; ++i) op.tb[i] = rank[n - 1 - f.tw[i]];
-            controls(f, op, true);
-            const std::vector<cd> mm = it.dot ? f.g : maybe_dag(f.m, dim, dagger);
-            if (it.dot) {
-                op.kind = f.k == 1 ? OP_DOT1 : (f.k == 2 ? OP_DOT2 : OP_DOTK);
-            } else {
-                op.kind = f.k == 1 ? OP_APPLY1 : (f.k == 2 ? OP_APPLY2 : OP_APPLYK);
-                op.cls = f.k == 1 ? classify1(mm) : (f.k == 2 ? classify2(mm) : MC_DENSE);
-            }
-            for (auto& x : mm) P.coef.push_back(x);
-        }
-        if (it.dot) {
-            op.slot = nslots++;
-            P.slot_param.push_back({f.param, f.coef});
-        }
-        P.tops.push_back(op);
-        ++q;
     }
     a.nops = (int)P.tops.size() - a.op0;
     a.nslots = nslots;
@@ -604,10 +721,10 @@ void run_program(qsv_ctx* c, const Program& P, qsv_dtype dt, int n, void* phi, v
     for (const Step& st : P.steps) {
         if (st.type == Step::TILE) {
             Timed t(c, lam ? KK_TILE2 : KK_TILE1, st.bytes);
-            hipError_t e = c128 ? launch_tile<double>(c->stream, lam != nullptr, phi, lam, st.ta, (const TOp*)c->ops.p,
+            hipError_t e = c128 ? launch_tile<double>(c->stream, lam != nullptr, st.generic, phi, lam, st.ta, (const TOp*)c->ops.p,
                                                       c->coef.p, (const uint64_t*)c->words.p, (double*)c->partials.p,
                                                       st.grid, st.nthr, st.R, st.lds)
-                                : launch_tile<float>(c->stream, lam != nullptr, phi, lam, st.ta, (const TOp*)c->ops.p,
+                                : launch_tile<float>(c->stream, lam != nullptr, st.generic, phi, lam, st.ta, (const TOp*)c->ops.p,
                                                      c->coef.p, (const uint64_t*)c->words.p, (double*)c->partials.p,
                                                      st.grid, st.nthr, st.R, st.lds);
             t.done(e);

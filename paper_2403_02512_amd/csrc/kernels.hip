@@ -307,7 +307,7 @@ struct TileCtx {
     const uint64_t* words;
     uint64_t base, offlo;
     const uint64_t* offhi;
-    int tid, nthr;
+    int tid, nthr, nwaves;
 };
 
 template <typename T, bool TWO, int R>
@@ -517,11 +517,305 @@ __device__ __forceinline__ void tile_dot(const TileCtx<T, TWO, R>& c, const TOp&
                 acc += (double)(op.m - 2 * cnt) * im_conj_mul(c.tl[t], c.tp[t]);
             }
         }
-        block_add(acc, c.red, c.sacc + op.slot, c.tid, c.nthr);
+        block_add(acc, c.red, c.sacc + op.slot * c.nwaves, c.tid, c.nthr);
     }
 }
 
-template <typename T, bool TWO, int LR>
+
+// ------------------------------------------------------------------ register subcube groups
+//
+// A GROUP op names GB tile bits Q.  The tile splits into 2^(b-GB) subcubes
+// of 2^GB elements that agree on the other tile bits; each thread loads whole
+// subcubes from LDS into registers, runs every sub-op of the group on them
+// (1- and 2-qubit matrices on bits of Q, diagonal phases on any global bits,
+// adjoint inner products), and writes them back once: one LDS round trip per
+// group instead of one per gate.  Element e of a subcube is tile index
+// tc | eo[e], eo[e] = sum of bit i of e shifted to Q[i].
+
+template <typename T, bool TWO, int GB, int P, int CLS>
+__device__ __forceinline__ void g_apply1(cx<T>* a, cx<T>* l, const cx<T>* m, uint32_t tc, const uint32_t* eo,
+                                         uint32_t lcm, uint32_t lcv) {
+    const cx<T> m0 = m[0], m1 = m[1], m2 = m[2], m3 = m[3];
+#pragma unroll
+    for (int e0 = 0; e0 < (1 << GB); ++e0) {
+        if (e0 & (1 << P)) continue;
+        const int e1 = e0 | (1 << P);
+        if (((tc | eo[e0]) & lcm) != lcv) continue;
+#pragma unroll
+        for (int v = 0; v < (TWO ? 2 : 1); ++v) {
+            cx<T>* x = v ? l : a;
+            const cx<T> x0 = x[e0], x1 = x[e1];
+            if (CLS == MC_ANTI) {
+                x[e0] = cmul(m1, x1);
+                x[e1] = cmul(m2, x0);
+            } else {
+                x[e0] = cmad(m0, x0, cmul(m1, x1));
+                x[e1] = cmad(m2, x0, cmul(m3, x1));
+            }
+        }
+    }
+}
+
+template <typename T, bool TWO, int GB, int P0, int P1, int CLS>
+__device__ __forceinline__ void g_apply2(cx<T>* a, cx<T>* l, const cx<T>* m, uint32_t tc, const uint32_t* eo,
+                                         uint32_t lcm, uint32_t lcv) {
+#pragma unroll
+    for (int e = 0; e < (1 << GB); ++e) {
+        if (e & ((1 << P0) | (1 << P1))) continue;
+        if (((tc | eo[e]) & lcm) != lcv) continue;
+        const int id[4] = {e, e | (1 << P1), e | (1 << P0), e | (1 << P0) | (1 << P1)};
+#pragma unroll
+        for (int v = 0; v < (TWO ? 2 : 1); ++v) {
+            cx<T>* x = v ? l : a;
+            if (CLS == MC_MID) {
+                const cx<T> x1 = x[id[1]], x2 = x[id[2]];
+                x[id[1]] = cmad(m[5], x1, cmul(m[6], x2));
+                x[id[2]] = cmad(m[9], x1, cmul(m[10], x2));
+            } else {
+                const cx<T> y[4] = {x[id[0]], x[id[1]], x[id[2]], x[id[3]]};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    cx<T> acc = cmul(m[r * 4], y[0]);
+#pragma unroll
+                    for (int j = 1; j < 4; ++j) acc = cmad(m[r * 4 + j], y[j], acc);
+                    x[id[r]] = acc;
+                }
+            }
+        }
+    }
+}
+
+template <typename T, int GB, int P>
+__device__ __forceinline__ double g_dot1(const cx<T>* a, const cx<T>* l, const cx<T>* G, uint32_t tc,
+                                         const uint32_t* eo, uint32_t lcm, uint32_t lcv) {
+    const cx<T> g0 = G[0], g1 = G[1], g2 = G[2], g3 = G[3];
+    double acc = 0.0;
+#pragma unroll
+    for (int e0 = 0; e0 < (1 << GB); ++e0) {
+        if (e0 & (1 << P)) continue;
+        const int e1 = e0 | (1 << P);
+        if (((tc | eo[e0]) & lcm) != lcv) continue;
+        acc += im_conj_mul(l[e0], cmad(g0, a[e0], cmul(g1, a[e1])));
+        acc += im_conj_mul(l[e1], cmad(g2, a[e0], cmul(g3, a[e1])));
+    }
+    return acc;
+}
+
+template <typename T, int GB, int P0, int P1>
+__device__ __forceinline__ double g_dot2(const cx<T>* a, const cx<T>* l, const cx<T>* G, uint32_t tc,
+                                         const uint32_t* eo, uint32_t lcm, uint32_t lcv) {
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < (1 << GB); ++e) {
+        if (e & ((1 << P0) | (1 << P1))) continue;
+        if (((tc | eo[e]) & lcm) != lcv) continue;
+        const int id[4] = {e, e | (1 << P1), e | (1 << P0), e | (1 << P0) | (1 << P1)};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            cx<T> v = cmul(G[r * 4], a[id[0]]);
+#pragma unroll
+            for (int j = 1; j < 4; ++j) v = cmad(G[r * 4 + j], a[id[j]], v);
+            acc += im_conj_mul(l[id[r]], v);
+        }
+    }
+    return acc;
+}
+
+#define QSV_P1_CASES(F)                                  \
+    switch (p0) {                                        \
+    case 0: F(0); break;                                 \
+    case 1: if constexpr (GB > 1) { F(1); } break;       \
+    case 2: if constexpr (GB > 2) { F(2); } break;       \
+    case 3: if constexpr (GB > 3) { F(3); } break;       \
+    default: break;                                      \
+    }
+#define QSV_P2_CASE(A, B, F) \
+    case A * 4 + B: if constexpr (GB > A && GB > B) { F(A, B); } break;
+#define QSV_P2_CASES(F)                                                                          \
+    switch (p0 * 4 + p1) {                                                                       \
+    QSV_P2_CASE(0, 1, F) QSV_P2_CASE(0, 2, F) QSV_P2_CASE(0, 3, F) QSV_P2_CASE(1, 0, F)          \
+    QSV_P2_CASE(1, 2, F) QSV_P2_CASE(1, 3, F) QSV_P2_CASE(2, 0, F) QSV_P2_CASE(2, 1, F)          \
+    QSV_P2_CASE(2, 3, F) QSV_P2_CASE(3, 0, F) QSV_P2_CASE(3, 1, F) QSV_P2_CASE(3, 2, F)          \
+    default: break;                                                                              \
+    }
+
+// register accumulators of the group's inner products, selected by a runtime
+// index through a switch so they stay in registers
+struct DotAcc {
+    double v[GROUP_MAX_DOTS];
+    __device__ __forceinline__ void add(int i, double x) {
+        switch (i) {
+        case 0: v[0] += x; break;
+        case 1: v[1] += x; break;
+        case 2: v[2] += x; break;
+        case 3: v[3] += x; break;
+        case 4: v[4] += x; break;
+        case 5: v[5] += x; break;
+        case 6: v[6] += x; break;
+        default: v[7] += x; break;
+        }
+    }
+    __device__ __forceinline__ double get(int i) const {
+        switch (i) {
+        case 0: return v[0];
+        case 1: return v[1];
+        case 2: return v[2];
+        case 3: return v[3];
+        case 4: return v[4];
+        case 5: return v[5];
+        case 6: return v[6];
+        default: return v[7];
+        }
+    }
+};
+
+template <typename T, bool TWO, int R, int GB>
+__device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TOp& g, const TOp* __restrict__ subs,
+                                           int b) {
+    constexpr int E = 1 << GB;
+    const int nsub = (c.nthr * R) >> GB;
+    const uint64_t* w = c.words + g.woff;
+    uint32_t eo[E];
+    uint64_t geo[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int i = 0; i < GB; ++i)
+            if ((e >> i) & 1) o |= 1u << g.tb[i];
+        eo[e] = o;
+        geo[e] = w[e];
+    }
+    DotAcc acc;
+#pragma unroll
+    for (int d = 0; d < GROUP_MAX_DOTS; ++d) acc.v[d] = 0.0;
+    const int nq = b - GB;
+    for (int sc = c.tid; sc < nsub; sc += c.nthr) {
+        uint32_t tc = (uint32_t)sc;
+#pragma unroll
+        for (int i = 0; i < GB; ++i) {  // Q ascending: insert a zero at each Q bit
+            const uint32_t q = (uint32_t)g.tb[i];
+            tc = ((tc >> q) << (q + 1)) | (tc & ((1u << q) - 1));
+        }
+        uint64_t gc = c.base;
+        for (int j = 0; j < nq; ++j)
+            if ((sc >> j) & 1) gc |= 1ull << w[E + j];
+        cx<T> a[E], l[TWO ? E : 1];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            a[e] = c.tp[tc | eo[e]];
+            if (TWO) l[e] = c.tl[tc | eo[e]];
+        }
+        for (int si = 0; si < g.m; ++si) {
+            const TOp& s = subs[si];
+            const bool local = s.kind == OP_APPLY1 || s.kind == OP_APPLY2 || s.kind == OP_DOT1 || s.kind == OP_DOT2;
+            if (local && (c.base & s.gcmask) != s.gcval) continue;
+            const cx<T>* m = c.coef + s.coff;
+            const int p0 = s.tb[0], p1 = s.tb[1];
+            switch (s.kind) {
+            case OP_APPLY1:
+                if (s.cls == MC_ANTI) {
+#define F(P) g_apply1<T, TWO, GB, P, MC_ANTI>(a, l, m, tc, eo, s.lcmask, s.lcval)
+                    QSV_P1_CASES(F)
+#undef F
+                } else {
+#define F(P) g_apply1<T, TWO, GB, P, MC_DENSE>(a, l, m, tc, eo, s.lcmask, s.lcval)
+                    QSV_P1_CASES(F)
+#undef F
+                }
+                break;
+            case OP_APPLY2:
+                if (s.cls == MC_MID) {
+#define F(A, B) g_apply2<T, TWO, GB, A, B, MC_MID>(a, l, m, tc, eo, s.lcmask, s.lcval)
+                    QSV_P2_CASES(F)
+#undef F
+                } else {
+#define F(A, B) g_apply2<T, TWO, GB, A, B, MC_DENSE>(a, l, m, tc, eo, s.lcmask, s.lcval)
+                    QSV_P2_CASES(F)
+#undef F
+                }
+                break;
+            case OP_DIAG:
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const uint64_t gi = gc | geo[e];
+                    if ((gi & s.gcmask) != s.gcval) continue;
+                    int j = 0;
+                    for (int i = 0; i < s.k; ++i) j = (j << 1) | (int)((gi >> s.tb[i]) & 1);
+                    const cx<T> d = m[j];
+                    a[e] = cmul(d, a[e]);
+                    if (TWO) l[e] = cmul(d, l[e]);
+                }
+                break;
+            case OP_ZPHASE: {
+                const uint64_t* z = c.words + s.woff;
+                const uint64_t pc = parity_bits(c.base, z, s.m) ^ z[s.m + sc];
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const cx<T> d = m[__popcll(pc ^ z[s.m + nsub + e])];
+                    a[e] = cmul(d, a[e]);
+                    if (TWO) l[e] = cmul(d, l[e]);
+                }
+            } break;
+            default:
+                if constexpr (TWO) {
+                    double v = 0.0;
+                    if (s.kind == OP_DOT1) {
+#define F(P) v = g_dot1<T, GB, P>(a, l, m, tc, eo, s.lcmask, s.lcval)
+                        QSV_P1_CASES(F)
+#undef F
+                    } else if (s.kind == OP_DOT2) {
+#define F(A, B) v = g_dot2<T, GB, A, B>(a, l, m, tc, eo, s.lcmask, s.lcval)
+                        QSV_P2_CASES(F)
+#undef F
+                    } else if (s.kind == OP_DOTDIAG) {
+#pragma unroll
+                        for (int e = 0; e < E; ++e) {
+                            const uint64_t gi = gc | geo[e];
+                            if ((gi & s.gcmask) != s.gcval) continue;
+                            int j = 0;
+                            for (int i = 0; i < s.k; ++i) j = (j << 1) | (int)((gi >> s.tb[i]) & 1);
+                            v += im_conj_mul(l[e], cmul(m[j], a[e]));
+                        }
+                    } else {  // OP_DOTZSUM
+                        const uint64_t* z = c.words + s.woff;
+                        const uint64_t pc = parity_bits(c.base, z, s.m) ^ z[s.m + sc];
+#pragma unroll
+                        for (int e = 0; e < E; ++e)
+                            v += (double)(s.m - 2 * __popcll(pc ^ z[s.m + nsub + e])) * im_conj_mul(l[e], a[e]);
+                    }
+                    acc.add(s.aux, v);
+                }
+                break;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            c.tp[tc | eo[e]] = a[e];
+            if (TWO) c.tl[tc | eo[e]] = l[e];
+        }
+    }
+    if constexpr (TWO) {
+        // flush: per-wave sums into the wave's accumulator (no barrier when
+        // the block is made of whole waves)
+        for (int si = 0; si < g.m; ++si) {
+            const TOp& s = subs[si];
+            if (s.kind < OP_DOT1 || s.kind == OP_DOTK || s.kind > OP_DOTZSUM) continue;
+            const double v = acc.get(s.aux);
+            if (c.nthr >= 64) {
+                const double tot = wave_sum(v);
+                if ((c.tid & 63) == 0) c.sacc[s.slot * c.nwaves + (c.tid >> 6)] += tot;
+            } else {
+                block_add(v, c.red, c.sacc + s.slot * c.nwaves, c.tid, c.nthr);
+            }
+        }
+    }
+}
+
+// GEN: the pass also holds standalone ops (k-qubit matrices, or a tile too
+// small for groups); group-only passes compile without those code paths,
+// which keeps their register footprint (and so their occupancy) lower.
+template <typename T, bool TWO, int LR, bool GEN>
 __global__ __launch_bounds__(256) void k_tile(cx<T>* __restrict__ phi, cx<T>* __restrict__ lam, const TileArgs a,
                                               const TOp* __restrict__ ops, const cx<T>* __restrict__ coef,
                                               const uint64_t* __restrict__ words, double* __restrict__ partials) {
@@ -540,10 +834,11 @@ __global__ __launch_bounds__(256) void k_tile(cx<T>* __restrict__ phi, cx<T>* __
     c.offhi = a.offhi;
     c.tid = tid;
     c.nthr = nthr;
+    c.nwaves = nthr >= 64 ? nthr >> 6 : 1;
     uint64_t offlo = 0;
     for (int j = 0; j < a.nthr_log2; ++j) offlo |= (uint64_t)((tid >> j) & 1) << a.sb[j];
     c.offlo = offlo;
-    for (int s = tid; s < a.nslots; s += nthr) c.sacc[s] = 0.0;
+    for (int s = tid; s < a.nslots * c.nwaves; s += nthr) c.sacc[s] = 0.0;
 
     for (uint64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
         const uint64_t base = expand_idx(tile, a.outer);
@@ -560,13 +855,21 @@ __global__ __launch_bounds__(256) void k_tile(cx<T>* __restrict__ phi, cx<T>* __
             if ((op.kind <= OP_APPLYK || (op.kind >= OP_DOT1 && op.kind <= OP_DOTK)) &&
                 (base & op.gcmask) != op.gcval)
                 continue;  // outer controls fail for this whole tile (uniform)
-            switch (op.kind) {
-            case OP_APPLY1: tile_apply1(c, op); break;
-            case OP_APPLY2: tile_apply2(c, op); break;
-            case OP_APPLYK: tile_applyk(c, op); break;
-            case OP_DIAG: tile_diag(c, op); break;
-            case OP_ZPHASE: tile_zphase(c, op); break;
-            default: tile_dot(c, op); break;
+            if (op.kind == OP_GROUP) {
+                tile_group<T, TWO, R, TWO ? GROUP_BITS_TWO : GROUP_BITS_ONE>(c, op, ops + a.op0 + oi + 1, a.b);
+                oi += op.m;
+                __syncthreads();
+                continue;
+            }
+            if constexpr (GEN) {
+                switch (op.kind) {
+                case OP_APPLY1: tile_apply1(c, op); break;
+                case OP_APPLY2: tile_apply2(c, op); break;
+                case OP_APPLYK: tile_applyk(c, op); break;
+                case OP_DIAG: tile_diag(c, op); break;
+                case OP_ZPHASE: tile_zphase(c, op); break;
+                default: tile_dot(c, op); break;
+                }
             }
             __syncthreads();
         }
@@ -578,50 +881,64 @@ __global__ __launch_bounds__(256) void k_tile(cx<T>* __restrict__ phi, cx<T>* __
         }
         __syncthreads();
     }
-    for (int s = tid; s < a.nslots; s += nthr) partials[(uint64_t)s * gridDim.x + blockIdx.x] = c.sacc[s];
+    __syncthreads();
+    for (int s = tid; s < a.nslots; s += nthr) {
+        double v = 0.0;
+        for (int w = 0; w < c.nwaves; ++w) v += c.sacc[s * c.nwaves + w];
+        partials[(uint64_t)s * gridDim.x + blockIdx.x] = v;
+    }
 }
 
 int tile_lds_bytes(int b, bool two, int elem_bytes, int nslots) {
-    return (two ? 2 : 1) * (1 << b) * elem_bytes + 64 * 8 + nslots * 8;
+    const int nthr = 1 << (b < 8 ? b : 8);
+    const int nwaves = nthr >= 64 ? nthr / 64 : 1;
+    return (two ? 2 : 1) * (1 << b) * elem_bytes + 64 * 8 + nslots * nwaves * 8;
 }
 
-template <typename T, bool TWO, int LR>
+template <typename T, bool TWO, int LR, bool GEN>
 static hipError_t launch_tile_lr(hipStream_t s, void* phi, void* lam, const TileArgs& a, const TOp* ops,
                                  const void* coef, const uint64_t* words, double* partials, int grid, int nthr,
                                  size_t lds) {
     static bool attr_set = false;
     if (lds > 65536 && !attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_tile<T, TWO, LR>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_tile<T, TWO, LR, GEN>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_tile<T, TWO, LR>), dim3(grid), dim3(nthr), lds, s, (cx<T>*)phi, (cx<T>*)lam, a, ops,
+    hipLaunchKernelGGL((k_tile<T, TWO, LR, GEN>), dim3(grid), dim3(nthr), lds, s, (cx<T>*)phi, (cx<T>*)lam, a, ops,
                        (const cx<T>*)coef, words, partials);
     return hipGetLastError();
 }
 
-template <typename T, bool TWO>
+template <typename T, bool TWO, bool GEN>
 static hipError_t launch_tile_two(hipStream_t s, void* phi, void* lam, const TileArgs& a, const TOp* ops,
                                   const void* coef, const uint64_t* words, double* partials, int grid, int nthr,
                                   int R, size_t lds) {
     switch (R) {
-    case 1: return launch_tile_lr<T, TWO, 0>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
-    case 2: return launch_tile_lr<T, TWO, 1>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
-    case 4: return launch_tile_lr<T, TWO, 2>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
-    case 8: return launch_tile_lr<T, TWO, 3>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
-    case 16: return launch_tile_lr<T, TWO, 4>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
-    case 32: return launch_tile_lr<T, TWO, 5>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
+    case 1: return launch_tile_lr<T, TWO, 0, GEN>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
+    case 2: return launch_tile_lr<T, TWO, 1, GEN>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
+    case 4: return launch_tile_lr<T, TWO, 2, GEN>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
+    case 8: return launch_tile_lr<T, TWO, 3, GEN>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
+    case 16: return launch_tile_lr<T, TWO, 4, GEN>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
+    case 32: return launch_tile_lr<T, TWO, 5, GEN>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T>
-hipError_t launch_tile(hipStream_t s, bool two, void* phi, void* lam, const TileArgs& a, const TOp* ops,
-                       const void* coef, const uint64_t* words, double* partials, int grid, int nthr, int R,
-                       size_t lds_bytes) {
-    if (two) return launch_tile_two<T, true>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, R, lds_bytes);
-    return launch_tile_two<T, false>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, R, lds_bytes);
+hipError_t launch_tile(hipStream_t s, bool two, bool generic, void* phi, void* lam, const TileArgs& a,
+                       const TOp* ops, const void* coef, const uint64_t* words, double* partials, int grid, int nthr,
+                       int R, size_t lds_bytes) {
+    if (two) {
+        if (generic)
+            return launch_tile_two<T, true, true>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, R,
+                                                  lds_bytes);
+        return launch_tile_two<T, true, false>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, R, lds_bytes);
+    }
+    if (generic)
+        return launch_tile_two<T, false, true>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, R, lds_bytes);
+    return launch_tile_two<T, false, false>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, R, lds_bytes);
 }
 
 // ------------------------------------------------------------------ Pauli sums
@@ -710,7 +1027,7 @@ hipError_t launch_reduce(hipStream_t s, const double* partials, int n_blocks, in
                                         uint64_t, int, const Mat4&);                                            \
     template hipError_t launch_gatek<T>(hipStream_t, void*, uint64_t, const Expand&, uint64_t, int,             \
                                         const int32_t*, const void*);                                           \
-    template hipError_t launch_tile<T>(hipStream_t, bool, void*, void*, const TileArgs&, const TOp*,            \
+    template hipError_t launch_tile<T>(hipStream_t, bool, bool, void*, void*, const TileArgs&, const TOp*,      \
                                        const void*, const uint64_t*, double*, int, int, int, size_t);           \
     template hipError_t launch_pauli<T>(hipStream_t, bool, const void*, void*, uint64_t, const PauliGroupDev*,  \
                                         int, const PauliTermDev*, double*, int);

@@ -71,8 +71,12 @@ std::vector<Pass> plan_passes(const std::vector<Item>& items, int n, const PlanO
                 bool ok = !(it.xbits & (bx | bz)) && !(it.zbits & bx);
                 if (ok && it.xbits) {
                     const uint64_t ns = p.S | it.xbits;
-                    if (__builtin_popcountll(ns) <= b) p.S = ns;
-                    else ok = false;
+                    if (__builtin_popcountll(ns) <= b)
+                        p.S = ns;
+                    else if (p.items.empty() && !bx && !bz && __builtin_popcountll(it.xbits) <= b)
+                        p.S = it.xbits;  // a wide first gate: its targets first, low bits as room allows
+                    else
+                        ok = false;
                 }
                 if (ok) {
                     p.items.push_back((int)j);
@@ -85,8 +89,19 @@ std::vector<Pass> plan_passes(const std::vector<Item>& items, int n, const PlanO
                 }
             }
         }
-        // pad S with the lowest free bits up to b bits: bigger contiguous runs
-        for (int bit = 0; __builtin_popcountll(p.S) < b && bit < n; ++bit) p.S |= 1ull << bit;
+        int bp = b;
+        if (p.items.empty()) {
+            // the first pending item does not fit next to the coalescing bits:
+            // give it a pass of its own whose bit set starts from its targets
+            const Item& it = items[first];
+            p.S = it.xbits;
+            bp = std::max(b, __builtin_popcountll(it.xbits));
+            p.items.push_back((int)first);
+            done[first] = 1;
+            --left;
+        }
+        // pad S with the lowest free bits up to the tile width: longer contiguous runs
+        for (int bit = 0; __builtin_popcountll(p.S) < bp && bit < n; ++bit) p.S |= 1ull << bit;
         passes.push_back(std::move(p));
     }
     return passes;

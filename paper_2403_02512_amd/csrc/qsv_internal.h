@@ -39,7 +39,8 @@ enum TOpKind : int32_t {
     OP_DOT2,
     OP_DOTK,
     OP_DOTDIAG,     // slot += Im <lam|D|phi> for diagonal D on global bits
-    OP_DOTZSUM      // slot += Im <lam| sum_j Z^{z_j} |phi>
+    OP_DOTZSUM,     // slot += Im <lam| sum_j Z^{z_j} |phi>
+    OP_GROUP        // the next m ops act inside register subcubes over the k tile bits tb[0..k-1]
 };
 
 enum MatClass : int32_t { MC_DENSE = 0, MC_DIAG = 1, MC_ANTI = 2, MC_MID = 3 };
@@ -51,9 +52,14 @@ struct TOp {
     uint64_t gcmask, gcval;  // controls on global index bits
     int64_t coff;            // complex offset into the coefficient table
     int64_t woff;            // u64 offset into the word table (ZPHASE/DOTZSUM)
-    int32_t m;               // number of parity masks (ZPHASE/DOTZSUM)
-    int32_t pad;
+    int32_t m;               // parity masks (ZPHASE/DOTZSUM); sub-op count (GROUP)
+    int32_t aux;             // register accumulator of a DOT inside a group
 };
+
+// Register subcube width of the grouped tile ops (elements per subcube = 2^GB)
+constexpr int GROUP_BITS_ONE = 4;  // one vector
+constexpr int GROUP_BITS_TWO = 3;  // phi and lambda
+constexpr int GROUP_MAX_DOTS = 8;
 
 constexpr int TILE_MAX_R_LOG2 = 5;   // at most 32 elements per thread
 constexpr int TILE_THREADS = 256;
@@ -102,7 +108,7 @@ template <typename T> hipError_t launch_gate2(hipStream_t s, void* psi, uint64_t
                                               uint64_t setmask, uint64_t b0, uint64_t b1, int cls, const Mat4& m);
 template <typename T> hipError_t launch_gatek(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex,
                                               uint64_t setmask, int k, const int32_t* tbits, const void* mat);
-template <typename T> hipError_t launch_tile(hipStream_t s, bool two, void* phi, void* lam, const TileArgs& a,
+template <typename T> hipError_t launch_tile(hipStream_t s, bool two, bool generic, void* phi, void* lam, const TileArgs& a,
                                              const TOp* ops, const void* coef, const uint64_t* words,
                                              double* partials, int grid, int nthr, int R, size_t lds_bytes);
 template <typename T> hipError_t launch_pauli(hipStream_t s, bool write_lambda, const void* psi, void* lam,

@@ -1,0 +1,81 @@
+"""Host-only checks of the pass planner through qsv_plan_stats (no GPU)."""
+import numpy as np
+import pytest
+
+from paper_2403_02512_amd import qsv
+from paper_2403_02512_amd import workloads as W
+
+
+def test_unfused_plan_is_one_pass_per_gate():
+    c = W.config3(n=20)
+    st = qsv.plan_stats(20, c.ops, c.params, fusion=False)
+    assert st["passes"] == len(c.ops) and st["tile_passes"] == 0
+    # H, RX: 2 N B each; IsingZZ: 2 N B (diagonal quads)
+    assert st["alg_bytes"] == len(c.ops) * 2 * 16 * 2 ** 20
+
+
+def test_qaoa_28q_fuses_into_few_passes():
+    c = W.config3()
+    fwd = qsv.plan_stats(28, c.ops, c.params)
+    adj = qsv.plan_stats(28, c.ops, c.params, adjoint=True)
+    assert fwd["passes"] <= 12 and fwd["tile_passes"] == fwd["passes"]
+    assert adj["passes"] <= 12
+    N = 2 ** 28
+    assert fwd["alg_bytes"] == fwd["passes"] * 2 * 16 * N
+    assert adj["alg_bytes"] == adj["passes"] * 4 * 16 * N
+
+
+def test_small_register_is_one_tile():
+    for n in (1, 3, 8, 12):
+        c = W.random_circuit(n, 60, seed=n)
+        st = qsv.plan_stats(n, c.ops, c.params)
+        assert st["passes"] == 1
+
+
+@pytest.mark.parametrize("name,k", [("RX", 1), ("IsingXX", 2), ("QubitUnitary", 3), ("QubitUnitary", 5),
+                                    ("QubitUnitary", 6)])
+def test_single_gate_uses_streaming_kernel_up_to_k5(name, k):
+    n = 20
+    rng = np.random.default_rng(0)
+    mat = W.random_unitary(k, rng) if name == "QubitUnitary" else None
+    slots = [(0, 1.0)] if name != "QubitUnitary" else []
+    o = W.op(name, list(range(n - k, n))[::-1], *slots, matrix=mat)
+    st = qsv.plan_stats(n, [o], [0.3])
+    assert st["passes"] == 1
+    assert st["tile_passes"] == (1 if k == 6 else 0)
+
+
+def test_non_commuting_gates_keep_order():
+    """Two gates on a high wire separated by a gate that mixes it cannot share
+    a pass with a third gate that needs a different tile bit set: the plan
+    needs at least two passes once the tile cannot hold all targets."""
+    n = 20
+    ops = [W.op("Hadamard", [w]) for w in range(n)]
+    st = qsv.plan_stats(n, ops, [], tile_bits=6, low_bits=2)
+    # 20 mixing bits, at most 6 per pass (2 of them low bits shared by all)
+    assert st["passes"] >= 1 + (n - 6 + 3) // 4
+
+
+def test_adjoint_plan_counts_inner_products():
+    c = W.config1()
+    st = qsv.plan_stats(10, c.ops, c.params, adjoint=True)
+    # 120 trainable slots + 160 un-applies in a single tile (plus group headers)
+    assert st["passes"] == 1 and st["kernel_ops"] >= 280
+
+
+def test_plan_stats_validates():
+    with pytest.raises(qsv.QsvError):
+        qsv.plan_stats(3, [W.op("RX", [5], (0, 1.0))], [0.1])
+
+
+@pytest.mark.timeout(60)
+def test_wide_gate_beside_coalescing_bits_terminates():
+    """A gate whose targets plus the coalescing bits exceed the tile width gets
+    a pass of its own instead of an empty pass (regression: the planner used
+    to loop forever)."""
+    n = 8
+    rng = np.random.default_rng(3)
+    ops = [W.op("QubitUnitary", [0, 1, 2, 3, 4], matrix=W.random_unitary(5, rng)), W.op("RX", [7], (0, 1.0))]
+    for adj in (False, True):
+        st = qsv.plan_stats(n, ops, [0.2], adjoint=adj, tile_bits=5, low_bits=2)
+        assert 1 <= st["passes"] <= 2
