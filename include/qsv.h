@@ -178,6 +178,14 @@ qsv_status qsv_plan_stats(int n_qubits, qsv_dtype dtype, const qsv_op *ops, size
                           int tile_bits, int low_bits, int fusion, int64_t *n_passes, int64_t *n_tile_passes,
                           int64_t *n_kernel_ops, double *alg_bytes);
 
+/* The same plan as a JSON document (host only): every pass with its kernel
+ * arguments, the lowered tile ops, the coefficient and word tables and the
+ * inner-product slot -> (parameter, coefficient) map.  Writes at most cap
+ * bytes (NUL-terminated) to out and the full size + 1 to *needed. */
+qsv_status qsv_plan_json(int n_qubits, qsv_dtype dtype, const qsv_op *ops, size_t n_ops, const double *params,
+                         size_t n_params, const double *matrices, size_t n_matrix_elems, int adjoint,
+                         int tile_bits, int low_bits, int fusion, char *out, size_t cap, size_t *needed);
+
 /* ---------------------------------------------------------------- hot path */
 /* Apply ops in order (paper Sec. 2.1.1 Alg. 1 and Alg. 2; Sec. 2.1.2 gates).
  * Asynchronous on the context stream: host arrays may be reused on return.

@@ -4,6 +4,7 @@
 // Sec. 2.1 and Sec. 3.1.1).
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -1261,6 +1262,84 @@ qsv_status qsv_validate_obs(int n, const qsv_pauli_sum* obs, size_t n_obs) {
     return guard(nullptr, [&] {
         if (n < 1 || n > QSV_MAX_QUBITS) fail(QSV_ERR_ARG, "n_qubits out of range");
         validate_obs_impl(n, obs, n_obs);
+    });
+}
+
+qsv_status qsv_plan_json(int n, qsv_dtype dt, const qsv_op* ops, size_t n_ops, const double* params,
+                         size_t n_params, const double* matrices, size_t n_mat, int adjoint, int tile_bits,
+                         int low_bits, int fusion, char* out, size_t cap, size_t* needed) {
+    return guard(nullptr, [&] {
+        validate_ops_impl(n, ops, n_ops, n_params, n_mat, params, matrices);
+        if (dt != QSV_C64 && dt != QSV_C128) fail(QSV_ERR_DTYPE, "unknown dtype");
+        if (tile_bits < 0 || tile_bits > 8 + TILE_MAX_R_LOG2 || low_bits < 0 || low_bits > 8)
+            fail(QSV_ERR_ARG, "tile options out of range");
+        const bool two = adjoint != 0;
+        std::vector<Factor> F = forward_factors(ops, n_ops, params, matrices, two);
+        std::vector<Item> items = two ? adjoint_items(F, n) : forward_items(F, n);
+        Program P = build_program(plan_opts(tile_bits, low_bits, fusion, dt, two), F, items, n, dt, two, two);
+        std::string js;
+        char buf[512];
+        auto add = [&](const char* fmt, auto... a) {
+            std::snprintf(buf, sizeof buf, fmt, a...);
+            js += buf;
+        };
+        js += "{\"steps\":[";
+        for (size_t i = 0; i < P.steps.size(); ++i) {
+            const Step& st = P.steps[i];
+            if (i) js += ",";
+            static const char* names[] = {"tile", "gate1", "diag1", "gate2", "gatek"};
+            add("{\"type\":\"%s\",\"bytes\":%.17g", names[st.type], st.bytes);
+            if (st.type == Step::TILE) {
+                const TileArgs& a = st.ta;
+                add(",\"b\":%d,\"nthr\":%d,\"R\":%d,\"grid\":%d,\"op0\":%d,\"nops\":%d,\"nslots\":%d,\"slot_base\":%d,"
+                    "\"generic\":%d,\"n_tiles\":%llu,\"sb\":[",
+                    a.b, st.nthr, st.R, st.grid, a.op0, a.nops, a.nslots, st.slot_base, (int)st.generic,
+                    (unsigned long long)a.n_tiles);
+                for (int j = 0; j < a.b; ++j) add(j ? ",%d" : "%d", a.sb[j]);
+                js += "],\"offhi\":[";
+                for (int r = 0; r < st.R; ++r) add(r ? ",%llu" : "%llu", (unsigned long long)a.offhi[r]);
+                js += "],\"outer\":[";
+                for (int j = 0; j < a.outer.nm; ++j) add(j ? ",%llu" : "%llu", (unsigned long long)a.outer.m[j]);
+                js += "]";
+            } else {
+                add(",\"n_items\":%llu,\"setmask\":%llu,\"tbit\":%llu,\"b0\":%llu,\"b1\":%llu,\"cls\":%d,\"k\":%d,"
+                    "\"coff\":%lld,\"dre\":%.17g,\"dim\":%.17g,\"tb\":[%d,%d,%d,%d,%d,%d],\"ex\":[",
+                    (unsigned long long)st.n_items, (unsigned long long)st.setmask, (unsigned long long)st.tbit,
+                    (unsigned long long)st.b0, (unsigned long long)st.b1, st.cls, st.k, (long long)st.coff, st.dre,
+                    st.dim, st.tb[0], st.tb[1], st.tb[2], st.tb[3], st.tb[4], st.tb[5]);
+                for (int j = 0; j < st.ex.nm; ++j) add(j ? ",%llu" : "%llu", (unsigned long long)st.ex.m[j]);
+                js += "],\"m2\":[";
+                for (int j = 0; j < 4; ++j) add(j ? ",%.17g,%.17g" : "%.17g,%.17g", st.m2.re[j], st.m2.im[j]);
+                js += "],\"m4\":[";
+                for (int j = 0; j < 16; ++j) add(j ? ",%.17g,%.17g" : "%.17g,%.17g", st.m4.re[j], st.m4.im[j]);
+                js += "]";
+            }
+            js += "}";
+        }
+        js += "],\"tops\":[";
+        for (size_t i = 0; i < P.tops.size(); ++i) {
+            const TOp& o = P.tops[i];
+            add("%s{\"kind\":%d,\"cls\":%d,\"k\":%d,\"slot\":%d,\"tb\":[%d,%d,%d,%d,%d,%d],\"lcmask\":%u,\"lcval\":%u,"
+                "\"gcmask\":%llu,\"gcval\":%llu,\"coff\":%lld,\"woff\":%lld,\"m\":%d,\"aux\":%d}",
+                i ? "," : "", o.kind, o.cls, o.k, o.slot, o.tb[0], o.tb[1], o.tb[2], o.tb[3], o.tb[4], o.tb[5],
+                o.lcmask, o.lcval, (unsigned long long)o.gcmask, (unsigned long long)o.gcval, (long long)o.coff,
+                (long long)o.woff, o.m, o.aux);
+        }
+        js += "],\"coef\":[";
+        for (size_t i = 0; i < P.coef.size(); ++i)
+            add(i ? ",%.17g,%.17g" : "%.17g,%.17g", P.coef[i].real(), P.coef[i].imag());
+        js += "],\"words\":[";
+        for (size_t i = 0; i < P.words.size(); ++i) add(i ? ",%llu" : "%llu", (unsigned long long)P.words[i]);
+        js += "],\"slot_param\":[";
+        for (size_t i = 0; i < P.slot_param.size(); ++i)
+            add(i ? ",[%d,%.17g]" : "[%d,%.17g]", P.slot_param[i].first, P.slot_param[i].second);
+        js += "]}";
+        if (needed) *needed = js.size() + 1;
+        if (out && cap) {
+            const size_t k = std::min(cap - 1, js.size());
+            std::memcpy(out, js.data(), k);
+            out[k] = 0;
+        }
     });
 }
 

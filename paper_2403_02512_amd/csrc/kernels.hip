@@ -457,7 +457,7 @@ __device__ __forceinline__ void tile_zphase(const TileCtx<T, TWO, R>& c, const T
     const uint64_t* ph = w + op.m + c.nthr;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int cnt = __popcll(pl ^ ph[r]);
+        const int cnt = (int)__popcll(pl ^ ph[r]);
         const cx<T> d = c.coef[op.coff + cnt];
         const int t = c.tid + r * c.nthr;
         c.tp[t] = cmul(d, c.tp[t]);
@@ -512,7 +512,7 @@ __device__ __forceinline__ void tile_dot(const TileCtx<T, TWO, R>& c, const TOp&
             const uint64_t* ph = w + op.m + c.nthr;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const int cnt = __popcll(pl ^ ph[r]);
+                const int cnt = (int)__popcll(pl ^ ph[r]);
                 const int t = c.tid + r * c.nthr;
                 acc += (double)(op.m - 2 * cnt) * im_conj_mul(c.tl[t], c.tp[t]);
             }
@@ -752,7 +752,7 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
                 const uint64_t pc = parity_bits(c.base, z, s.m) ^ z[s.m + sc];
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
-                    const cx<T> d = m[__popcll(pc ^ z[s.m + nsub + e])];
+                    const cx<T> d = m[(int)__popcll(pc ^ z[s.m + nsub + e])];
                     a[e] = cmul(d, a[e]);
                     if (TWO) l[e] = cmul(d, l[e]);
                 }
@@ -782,7 +782,7 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
                         const uint64_t pc = parity_bits(c.base, z, s.m) ^ z[s.m + sc];
 #pragma unroll
                         for (int e = 0; e < E; ++e)
-                            v += (double)(s.m - 2 * __popcll(pc ^ z[s.m + nsub + e])) * im_conj_mul(l[e], a[e]);
+                            v += (double)(s.m - 2 * (int)__popcll(pc ^ z[s.m + nsub + e])) * im_conj_mul(l[e], a[e]);
                     }
                     acc.add(s.aux, v);
                 }

@@ -8,8 +8,11 @@ fallback: without the built library or a GPU the calls fail loudly.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -53,6 +56,20 @@ class QsvPauliSum(ctypes.Structure):
 
 
 _lib = None
+_live = weakref.WeakSet()   # contexts and states still open, released before interpreter exit
+
+
+def _close_all():
+    objs = list(_live)
+    for o in objs:              # states first: they belong to contexts
+        if isinstance(o, State):
+            o.close()
+    for o in objs:
+        if isinstance(o, Context):
+            o.close()
+
+
+atexit.register(_close_all)
 
 EXPORTS = [
     "qsv_version", "qsv_status_string", "qsv_thread_last_error", "qsv_device_count", "qsv_ctx_create",
@@ -61,7 +78,7 @@ EXPORTS = [
     "qsv_kernel_name", "qsv_ctx_kernel_stats", "qsv_ctx_reset_stats", "qsv_state_create", "qsv_state_wrap",
     "qsv_state_destroy", "qsv_state_n_qubits", "qsv_state_device_ptr", "qsv_state_reset", "qsv_state_copy",
     "qsv_state_to_host", "qsv_state_from_host", "qsv_validate_ops", "qsv_validate_obs", "qsv_apply",
-    "qsv_expval", "qsv_adjoint_jacobian", "qsv_adjoint_vjp", "qsv_plan_stats",
+    "qsv_expval", "qsv_adjoint_jacobian", "qsv_adjoint_vjp", "qsv_plan_stats", "qsv_plan_json",
 ]
 
 
@@ -100,6 +117,8 @@ def lib():
         "qsv_adjoint_vjp": ([vp, opp, sz, dp, sz, dp, sz, obp, sz, dp, dp, dp, u32], i32),
         "qsv_plan_stats": ([i32, i32, opp, sz, dp, sz, dp, sz, i32, i32, i32, i32, ctypes.POINTER(i64),
                             ctypes.POINTER(i64), ctypes.POINTER(i64), dp], i32),
+        "qsv_plan_json": ([i32, i32, opp, sz, dp, sz, dp, sz, i32, i32, i32, i32, ctypes.c_char_p, sz,
+                           ctypes.POINTER(sz)], i32),
     }
     for name in EXPORTS:
         f = getattr(L, name)
@@ -220,6 +239,20 @@ def plan_stats(n_qubits: int, ops, params, dtype: int = C128, adjoint: bool = Fa
     return {"passes": a.value, "tile_passes": b.value, "kernel_ops": c.value, "alg_bytes": by.value}
 
 
+def plan_json(n_qubits: int, ops, params, dtype: int = C128, adjoint: bool = False, tile_bits: int = 0,
+              low_bits: int = 0, fusion: bool = True) -> dict:
+    """Host-only dump of the lowered program (passes, tile ops, tables)."""
+    import json
+    m = MarshalledOps(ops, params)
+    need = ctypes.c_size_t()
+    args = (n_qubits, dtype, m.arr, m.n, _dptr(m.params), m.n_params, m.mat_ptr(), m.n_mat, int(adjoint),
+            tile_bits, low_bits, int(fusion))
+    _check(lib().qsv_plan_json(*args, None, 0, ctypes.byref(need)))
+    buf = ctypes.create_string_buffer(need.value)
+    _check(lib().qsv_plan_json(*args, buf, need.value, ctypes.byref(need)))
+    return json.loads(buf.value.decode())
+
+
 def device_count() -> int:
     return int(lib().qsv_device_count())
 
@@ -237,13 +270,19 @@ class Context:
         _check(L.qsv_ctx_create(device, ctypes.c_void_p(stream) if stream else None, ctypes.byref(h)))
         self.h = h
         self.device = device
+        self.states = weakref.WeakSet()
+        _live.add(self)
 
     def close(self):
         if getattr(self, "h", None):
+            for st in list(self.states):   # a state must not outlive its context
+                st.close()
             lib().qsv_ctx_destroy(self.h)
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -309,13 +348,17 @@ class State:
         else:
             _check(L.qsv_state_create(ctx.h, n_qubits, dtype, ctypes.byref(h)), ctx.h)
         self.h = h
+        _live.add(self)
+        ctx.states.add(self)
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
             lib().qsv_state_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -1,0 +1,298 @@
+"""CPU model of the lowered device program (tests only).
+
+Interprets the JSON plan of ``qsv_plan_json`` the way the HIP kernels do:
+tile index arithmetic (tile bases from the insert-zero masks, element
+offsets from the tile-bit deposit), register subcube groups (subcube base
+with zeros inserted at the group bits, element offsets), the Z-parity tables
+and the per-slot inner products.  It shares no code with the oracle; it lets
+the CPU suite check planning and lowering against the oracle without a GPU.
+The streaming single-gate passes are modelled by their index sets.
+"""
+import numpy as np
+
+OP_APPLY1, OP_APPLY2, OP_APPLYK, OP_DIAG, OP_ZPHASE, OP_DOT1, OP_DOT2, OP_DOTK, OP_DOTDIAG, OP_DOTZSUM, OP_GROUP = \
+    range(1, 12)
+MC_DENSE, MC_DIAG, MC_ANTI, MC_MID = range(4)
+
+
+def _coef(prog, off, cnt):
+    c = prog["_coef"]
+    return c[off:off + cnt]
+
+
+def expand(k, masks):
+    r = k & masks[0]
+    for i in range(1, len(masks)):
+        r |= (k << i) & masks[i]
+    return r
+
+
+def popc(x):
+    return bin(x).count("1")
+
+
+def parity_bits(x, z):
+    p = 0
+    for j, zm in enumerate(z):
+        p |= (popc(x & zm) & 1) << j
+    return p
+
+
+def run_program(prog, phi, lam=None, slots=None):
+    """Apply every pass of the program to phi (and lam); inner products are
+    added to slots[slot_base + slot]."""
+    prog["_coef"] = np.array(prog["coef"], dtype=float).view(np.complex128)
+    for st in prog["steps"]:
+        if st["type"] == "tile":
+            _tile(prog, st, phi, lam, slots)
+        else:
+            _stream(prog, st, phi)
+
+
+def _stream(prog, st, psi):
+    ex = st["ex"]
+    idx = np.array([expand(k, ex) | st["setmask"] for k in range(st["n_items"])], dtype=np.int64)
+    m2 = np.array(st["m2"], dtype=float).view(np.complex128)
+    m4 = np.array(st["m4"], dtype=float).view(np.complex128)
+    if st["type"] == "diag1":
+        psi[idx] *= st["dre"] + 1j * st["dim"]
+    elif st["type"] == "gate1":
+        i0, i1 = idx, idx | st["tbit"]
+        a0, a1 = psi[i0].copy(), psi[i1].copy()
+        psi[i0] = m2[0] * a0 + m2[1] * a1
+        psi[i1] = m2[2] * a0 + m2[3] * a1
+    elif st["type"] == "gate2":
+        b0, b1 = st["b0"], st["b1"]
+        ids = [idx, idx | b1, idx | b0, idx | b0 | b1]
+        a = [psi[i].copy() for i in ids]
+        M = m4.reshape(4, 4)
+        for r in range(4):
+            psi[ids[r]] = sum(M[r, j] * a[j] for j in range(4))
+    else:
+        k = st["k"]
+        D = 1 << k
+        M = _coef(prog, st["coff"], D * D).reshape(D, D)
+        offs = []
+        for j in range(D):
+            o = 0
+            for i in range(k):
+                if (j >> (k - 1 - i)) & 1:
+                    o |= 1 << st["tb"][i]
+            offs.append(o)
+        a = np.stack([psi[idx | o] for o in offs])
+        out = M @ a
+        for j, o in enumerate(offs):
+            psi[idx | o] = out[j]
+
+
+def _tile(prog, st, phi, lam, slots):
+    b, nthr, R = st["b"], st["nthr"], st["R"]
+    sb = st["sb"]
+    tsz = 1 << b
+    # element t = tid + r * nthr -> deposit into the tile bits
+    dep = np.zeros(tsz, dtype=np.int64)
+    for t in range(tsz):
+        o = 0
+        for j in range(b):
+            if (t >> j) & 1:
+                o |= 1 << sb[j]
+        dep[t] = o
+    tops = prog["tops"][st["op0"]:st["op0"] + st["nops"]]
+    two = lam is not None
+    for T in range(st["n_tiles"]):
+        base = expand(T, st["outer"])
+        g = base | dep
+        tp = phi[g].copy()
+        tl = lam[g].copy() if two else None
+        i = 0
+        while i < len(tops):
+            op = tops[i]
+            if op["kind"] == OP_GROUP:
+                _group(prog, st, op, tops[i + 1:i + 1 + op["m"]], tp, tl, base, slots)
+                i += 1 + op["m"]
+                continue
+            _standalone(prog, st, op, tp, tl, base, dep, slots)
+            i += 1
+        phi[g] = tp
+        if two:
+            lam[g] = tl
+
+
+def _group(prog, st, g, subs, tp, tl, base, slots):
+    b = st["b"]
+    GB = g["k"]
+    Q = g["tb"][:GB]
+    E = 1 << GB
+    nsub = (1 << b) >> GB
+    w = prog["words"]
+    eo = np.array([sum(((e >> i) & 1) << Q[i] for i in range(GB)) for e in range(E)], dtype=np.int64)
+    geo = np.array(w[g["woff"]:g["woff"] + E], dtype=np.int64)
+    gpos = w[g["woff"] + E:g["woff"] + E + b - GB]
+    sc = np.arange(nsub, dtype=np.int64)
+    tc = sc.copy()
+    for q in Q:
+        tc = ((tc >> q) << (q + 1)) | (tc & ((1 << q) - 1))
+    gc = np.full(nsub, base, dtype=np.int64)
+    for j, p in enumerate(gpos):
+        gc |= ((sc >> j) & 1) << p
+    idx = tc[:, None] | eo[None, :]            # [subcube, element] -> tile index
+    gi = gc[:, None] | geo[None, :]             # global index
+    a = tp[idx]
+    l = tl[idx] if tl is not None else None
+    for s in subs:
+        kind = s["kind"]
+        local = kind in (OP_APPLY1, OP_APPLY2, OP_DOT1, OP_DOT2)
+        if local and (base & s["gcmask"]) != s["gcval"]:
+            continue
+        ok = ((idx & s["lcmask"]) == s["lcval"])
+        if kind in (OP_APPLY1, OP_DOT1):
+            P = s["tb"][0]
+            m = _coef(prog, s["coff"], 4)
+            for e0 in range(E):
+                if e0 & (1 << P):
+                    continue
+                e1 = e0 | (1 << P)
+                sel = ok[:, e0]
+                if kind == OP_APPLY1:
+                    for x in ([a, l] if l is not None else [a]):
+                        x0, x1 = x[sel, e0].copy(), x[sel, e1].copy()
+                        if s["cls"] == MC_ANTI:
+                            x[sel, e0], x[sel, e1] = m[1] * x1, m[2] * x0
+                        else:
+                            x[sel, e0], x[sel, e1] = m[0] * x0 + m[1] * x1, m[2] * x0 + m[3] * x1
+                else:
+                    p0, p1 = a[sel, e0], a[sel, e1]
+                    v = (np.conj(l[sel, e0]) * (m[0] * p0 + m[1] * p1) + np.conj(l[sel, e1]) * (m[2] * p0 + m[3] * p1))
+                    slots[st["slot_base"] + s["slot"]] += v.imag.sum()
+        elif kind in (OP_APPLY2, OP_DOT2):
+            P0, P1 = s["tb"][0], s["tb"][1]
+            m = _coef(prog, s["coff"], 16).reshape(4, 4)
+            for e in range(E):
+                if e & ((1 << P0) | (1 << P1)):
+                    continue
+                ids = [e, e | (1 << P1), e | (1 << P0), e | (1 << P0) | (1 << P1)]
+                sel = ok[:, e]
+                if kind == OP_APPLY2:
+                    for x in ([a, l] if l is not None else [a]):
+                        y = [x[sel, i].copy() for i in ids]
+                        if s["cls"] == MC_MID:
+                            x[sel, ids[1]] = m[1, 1] * y[1] + m[1, 2] * y[2]
+                            x[sel, ids[2]] = m[2, 1] * y[1] + m[2, 2] * y[2]
+                        else:
+                            for r in range(4):
+                                x[sel, ids[r]] = sum(m[r, j] * y[j] for j in range(4))
+                else:
+                    y = [a[sel, i] for i in ids]
+                    v = sum(np.conj(l[sel, ids[r]]) * sum(m[r, j] * y[j] for j in range(4)) for r in range(4))
+                    slots[st["slot_base"] + s["slot"]] += v.imag.sum()
+        elif kind in (OP_DIAG, OP_DOTDIAG):
+            k = s["k"]
+            d = _coef(prog, s["coff"], 1 << k)
+            j = np.zeros_like(gi)
+            for i in range(k):
+                j = (j << 1) | ((gi >> s["tb"][i]) & 1)
+            on = (gi & s["gcmask"]) == s["gcval"]
+            dd = np.where(on, d[j], 1.0)
+            if kind == OP_DIAG:
+                a *= dd
+                if l is not None:
+                    l *= dd
+            else:
+                v = np.where(on, np.conj(l) * d[j] * a, 0)
+                slots[st["slot_base"] + s["slot"]] += v.imag.sum()
+        elif kind in (OP_ZPHASE, OP_DOTZSUM):
+            mz = s["m"]
+            z = w[s["woff"]:s["woff"] + mz]
+            pb = parity_bits(base, z)
+            pcs = np.array(w[s["woff"] + mz:s["woff"] + mz + nsub], dtype=np.int64)
+            pes = np.array(w[s["woff"] + mz + nsub:s["woff"] + mz + nsub + E], dtype=np.int64)
+            cnt = np.vectorize(popc)(pb ^ pcs[:, None] ^ pes[None, :])
+            if kind == OP_ZPHASE:
+                d = _coef(prog, s["coff"], mz + 1)[cnt]
+                a *= d
+                if l is not None:
+                    l *= d
+            else:
+                v = (mz - 2 * cnt) * (np.conj(l) * a).imag
+                slots[st["slot_base"] + s["slot"]] += v.sum()
+        else:
+            raise AssertionError(f"op kind {kind} inside a group")
+    tp[idx] = a
+    if tl is not None:
+        tl[idx] = l
+
+
+def _standalone(prog, st, op, tp, tl, base, dep, slots):
+    kind = op["kind"]
+    b, nthr, R = st["b"], st["nthr"], st["R"]
+    tsz = 1 << b
+    t = np.arange(tsz, dtype=np.int64)
+    gi = base | dep
+    if kind in (OP_APPLY1, OP_APPLY2, OP_APPLYK, OP_DOT1, OP_DOT2, OP_DOTK) and (base & op["gcmask"]) != op["gcval"]:
+        return
+    if kind in (OP_APPLY1, OP_APPLY2, OP_APPLYK, OP_DOT1, OP_DOT2, OP_DOTK):
+        k = op["k"]
+        D = 1 << k
+        tmask = sum(1 << op["tb"][i] for i in range(k))
+        G = _coef(prog, op["coff"], D * D).reshape(D, D)
+        gb = t[(t & tmask) == 0]
+        gb = gb[(gb & op["lcmask"]) == op["lcval"]]
+        offs = [sum(((j >> (k - 1 - i)) & 1) << op["tb"][i] for i in range(k)) for j in range(D)]
+        ids = np.stack([gb | o for o in offs])
+        if kind in (OP_APPLY1, OP_APPLY2, OP_APPLYK):
+            for x in ([tp, tl] if tl is not None else [tp]):
+                x[ids] = G @ x[ids]
+        else:
+            v = np.sum(np.conj(tl[ids]) * (G @ tp[ids]))
+            slots[st["slot_base"] + op["slot"]] += v.imag
+    elif kind in (OP_DIAG, OP_DOTDIAG):
+        k = op["k"]
+        d = _coef(prog, op["coff"], 1 << k)
+        j = np.zeros_like(gi)
+        for i in range(k):
+            j = (j << 1) | ((gi >> op["tb"][i]) & 1)
+        on = (gi & op["gcmask"]) == op["gcval"]
+        if kind == OP_DIAG:
+            dd = np.where(on, d[j], 1.0)
+            tp *= dd
+            if tl is not None:
+                tl *= dd
+        else:
+            slots[st["slot_base"] + op["slot"]] += np.where(on, np.conj(tl) * d[j] * tp, 0).imag.sum()
+    else:  # ZPHASE / DOTZSUM with per-thread and per-r parity tables
+        w = prog["words"]
+        mz = op["m"]
+        z = w[op["woff"]:op["woff"] + mz]
+        pb = parity_bits(base, z)
+        plo = w[op["woff"] + mz:op["woff"] + mz + nthr]
+        phi_r = w[op["woff"] + mz + nthr:op["woff"] + mz + nthr + R]
+        cnt = np.array([popc(pb ^ plo[int(x) % nthr] ^ phi_r[int(x) // nthr]) for x in t])
+        if kind == OP_ZPHASE:
+            d = _coef(prog, op["coff"], mz + 1)[cnt]
+            tp *= d
+            if tl is not None:
+                tl *= d
+        else:
+            slots[st["slot_base"] + op["slot"]] += ((mz - 2 * cnt) * (np.conj(tl) * tp).imag).sum()
+
+
+def emulate_apply(n, ops, params, psi0, **opts):
+    from paper_2403_02512_amd import qsv
+    prog = qsv.plan_json(n, ops, params, **opts)
+    psi = np.array(psi0, dtype=np.complex128, copy=True)
+    run_program(prog, psi)
+    return psi
+
+
+def emulate_adjoint(n, ops, params, psi, lam, **opts):
+    """One reverse sweep from phi = psi, lambda = lam; returns the gradient."""
+    from paper_2403_02512_amd import qsv
+    prog = qsv.plan_json(n, ops, params, adjoint=True, **opts)
+    phi = np.array(psi, dtype=np.complex128, copy=True)
+    lm = np.array(lam, dtype=np.complex128, copy=True)
+    slots = np.zeros(len(prog["slot_param"]))
+    run_program(prog, phi, lm, slots)
+    grad = np.zeros(len(params))
+    for s, (p, c) in enumerate(prog["slot_param"]):
+        grad[p] += c * slots[s]
+    return grad, phi

@@ -94,7 +94,7 @@ def test_wide_tiles_and_large_k(ctx, n):
         k = int(rng.integers(1, min(6, n) + 1))
         wires = list(rng.choice(n, size=k, replace=False))
         ops.append(W.op("QubitUnitary", wires, matrix=W.random_unitary(k, rng)))
-        ops.append(W.op("MultiRZ", list(rng.choice(n, size=int(rng.integers(1, n + 1)), replace=False)),
+        ops.append(W.op("MultiRZ", list(rng.choice(n, size=int(rng.integers(1, min(n, 8) + 1)), replace=False)),
                         (-1, float(rng.uniform(-3, 3)))))
     psi0 = W.random_state(n, 7)
     for opts in ({}, {qsv.OPT_TILE_BITS: 6, qsv.OPT_LOW_BITS: 1}, {qsv.OPT_FUSION: 0}):

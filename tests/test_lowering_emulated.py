@@ -1,0 +1,43 @@
+"""CPU checks of planning and lowering: the lowered device program (passes,
+tile ops, register groups, Z-parity tables, inner-product slots), run by the
+CPU model in program_emulator.py, against the oracle.  No GPU needed."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_02512_amd import workloads as W
+from tests.program_emulator import emulate_adjoint, emulate_apply
+
+OPTS = [{}, {"tile_bits": 5, "low_bits": 2}, {"tile_bits": 4, "low_bits": 1}, {"fusion": False}]
+
+
+@pytest.mark.parametrize("opt", range(len(OPTS)))
+@pytest.mark.parametrize("n,seed", [(2, 0), (5, 1), (7, 2), (9, 3)])
+def test_forward_program(n, seed, opt):
+    c = W.random_circuit(n, 40, seed=500 + seed, n_params=6, p_ctrl=0.25, max_k=min(n, 4))
+    psi0 = W.random_state(n, seed)
+    got = emulate_apply(n, c.ops, c.params, psi0, **OPTS[opt])
+    np.testing.assert_allclose(got, oracle.apply(n, c.ops, c.params, psi=psi0), atol=1e-12)
+
+
+@pytest.mark.parametrize("opt", range(len(OPTS)))
+@pytest.mark.parametrize("n,seed", [(2, 0), (5, 1), (7, 2), (9, 3)])
+def test_adjoint_program(n, seed, opt):
+    c = W.random_circuit(n, 30, seed=600 + seed, n_params=5, p_ctrl=0.25, max_k=min(n, 4))
+    obs = W.random_observables(n, np.random.default_rng(seed), n_obs=1, n_terms=3)
+    psi = oracle.apply(n, c.ops, c.params)
+    lam = oracle.apply_pauli_sum(psi, obs[0])
+    g, phi = emulate_adjoint(n, c.ops, c.params, psi, lam, **OPTS[opt])
+    np.testing.assert_allclose(g, oracle.adjoint_jacobian(psi, c.ops, c.params, obs)[0], atol=1e-11)
+    np.testing.assert_allclose(phi, oracle.zero_state(n), atol=1e-12)   # the sweep un-applies everything
+
+
+@pytest.mark.parametrize("n", [8, 10])
+def test_qaoa_program(n):
+    c = W.config3(n=n)
+    psi = oracle.apply(n, c.ops, c.params)
+    np.testing.assert_allclose(emulate_apply(n, c.ops, c.params, oracle.zero_state(n)), psi, atol=1e-12)
+    lam = oracle.apply_pauli_sum(psi, c.observables[0])
+    for opts in ({}, {"tile_bits": 6, "low_bits": 2}):
+        g, _ = emulate_adjoint(n, c.ops, c.params, psi, lam, **opts)
+        np.testing.assert_allclose(g, oracle.adjoint_jacobian(psi, c.ops, c.params, c.observables)[0], atol=1e-11)
