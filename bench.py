@@ -145,6 +145,9 @@ def main():
     ap.add_argument("--n", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fusion", type=int, default=1)
+    ap.add_argument("--tile-bits", type=int, default=0, help="qubits per LDS tile, one-vector passes (0: default)")
+    ap.add_argument("--tile-bits-adj", type=int, default=0, help="qubits per LDS tile, adjoint passes (0: default)")
+    ap.add_argument("--low-bits", type=int, default=0, help="coalescing low bits per tile (0: default)")
     ap.add_argument("--micro", action="store_true", help="per-kernel-class gate-apply bandwidth sweep")
     ap.add_argument("--micro-dtype", default="c128", choices=["c128", "c64"])
     args = ap.parse_args()
@@ -168,6 +171,9 @@ def main():
     stream = torch.cuda.current_stream(dev).cuda_stream
     ctx = qsv.Context(0, stream)
     ctx.set_option(qsv.OPT_FUSION, args.fusion)
+    ctx.set_option(qsv.OPT_TILE_BITS, args.tile_bits)
+    ctx.set_option(qsv.OPT_TILE_BITS_ADJ, args.tile_bits_adj)
+    ctx.set_option(qsv.OPT_LOW_BITS, args.low_bits)
     psi = torch.empty(1 << n, dtype=torch.complex128, device=dev)
     st = qsv.State(ctx, n, qsv.C128, tensor=psi)
     m_ops = qsv.MarshalledOps(circ.ops, circ.params)
@@ -216,7 +222,8 @@ def main():
         "config": {"workload": f"QAOA MaxCut 3-regular graph, {n} qubits, p=4, complex128: forward + <H_C> + "
                                f"adjoint Jacobian", "n_qubits": n, "n_gates": len(circ.ops),
                    "n_params": circ.n_params, "n_terms": len(circ.observables[0].words), "precision": "c128",
-                   "fusion": bool(args.fusion)},
+                   "fusion": bool(args.fusion), "tile_bits": args.tile_bits or "default",
+                   "tile_bits_adj": args.tile_bits_adj or "default", "low_bits": args.low_bits or "default"},
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels,
         "result": {"expval": float(ev[0]), "jac": [float(x) for x in jac[0]]},
     }

@@ -294,6 +294,17 @@ struct Program {
 int classify1(const std::vector<cd>& m) {
     if (m[1] == 0.0 && m[2] == 0.0) return MC_DIAG;
     if (m[0] == 0.0 && m[3] == 0.0) return MC_ANTI;
+    bool real = true;
+    for (int j = 0; j < 4; ++j) real = real && m[j].imag() == 0.0;
+    if (real) return MC_REAL;
+    if (m[0].imag() == 0.0 && m[3].imag() == 0.0 && m[1].real() == 0.0 && m[2].real() == 0.0) return MC_RIRI;
+    return MC_DENSE;
+}
+
+// generator classes of one-target inner products
+int classify_gen1(const std::vector<cd>& g) {
+    if (g[0] == 0.0 && g[3] == 0.0 && g[1] == 1.0 && g[2] == 1.0) return MC_PX;
+    if (g[0] == 0.0 && g[3] == 0.0 && g[1] == cd(0.0, -1.0) && g[2] == cd(0.0, 1.0)) return MC_PY;
     return MC_DENSE;
 }
 
@@ -454,6 +465,10 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
     const bool grouped = b >= GB;
     const int nsub = grouped ? (1 << (b - GB)) : 0;
     int nslots = 0;
+    // phase tables of the pass, appended contiguously after emission (the
+    // kernel copies them to LDS once per launch)
+    std::vector<cd> ztab;
+    std::vector<std::pair<size_t, int>> zpatch;  // (tops index, offset in ztab)
 
     auto controls = [&](const Factor& f, TOp& op, bool local_ok) {
         op.lcmask = op.lcval = 0;
@@ -515,8 +530,9 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
             }
             if (pr.kind == Proto::ZPHASE) {
                 const int m = (int)pr.z.size();
+                zpatch.push_back({P.tops.size(), (int)ztab.size()});
                 for (int cnt = 0; cnt <= m; ++cnt)
-                    P.coef.push_back(std::exp(cd(0.0, -0.5 * pr.angle * (m - 2 * cnt))));
+                    ztab.push_back(std::exp(cd(0.0, -0.5 * pr.angle * (m - 2 * cnt))));
             }
             P.tops.push_back(op);
             return;
@@ -548,6 +564,7 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
         }
         if (dot) {
             op.kind = f.k == 1 ? OP_DOT1 : (f.k == 2 ? OP_DOT2 : OP_DOTK);
+            if (Q && f.k == 1) op.cls = classify_gen1(mm);
         } else {
             op.kind = f.k == 1 ? OP_APPLY1 : (f.k == 2 ? OP_APPLY2 : OP_APPLYK);
             op.cls = f.k == 1 ? classify1(mm) : (f.k == 2 ? classify2(mm) : MC_DENSE);
@@ -615,8 +632,15 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
     }
     a.nops = (int)P.tops.size() - a.op0;
     a.nslots = nslots;
+    a.zt_off = (int64_t)P.coef.size();
+    a.zt_n = (int)ztab.size();
+    for (auto& zp : zpatch) {
+        P.tops[zp.first].coff = a.zt_off + zp.second;
+        P.tops[zp.first].aux = zp.second;
+    }
+    for (auto& x : ztab) P.coef.push_back(x);
     st.nslots = nslots;
-    st.lds = (size_t)tile_lds_bytes(b, two, (int)eb, nslots);
+    st.lds = (size_t)tile_lds_bytes(b, two, (int)eb, nslots, a.zt_n);
     st.bytes = (double)(two ? 4 : 2) * (double)((uint64_t)1 << n) * (double)eb;
     P.max_partials = std::max(P.max_partials, (size_t)nslots * st.grid);
     P.steps.push_back(st);

@@ -294,6 +294,12 @@ hipError_t launch_gatek(hipStream_t s, void* psi, uint64_t n_items, const Expand
 
 // ------------------------------------------------------------------ LDS-tiled fused pass
 
+// LDS position of tile element t: bits 4..7 are XOR-ed into bits 0..3, so
+// that threads reading subcubes whose group bits include the lowest tile bits
+// (a lane stride of 16 elements) spread over all banks.  A bijection on any
+// tile size.
+__device__ __forceinline__ uint32_t sw(uint32_t t) { return t ^ ((t >> 4) & 15u); }
+
 // One op of a tile pass.  tp/tl: the phi/lambda tiles in LDS (tl only when
 // TWO).  The thread owns tile elements t = tid + r * nthr, r < R; pair and
 // quad ops address any element of the tile.
@@ -307,6 +313,7 @@ struct TileCtx {
     const uint64_t* words;
     uint64_t base, offlo;
     const uint64_t* offhi;
+    const cx<T>* ztab;  // the pass's phase tables, in LDS
     int tid, nthr, nwaves;
 };
 
@@ -323,16 +330,17 @@ __device__ __forceinline__ void tile_apply1(const TileCtx<T, TWO, R>& c, const T
 #pragma unroll
         for (int v = 0; v < (TWO ? 2 : 1); ++v) {
             cx<T>* t = v ? c.tl : c.tp;
-            const cx<T> a0 = t[t0], a1 = t[t1];
+            const uint32_t s0 = sw(t0), s1 = sw(t1);
+            const cx<T> a0 = t[s0], a1 = t[s1];
             if (cls == MC_DIAG) {
-                t[t0] = cmul(m0, a0);
-                t[t1] = cmul(m3, a1);
+                t[s0] = cmul(m0, a0);
+                t[s1] = cmul(m3, a1);
             } else if (cls == MC_ANTI) {
-                t[t0] = cmul(m1, a1);
-                t[t1] = cmul(m2, a0);
+                t[s0] = cmul(m1, a1);
+                t[s1] = cmul(m2, a0);
             } else {
-                t[t0] = cmad(m0, a0, cmul(m1, a1));
-                t[t1] = cmad(m2, a0, cmul(m3, a1));
+                t[s0] = cmad(m0, a0, cmul(m1, a1));
+                t[s1] = cmad(m2, a0, cmul(m3, a1));
             }
         }
     }
@@ -349,7 +357,7 @@ __device__ __forceinline__ void tile_apply2(const TileCtx<T, TWO, R>& c, const T
         uint32_t t = (((uint32_t)p & ~(plo - 1)) << 1) | ((uint32_t)p & (plo - 1));
         t = ((t & ~(phi - 1)) << 1) | (t & (phi - 1));
         if ((t & op.lcmask) != op.lcval) continue;
-        const uint32_t idx[4] = {t, t | b1, t | b0, t | b0 | b1};
+        const uint32_t idx[4] = {sw(t), sw(t | b1), sw(t | b0), sw(t | b0 | b1)};
 #pragma unroll
         for (int v = 0; v < (TWO ? 2 : 1); ++v) {
             cx<T>* tt = v ? c.tl : c.tp;
@@ -410,8 +418,8 @@ __device__ __forceinline__ void tile_applyk(const TileCtx<T, TWO, R>& c, const T
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const cx<T> mm = c.coef[op.coff + row[r] * dim + j];
-            ap[r] = cmad(mm, c.tp[gb[r] | sp], ap[r]);
-            if (TWO) al[r] = cmad(mm, c.tl[gb[r] | sp], al[r]);
+            ap[r] = cmad(mm, c.tp[sw(gb[r] | sp)], ap[r]);
+            if (TWO) al[r] = cmad(mm, c.tl[sw(gb[r] | sp)], al[r]);
         }
     }
     __syncthreads();
@@ -419,8 +427,8 @@ __device__ __forceinline__ void tile_applyk(const TileCtx<T, TWO, R>& c, const T
     for (int r = 0; r < R; ++r) {
         if (!on[r]) continue;
         const uint32_t t = c.tid + r * c.nthr;
-        c.tp[t] = ap[r];
-        if (TWO) c.tl[t] = al[r];
+        c.tp[sw(t)] = ap[r];
+        if (TWO) c.tl[sw(t)] = al[r];
     }
 }
 
@@ -434,8 +442,8 @@ __device__ __forceinline__ void tile_diag(const TileCtx<T, TWO, R>& c, const TOp
         for (int i = 0; i < op.k; ++i) j = (j << 1) | (int)((g >> op.tb[i]) & 1);
         const cx<T> d = c.coef[op.coff + j];
         const int t = c.tid + r * c.nthr;
-        c.tp[t] = cmul(d, c.tp[t]);
-        if (TWO) c.tl[t] = cmul(d, c.tl[t]);
+        c.tp[sw(t)] = cmul(d, c.tp[sw(t)]);
+        if (TWO) c.tl[sw(t)] = cmul(d, c.tl[sw(t)]);
     }
 }
 
@@ -460,8 +468,8 @@ __device__ __forceinline__ void tile_zphase(const TileCtx<T, TWO, R>& c, const T
         const int cnt = (int)__popcll(pl ^ ph[r]);
         const cx<T> d = c.coef[op.coff + cnt];
         const int t = c.tid + r * c.nthr;
-        c.tp[t] = cmul(d, c.tp[t]);
-        if (TWO) c.tl[t] = cmul(d, c.tl[t]);
+        c.tp[sw(t)] = cmul(d, c.tp[sw(t)]);
+        if (TWO) c.tl[sw(t)] = cmul(d, c.tl[sw(t)]);
     }
 }
 
@@ -476,9 +484,9 @@ __device__ __forceinline__ void tile_dot(const TileCtx<T, TWO, R>& c, const TOp&
             for (int p = c.tid; p < half; p += c.nthr) {
                 const uint32_t t0 = (((uint32_t)p & ~lo) << 1) | ((uint32_t)p & lo), t1 = t0 | qb;
                 if ((t0 & op.lcmask) != op.lcval) continue;
-                const cx<T> p0 = c.tp[t0], p1 = c.tp[t1];
-                acc += im_conj_mul(c.tl[t0], cmad(G[0], p0, cmul(G[1], p1)));
-                acc += im_conj_mul(c.tl[t1], cmad(G[2], p0, cmul(G[3], p1)));
+                const cx<T> p0 = c.tp[sw(t0)], p1 = c.tp[sw(t1)];
+                acc += im_conj_mul(c.tl[sw(t0)], cmad(G[0], p0, cmul(G[1], p1)));
+                acc += im_conj_mul(c.tl[sw(t1)], cmad(G[2], p0, cmul(G[3], p1)));
             }
         } else if (op.kind == OP_DOT2 || op.kind == OP_DOTK) {
             const int k = op.k, dim = 1 << k;
@@ -492,8 +500,8 @@ __device__ __forceinline__ void tile_dot(const TileCtx<T, TWO, R>& c, const TOp&
                 for (int i = 0; i < k; ++i) rw = (rw << 1) | ((t >> op.tb[i]) & 1);
                 const uint32_t gb = t & ~tmask;
                 cx<T> v = {T(0), T(0)};
-                for (int j = 0; j < dim; ++j) v = cmad(G[rw * dim + j], c.tp[gb | spread_bits(j, k, op.tb)], v);
-                acc += im_conj_mul(c.tl[t], v);
+                for (int j = 0; j < dim; ++j) v = cmad(G[rw * dim + j], c.tp[sw(gb | spread_bits(j, k, op.tb))], v);
+                acc += im_conj_mul(c.tl[sw(t)], v);
             }
         } else if (op.kind == OP_DOTDIAG) {
 #pragma unroll
@@ -503,7 +511,7 @@ __device__ __forceinline__ void tile_dot(const TileCtx<T, TWO, R>& c, const TOp&
                 int j = 0;
                 for (int i = 0; i < op.k; ++i) j = (j << 1) | (int)((g >> op.tb[i]) & 1);
                 const int t = c.tid + r * c.nthr;
-                acc += im_conj_mul(c.tl[t], cmul(G[j], c.tp[t]));
+                acc += im_conj_mul(c.tl[sw(t)], cmul(G[j], c.tp[sw(t)]));
             }
         } else {  // OP_DOTZSUM: generator sum_j Z^{z_j}, eigenvalue m - 2 * (odd count)
             const uint64_t* w = c.words + op.woff;
@@ -514,7 +522,7 @@ __device__ __forceinline__ void tile_dot(const TileCtx<T, TWO, R>& c, const TOp&
             for (int r = 0; r < R; ++r) {
                 const int cnt = (int)__popcll(pl ^ ph[r]);
                 const int t = c.tid + r * c.nthr;
-                acc += (double)(op.m - 2 * cnt) * im_conj_mul(c.tl[t], c.tp[t]);
+                acc += (double)(op.m - 2 * cnt) * im_conj_mul(c.tl[sw(t)], c.tp[sw(t)]);
             }
         }
         block_add(acc, c.red, c.sacc + op.slot * c.nwaves, c.tid, c.nthr);
@@ -532,37 +540,48 @@ __device__ __forceinline__ void tile_dot(const TileCtx<T, TWO, R>& c, const TOp&
 // group instead of one per gate.  Element e of a subcube is tile index
 // tc | eo[e], eo[e] = sum of bit i of e shifted to Q[i].
 
-template <typename T, bool TWO, int GB, int P, int CLS>
-__device__ __forceinline__ void g_apply1(cx<T>* a, cx<T>* l, const cx<T>* m, uint32_t tc, const uint32_t* eo,
+// 2x2 update of one register pair, specialised by matrix class
+template <typename T, int CLS>
+__device__ __forceinline__ void bfly(const cx<T>* m, cx<T>& x0, cx<T>& x1) {
+    const cx<T> a0 = x0, a1 = x1;
+    if (CLS == MC_ANTI) {
+        x0 = cmul(m[1], a1);
+        x1 = cmul(m[2], a0);
+    } else if (CLS == MC_REAL) {
+        const T m0 = m[0].re, m1 = m[1].re, m2 = m[2].re, m3 = m[3].re;
+        x0 = {m0 * a0.re + m1 * a1.re, m0 * a0.im + m1 * a1.im};
+        x1 = {m2 * a0.re + m3 * a1.re, m2 * a0.im + m3 * a1.im};
+    } else if (CLS == MC_RIRI) {  // [[r0, i q1], [i q2, r3]]
+        const T r0 = m[0].re, q1 = m[1].im, q2 = m[2].im, r3 = m[3].re;
+        x0 = {r0 * a0.re - q1 * a1.im, r0 * a0.im + q1 * a1.re};
+        x1 = {r3 * a1.re - q2 * a0.im, r3 * a1.im + q2 * a0.re};
+    } else {
+        x0 = cmad(m[0], a0, cmul(m[1], a1));
+        x1 = cmad(m[2], a0, cmul(m[3], a1));
+    }
+}
+
+template <typename T, bool TWO, int GB, int P, int CLS, bool CTRL>
+__device__ __forceinline__ void g_apply1(cx<T>* a, cx<T>* l, const cx<T>* mg, uint32_t tc, const uint32_t* eo,
                                          uint32_t lcm, uint32_t lcv) {
-    const cx<T> m0 = m[0], m1 = m[1], m2 = m[2], m3 = m[3];
+    const cx<T> m[4] = {mg[0], mg[1], mg[2], mg[3]};
 #pragma unroll
     for (int e0 = 0; e0 < (1 << GB); ++e0) {
         if (e0 & (1 << P)) continue;
         const int e1 = e0 | (1 << P);
-        if (((tc | eo[e0]) & lcm) != lcv) continue;
-#pragma unroll
-        for (int v = 0; v < (TWO ? 2 : 1); ++v) {
-            cx<T>* x = v ? l : a;
-            const cx<T> x0 = x[e0], x1 = x[e1];
-            if (CLS == MC_ANTI) {
-                x[e0] = cmul(m1, x1);
-                x[e1] = cmul(m2, x0);
-            } else {
-                x[e0] = cmad(m0, x0, cmul(m1, x1));
-                x[e1] = cmad(m2, x0, cmul(m3, x1));
-            }
-        }
+        if (CTRL && ((tc | eo[e0]) & lcm) != lcv) continue;
+        bfly<T, CLS>(m, a[e0], a[e1]);
+        if (TWO) bfly<T, CLS>(m, l[e0], l[e1]);
     }
 }
 
-template <typename T, bool TWO, int GB, int P0, int P1, int CLS>
+template <typename T, bool TWO, int GB, int P0, int P1, int CLS, bool CTRL>
 __device__ __forceinline__ void g_apply2(cx<T>* a, cx<T>* l, const cx<T>* m, uint32_t tc, const uint32_t* eo,
                                          uint32_t lcm, uint32_t lcv) {
 #pragma unroll
     for (int e = 0; e < (1 << GB); ++e) {
         if (e & ((1 << P0) | (1 << P1))) continue;
-        if (((tc | eo[e]) & lcm) != lcv) continue;
+        if (CTRL && ((tc | eo[e]) & lcm) != lcv) continue;
         const int id[4] = {e, e | (1 << P1), e | (1 << P0), e | (1 << P0) | (1 << P1)};
 #pragma unroll
         for (int v = 0; v < (TWO ? 2 : 1); ++v) {
@@ -585,7 +604,7 @@ __device__ __forceinline__ void g_apply2(cx<T>* a, cx<T>* l, const cx<T>* m, uin
     }
 }
 
-template <typename T, int GB, int P>
+template <typename T, int GB, int P, int CLS, bool CTRL>
 __device__ __forceinline__ double g_dot1(const cx<T>* a, const cx<T>* l, const cx<T>* G, uint32_t tc,
                                          const uint32_t* eo, uint32_t lcm, uint32_t lcv) {
     const cx<T> g0 = G[0], g1 = G[1], g2 = G[2], g3 = G[3];
@@ -594,21 +613,28 @@ __device__ __forceinline__ double g_dot1(const cx<T>* a, const cx<T>* l, const c
     for (int e0 = 0; e0 < (1 << GB); ++e0) {
         if (e0 & (1 << P)) continue;
         const int e1 = e0 | (1 << P);
-        if (((tc | eo[e0]) & lcm) != lcv) continue;
-        acc += im_conj_mul(l[e0], cmad(g0, a[e0], cmul(g1, a[e1])));
-        acc += im_conj_mul(l[e1], cmad(g2, a[e0], cmul(g3, a[e1])));
+        if (CTRL && ((tc | eo[e0]) & lcm) != lcv) continue;
+        if (CLS == MC_PX) {         // G = X: Im(l0* p1) + Im(l1* p0)
+            acc += im_conj_mul(l[e0], a[e1]) + im_conj_mul(l[e1], a[e0]);
+        } else if (CLS == MC_PY) {  // G = Y: Re(l1* p0) - Re(l0* p1)
+            acc += (double)l[e1].re * a[e0].re + (double)l[e1].im * a[e0].im -
+                   (double)l[e0].re * a[e1].re - (double)l[e0].im * a[e1].im;
+        } else {
+            acc += im_conj_mul(l[e0], cmad(g0, a[e0], cmul(g1, a[e1])));
+            acc += im_conj_mul(l[e1], cmad(g2, a[e0], cmul(g3, a[e1])));
+        }
     }
     return acc;
 }
 
-template <typename T, int GB, int P0, int P1>
+template <typename T, int GB, int P0, int P1, bool CTRL>
 __device__ __forceinline__ double g_dot2(const cx<T>* a, const cx<T>* l, const cx<T>* G, uint32_t tc,
                                          const uint32_t* eo, uint32_t lcm, uint32_t lcv) {
     double acc = 0.0;
 #pragma unroll
     for (int e = 0; e < (1 << GB); ++e) {
         if (e & ((1 << P0) | (1 << P1))) continue;
-        if (((tc | eo[e]) & lcm) != lcv) continue;
+        if (CTRL && ((tc | eo[e]) & lcm) != lcv) continue;
         const int id[4] = {e, e | (1 << P1), e | (1 << P0), e | (1 << P0) | (1 << P1)};
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -676,7 +702,6 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
     const int nsub = (c.nthr * R) >> GB;
     const uint64_t* w = c.words + g.woff;
     uint32_t eo[E];
-    uint64_t geo[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         uint32_t o = 0;
@@ -684,12 +709,12 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
         for (int i = 0; i < GB; ++i)
             if ((e >> i) & 1) o |= 1u << g.tb[i];
         eo[e] = o;
-        geo[e] = w[e];
     }
     DotAcc acc;
 #pragma unroll
     for (int d = 0; d < GROUP_MAX_DOTS; ++d) acc.v[d] = 0.0;
     const int nq = b - GB;
+#pragma unroll 1
     for (int sc = c.tid; sc < nsub; sc += c.nthr) {
         uint32_t tc = (uint32_t)sc;
 #pragma unroll
@@ -703,8 +728,8 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
         cx<T> a[E], l[TWO ? E : 1];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            a[e] = c.tp[tc | eo[e]];
-            if (TWO) l[e] = c.tl[tc | eo[e]];
+            a[e] = c.tp[sw(tc | eo[e])];
+            if (TWO) l[e] = c.tl[sw(tc | eo[e])];
         }
         for (int si = 0; si < g.m; ++si) {
             const TOp& s = subs[si];
@@ -713,24 +738,47 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
             const cx<T>* m = c.coef + s.coff;
             const int p0 = s.tb[0], p1 = s.tb[1];
             switch (s.kind) {
-            case OP_APPLY1:
-                if (s.cls == MC_ANTI) {
-#define F(P) g_apply1<T, TWO, GB, P, MC_ANTI>(a, l, m, tc, eo, s.lcmask, s.lcval)
+            case OP_APPLY1: {
+                const bool ctrl = s.lcmask != 0;
+                if (ctrl) {
+#define F(P) g_apply1<T, TWO, GB, P, MC_DENSE, true>(a, l, m, tc, eo, s.lcmask, s.lcval)
+                    QSV_P1_CASES(F)
+#undef F
+                } else if (s.cls == MC_ANTI) {
+#define F(P) g_apply1<T, TWO, GB, P, MC_ANTI, false>(a, l, m, tc, eo, 0, 0)
+                    QSV_P1_CASES(F)
+#undef F
+                } else if (s.cls == MC_REAL) {
+#define F(P) g_apply1<T, TWO, GB, P, MC_REAL, false>(a, l, m, tc, eo, 0, 0)
+                    QSV_P1_CASES(F)
+#undef F
+                } else if (s.cls == MC_RIRI) {
+#define F(P) g_apply1<T, TWO, GB, P, MC_RIRI, false>(a, l, m, tc, eo, 0, 0)
                     QSV_P1_CASES(F)
 #undef F
                 } else {
-#define F(P) g_apply1<T, TWO, GB, P, MC_DENSE>(a, l, m, tc, eo, s.lcmask, s.lcval)
+#define F(P) g_apply1<T, TWO, GB, P, MC_DENSE, false>(a, l, m, tc, eo, 0, 0)
                     QSV_P1_CASES(F)
 #undef F
                 }
-                break;
+            } break;
             case OP_APPLY2:
-                if (s.cls == MC_MID) {
-#define F(A, B) g_apply2<T, TWO, GB, A, B, MC_MID>(a, l, m, tc, eo, s.lcmask, s.lcval)
+                if (s.lcmask) {
+                    if (s.cls == MC_MID) {
+#define F(A, B) g_apply2<T, TWO, GB, A, B, MC_MID, true>(a, l, m, tc, eo, s.lcmask, s.lcval)
+                        QSV_P2_CASES(F)
+#undef F
+                    } else {
+#define F(A, B) g_apply2<T, TWO, GB, A, B, MC_DENSE, true>(a, l, m, tc, eo, s.lcmask, s.lcval)
+                        QSV_P2_CASES(F)
+#undef F
+                    }
+                } else if (s.cls == MC_MID) {
+#define F(A, B) g_apply2<T, TWO, GB, A, B, MC_MID, false>(a, l, m, tc, eo, 0, 0)
                     QSV_P2_CASES(F)
 #undef F
                 } else {
-#define F(A, B) g_apply2<T, TWO, GB, A, B, MC_DENSE>(a, l, m, tc, eo, s.lcmask, s.lcval)
+#define F(A, B) g_apply2<T, TWO, GB, A, B, MC_DENSE, false>(a, l, m, tc, eo, 0, 0)
                     QSV_P2_CASES(F)
 #undef F
                 }
@@ -738,7 +786,7 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
             case OP_DIAG:
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
-                    const uint64_t gi = gc | geo[e];
+                    const uint64_t gi = gc | w[e];
                     if ((gi & s.gcmask) != s.gcval) continue;
                     int j = 0;
                     for (int i = 0; i < s.k; ++i) j = (j << 1) | (int)((gi >> s.tb[i]) & 1);
@@ -752,7 +800,7 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
                 const uint64_t pc = parity_bits(c.base, z, s.m) ^ z[s.m + sc];
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
-                    const cx<T> d = m[(int)__popcll(pc ^ z[s.m + nsub + e])];
+                    const cx<T> d = c.ztab[s.aux + (int)__popcll(pc ^ z[s.m + nsub + e])];
                     a[e] = cmul(d, a[e]);
                     if (TWO) l[e] = cmul(d, l[e]);
                 }
@@ -761,17 +809,37 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
                 if constexpr (TWO) {
                     double v = 0.0;
                     if (s.kind == OP_DOT1) {
-#define F(P) v = g_dot1<T, GB, P>(a, l, m, tc, eo, s.lcmask, s.lcval)
-                        QSV_P1_CASES(F)
+                        if (s.lcmask) {
+#define F(P) v = g_dot1<T, GB, P, MC_DENSE, true>(a, l, m, tc, eo, s.lcmask, s.lcval)
+                            QSV_P1_CASES(F)
 #undef F
+                        } else if (s.cls == MC_PX) {
+#define F(P) v = g_dot1<T, GB, P, MC_PX, false>(a, l, m, tc, eo, 0, 0)
+                            QSV_P1_CASES(F)
+#undef F
+                        } else if (s.cls == MC_PY) {
+#define F(P) v = g_dot1<T, GB, P, MC_PY, false>(a, l, m, tc, eo, 0, 0)
+                            QSV_P1_CASES(F)
+#undef F
+                        } else {
+#define F(P) v = g_dot1<T, GB, P, MC_DENSE, false>(a, l, m, tc, eo, 0, 0)
+                            QSV_P1_CASES(F)
+#undef F
+                        }
                     } else if (s.kind == OP_DOT2) {
-#define F(A, B) v = g_dot2<T, GB, A, B>(a, l, m, tc, eo, s.lcmask, s.lcval)
-                        QSV_P2_CASES(F)
+                        if (s.lcmask) {
+#define F(A, B) v = g_dot2<T, GB, A, B, true>(a, l, m, tc, eo, s.lcmask, s.lcval)
+                            QSV_P2_CASES(F)
 #undef F
+                        } else {
+#define F(A, B) v = g_dot2<T, GB, A, B, false>(a, l, m, tc, eo, 0, 0)
+                            QSV_P2_CASES(F)
+#undef F
+                        }
                     } else if (s.kind == OP_DOTDIAG) {
 #pragma unroll
                         for (int e = 0; e < E; ++e) {
-                            const uint64_t gi = gc | geo[e];
+                            const uint64_t gi = gc | w[e];
                             if ((gi & s.gcmask) != s.gcval) continue;
                             int j = 0;
                             for (int i = 0; i < s.k; ++i) j = (j << 1) | (int)((gi >> s.tb[i]) & 1);
@@ -791,8 +859,8 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
         }
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            c.tp[tc | eo[e]] = a[e];
-            if (TWO) c.tl[tc | eo[e]] = l[e];
+            c.tp[sw(tc | eo[e])] = a[e];
+            if (TWO) c.tl[sw(tc | eo[e])] = l[e];
         }
     }
     if constexpr (TWO) {
@@ -816,7 +884,7 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
 // small for groups); group-only passes compile without those code paths,
 // which keeps their register footprint (and so their occupancy) lower.
 template <typename T, bool TWO, int LR, bool GEN>
-__global__ __launch_bounds__(256) void k_tile(cx<T>* __restrict__ phi, cx<T>* __restrict__ lam, const TileArgs a,
+__global__ __launch_bounds__(256, 2) void k_tile(cx<T>* __restrict__ phi, cx<T>* __restrict__ lam, const TileArgs a,
                                               const TOp* __restrict__ ops, const cx<T>* __restrict__ coef,
                                               const uint64_t* __restrict__ words, double* __restrict__ partials) {
     constexpr int R = 1 << LR;
@@ -835,6 +903,13 @@ __global__ __launch_bounds__(256) void k_tile(cx<T>* __restrict__ phi, cx<T>* __
     c.tid = tid;
     c.nthr = nthr;
     c.nwaves = nthr >= 64 ? nthr >> 6 : 1;
+    {
+        // phase tables after the per-wave slot accumulators, 16-byte aligned
+        const size_t off = (64 + (size_t)a.nslots * c.nwaves) * sizeof(double);
+        cx<T>* zt = reinterpret_cast<cx<T>*>(reinterpret_cast<unsigned char*>(c.red) + ((off + 15) & ~(size_t)15));
+        for (int i = tid; i < a.zt_n; i += nthr) zt[i] = coef[a.zt_off + i];
+        c.ztab = zt;
+    }
     uint64_t offlo = 0;
     for (int j = 0; j < a.nthr_log2; ++j) offlo |= (uint64_t)((tid >> j) & 1) << a.sb[j];
     c.offlo = offlo;
@@ -843,11 +918,22 @@ __global__ __launch_bounds__(256) void k_tile(cx<T>* __restrict__ phi, cx<T>* __
     for (uint64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
         const uint64_t base = expand_idx(tile, a.outer);
         c.base = base;
+        // global -> LDS in chunks of LCH elements per thread: LCH loads in
+        // flight per thread without keeping all R values live in registers
+        constexpr int LCH = R < 8 ? R : 8;
+        for (int r0 = 0; r0 < R; r0 += LCH) {
+            cx<T> vp[LCH], vl[LCH];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint64_t g = base | offlo | a.offhi[r];
-            c.tp[tid + r * nthr] = phi[g];
-            if (TWO) c.tl[tid + r * nthr] = lam[g];
+            for (int r = 0; r < LCH; ++r) {
+                const uint64_t g = base | offlo | a.offhi[r0 + r];
+                vp[r] = phi[g];
+                if (TWO) vl[r] = lam[g];
+            }
+#pragma unroll
+            for (int r = 0; r < LCH; ++r) {
+                c.tp[sw(tid + (r0 + r) * nthr)] = vp[r];
+                if (TWO) c.tl[sw(tid + (r0 + r) * nthr)] = vl[r];
+            }
         }
         __syncthreads();
         for (int oi = 0; oi < a.nops; ++oi) {
@@ -873,11 +959,13 @@ __global__ __launch_bounds__(256) void k_tile(cx<T>* __restrict__ phi, cx<T>* __
             }
             __syncthreads();
         }
+        for (int r0 = 0; r0 < R; r0 += LCH) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint64_t g = base | offlo | a.offhi[r];
-            phi[g] = c.tp[tid + r * nthr];
-            if (TWO) lam[g] = c.tl[tid + r * nthr];
+            for (int r = 0; r < LCH; ++r) {
+                const uint64_t g = base | offlo | a.offhi[r0 + r];
+                phi[g] = c.tp[sw(tid + (r0 + r) * nthr)];
+                if (TWO) lam[g] = c.tl[sw(tid + (r0 + r) * nthr)];
+            }
         }
         __syncthreads();
     }
@@ -889,10 +977,11 @@ __global__ __launch_bounds__(256) void k_tile(cx<T>* __restrict__ phi, cx<T>* __
     }
 }
 
-int tile_lds_bytes(int b, bool two, int elem_bytes, int nslots) {
+int tile_lds_bytes(int b, bool two, int elem_bytes, int nslots, int zt_n) {
     const int nthr = 1 << (b < 8 ? b : 8);
     const int nwaves = nthr >= 64 ? nthr / 64 : 1;
-    return (two ? 2 : 1) * (1 << b) * elem_bytes + 64 * 8 + nslots * nwaves * 8;
+    const int acc = ((64 + nslots * nwaves) * 8 + 15) & ~15;
+    return (two ? 2 : 1) * (1 << b) * elem_bytes + acc + zt_n * elem_bytes;
 }
 
 template <typename T, bool TWO, int LR, bool GEN>

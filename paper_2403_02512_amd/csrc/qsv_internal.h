@@ -43,7 +43,12 @@ enum TOpKind : int32_t {
     OP_GROUP        // the next m ops act inside register subcubes over the k tile bits tb[0..k-1]
 };
 
-enum MatClass : int32_t { MC_DENSE = 0, MC_DIAG = 1, MC_ANTI = 2, MC_MID = 3 };
+// Matrix classes.  DENSE/DIAG/ANTI/MID are used by every kernel; the finer
+// classes only by the register-group ops (elsewhere they run as DENSE):
+// REAL = all entries real (H, RY), RIRI = real diagonal and imaginary
+// off-diagonal (RX), PX / PY = exactly Pauli X / Y (inner-product generators).
+enum MatClass : int32_t { MC_DENSE = 0, MC_DIAG = 1, MC_ANTI = 2, MC_MID = 3, MC_REAL = 4, MC_RIRI = 5, MC_PX = 6,
+                          MC_PY = 7 };
 
 struct TOp {
     int32_t kind, cls, k, slot;
@@ -73,7 +78,8 @@ struct TileArgs {
     int32_t nthr_log2;
     int32_t op0, nops;
     int32_t nslots;
-    int32_t pad;
+    int32_t zt_n;           // phase-table entries copied to LDS at kernel start
+    int64_t zt_off;         // their offset in the coefficient table
 };
 
 struct PauliGroupDev {
@@ -116,7 +122,7 @@ template <typename T> hipError_t launch_pauli(hipStream_t s, bool write_lambda, 
                                               const PauliTermDev* terms, double* partials, int grid);
 hipError_t launch_reduce(hipStream_t s, const double* partials, int n_blocks, int n_slots, double* out);
 
-int tile_lds_bytes(int b, bool two, int elem_bytes, int nslots);
+int tile_lds_bytes(int b, bool two, int elem_bytes, int nslots, int zt_n);
 int pauli_grid(uint64_t N);
 
 // ------------------------------------------------------------------ host gate model (gates.cpp)

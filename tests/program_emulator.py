@@ -12,7 +12,7 @@ import numpy as np
 
 OP_APPLY1, OP_APPLY2, OP_APPLYK, OP_DIAG, OP_ZPHASE, OP_DOT1, OP_DOT2, OP_DOTK, OP_DOTDIAG, OP_DOTZSUM, OP_GROUP = \
     range(1, 12)
-MC_DENSE, MC_DIAG, MC_ANTI, MC_MID = range(4)
+MC_DENSE, MC_DIAG, MC_ANTI, MC_MID, MC_REAL, MC_RIRI, MC_PX, MC_PY = range(8)
 
 
 def _coef(prog, off, cnt):
