@@ -197,6 +197,27 @@ qsv_status qsv_apply(qsv_state *s, const qsv_op *ops, size_t n_ops, const double
  * synchronises the context stream. */
 qsv_status qsv_expval(qsv_state *s, const qsv_pauli_sum *obs, size_t n_obs, double *out);
 
+/* Variance out[o] = <H_o^2> - <H_o>^2 = ||H_o psi||^2 - <H_o>^2 for n_obs Pauli
+ * sums (paper Sec. 2.2 lists variances among the measurements).  Host output;
+ * synchronises the context stream. */
+qsv_status qsv_var(qsv_state *s, const qsv_pauli_sum *obs, size_t n_obs, double *out);
+
+/* <psi|S|psi> for a sparse 2^n x 2^n matrix S in CSR form (paper Sec. 2.2:
+ * SparseHamiltonian observables): row_ptr[2^n + 1] (row_ptr[0] = 0,
+ * row_ptr[2^n] = nnz), col[nnz] column indices, values[2 nnz] complex FP64
+ * interleaved.  out[0], out[1] = real and imaginary part (the latter is zero
+ * up to rounding for Hermitian S).  Host arrays, copied once; validated
+ * (monotone row_ptr, columns in range) before any device work. */
+qsv_status qsv_expval_sparse(qsv_state *s, const int64_t *row_ptr, const int64_t *col, const double *values,
+                             int64_t nnz, double *out);
+
+/* Marginal probabilities of the computational-basis outcomes of n_wires wires
+ * (paper Sec. 2.2: probabilities, e.g. the GHZ listing's three wires).
+ * out[b] for b < 2^n_wires, the first listed wire being the most significant
+ * bit of b.  1 <= n_wires <= min(n, 20), distinct wires.  FP64 sums in a fixed
+ * order.  Host output; synchronises the context stream. */
+qsv_status qsv_probs(qsv_state *s, const int32_t *wires, int n_wires, double *out);
+
 /* Adjoint-method Jacobian (paper Sec. 2.1 and Sec. 3.1.1; Jones & Gacon):
  * jac[o*n_params + p] = d<psi|H_o|psi>/d params[p], where s holds the state
  * AFTER the ops.  The forward states are recomputed by un-applying the gates.

@@ -44,7 +44,7 @@ struct qsv_ctx {
     std::string err;
     int64_t opt_fusion = 1, opt_tile_bits = 0, opt_tile_bits_adj = 0, opt_low_bits = 0, opt_profile = 0,
             opt_nontemporal = 0;
-    DevBuf ops, coef, words, partials, slots, pgroups, pterms, ws0, ws1;
+    DevBuf ops, coef, words, partials, slots, pgroups, pterms, ws0, ws1, binbits, csr_ptr, csr_col, csr_val;
     void* pin = nullptr;
     size_t pin_bytes = 0;
     hipEvent_t pin_ev = nullptr;
@@ -845,21 +845,23 @@ void add_pauli(PauliTables& T, const qsv_pauli_sum& h, double scale) {
 }
 
 // expval (or lambda) of observable o into slots[out_slot]
-void run_pauli(qsv_ctx* c, qsv_dtype dt, int n, const PauliTables& T, int o, const void* psi, void* lam, double* slot) {
+// norm2: also ||H psi||^2 into slot[1] (variance), without writing lambda
+void run_pauli(qsv_ctx* c, qsv_dtype dt, int n, const PauliTables& T, int o, const void* psi, void* lam, double* slot,
+               bool norm2 = false) {
     const uint64_t N = 1ull << n;
     const int grid = pauli_grid(N);
     const double eb = (double)elem_bytes(dt);
     const double bytes = (1.0 + T.n_x_groups[o] + (lam ? 1.0 : 0.0)) * (double)N * eb;
-    ensure(c, c->partials, (size_t)grid * 8);
+    ensure(c, c->partials, (size_t)grid * 16);
     const PauliGroupDev* g = (const PauliGroupDev*)c->pgroups.p + T.obs_groups[o].first;
     const PauliTermDev* tm = (const PauliTermDev*)c->pterms.p;
     Timed t(c, lam ? KK_PAULI_LAMBDA : KK_PAULI, bytes);
-    t.done(dt == QSV_C128 ? launch_pauli<double>(c->stream, lam != nullptr, psi, lam, N, g, T.obs_groups[o].second, tm,
-                                                 (double*)c->partials.p, grid)
-                          : launch_pauli<float>(c->stream, lam != nullptr, psi, lam, N, g, T.obs_groups[o].second, tm,
-                                                (double*)c->partials.p, grid));
+    t.done(dt == QSV_C128 ? launch_pauli<double>(c->stream, lam != nullptr, norm2, psi, lam, N, g,
+                                                 T.obs_groups[o].second, tm, (double*)c->partials.p, grid)
+                          : launch_pauli<float>(c->stream, lam != nullptr, norm2, psi, lam, N, g,
+                                                T.obs_groups[o].second, tm, (double*)c->partials.p, grid));
     Timed tr(c, KK_REDUCE, 8.0 * grid);
-    tr.done(launch_reduce(c->stream, (const double*)c->partials.p, grid, 1, slot));
+    tr.done(launch_reduce(c->stream, (const double*)c->partials.p, grid, norm2 ? 2 : 1, slot));
 }
 
 void upload_program(qsv_ctx* c, const Program& P, qsv_dtype dt, const PauliTables* T) {
@@ -1057,7 +1059,8 @@ void qsv_ctx_destroy(qsv_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (DevBuf* b : {&c->ops, &c->coef, &c->words, &c->partials, &c->slots, &c->pgroups, &c->pterms, &c->ws0, &c->ws1})
+    for (DevBuf* b : {&c->ops, &c->coef, &c->words, &c->partials, &c->slots, &c->pgroups, &c->pterms, &c->ws0, &c->ws1,
+                      &c->binbits, &c->csr_ptr, &c->csr_col, &c->csr_val})
         release(*b);
     if (c->pin) (void)hipHostFree(c->pin);
     for (auto& r : c->recs) {
@@ -1139,7 +1142,8 @@ qsv_status qsv_ctx_workspace_bytes(qsv_ctx* c, size_t* out) {
     return guard(c, [&] {
         if (!c || !out) fail(QSV_ERR_ARG, "NULL argument");
         size_t t = 0;
-        for (DevBuf* b : {&c->ops, &c->coef, &c->words, &c->partials, &c->slots, &c->pgroups, &c->pterms, &c->ws0, &c->ws1})
+        for (DevBuf* b : {&c->ops, &c->coef, &c->words, &c->partials, &c->slots, &c->pgroups, &c->pterms, &c->ws0, &c->ws1,
+                          &c->binbits, &c->csr_ptr, &c->csr_col, &c->csr_val})
             t += b->bytes;
         *out = t;
     });
@@ -1424,6 +1428,109 @@ qsv_status qsv_expval(qsv_state* s, const qsv_pauli_sum* obs, size_t n_obs, doub
         ensure(c, c->slots, n_obs * 8);
         for (size_t o = 0; o < n_obs; ++o) run_pauli(c, s->dt, s->n, T, (int)o, s->ptr, nullptr, (double*)c->slots.p + o);
         HIPCHK(hipMemcpyAsync(out, c->slots.p, n_obs * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    });
+}
+
+qsv_status qsv_var(qsv_state* s, const qsv_pauli_sum* obs, size_t n_obs, double* out) {
+    qsv_ctx* c = s ? s->ctx : nullptr;
+    return guard(c, [&] {
+        state_ctx(s);
+        validate_obs_impl(s->n, obs, n_obs);
+        if (n_obs && !out) fail(QSV_ERR_ARG, "out is NULL");
+        if (!n_obs) return;
+        set_device(c);
+        PauliTables T;
+        for (size_t o = 0; o < n_obs; ++o) add_pauli(T, obs[o], 1.0);
+        upload(c, {{&c->pgroups, T.groups.data(), T.groups.size() * sizeof(PauliGroupDev)},
+                   {&c->pterms, T.terms.data(), T.terms.size() * sizeof(PauliTermDev)}});
+        ensure(c, c->slots, n_obs * 16);
+        for (size_t o = 0; o < n_obs; ++o)
+            run_pauli(c, s->dt, s->n, T, (int)o, s->ptr, nullptr, (double*)c->slots.p + 2 * o, true);
+        std::vector<double> h(2 * n_obs);
+        HIPCHK(hipMemcpyAsync(h.data(), c->slots.p, h.size() * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (size_t o = 0; o < n_obs; ++o) out[o] = h[2 * o + 1] - h[2 * o] * h[2 * o];
+    });
+}
+
+qsv_status qsv_expval_sparse(qsv_state* s, const int64_t* row_ptr, const int64_t* col, const double* values,
+                             int64_t nnz, double* out) {
+    qsv_ctx* c = s ? s->ctx : nullptr;
+    return guard(c, [&] {
+        state_ctx(s);
+        if (!row_ptr || !out || (nnz && (!col || !values))) fail(QSV_ERR_ARG, "NULL argument");
+        const uint64_t N = 1ull << s->n;
+        if (row_ptr[0] != 0 || row_ptr[N] != nnz || nnz < 0) fail(QSV_ERR_ARG, "row_ptr must run from 0 to nnz");
+        for (uint64_t i = 0; i < N; ++i)
+            if (row_ptr[i + 1] < row_ptr[i]) fail(QSV_ERR_ARG, "row_ptr not monotone");
+        for (int64_t k = 0; k < nnz; ++k)
+            if (col[k] < 0 || (uint64_t)col[k] >= N) fail(QSV_ERR_ARG, "column index out of range");
+        set_device(c);
+        upload(c, {{&c->csr_ptr, row_ptr, (N + 1) * 8}, {&c->csr_col, col, (size_t)nnz * 8},
+                   {&c->csr_val, values, (size_t)nnz * 16}});
+        const int grid = pauli_grid(N);
+        ensure(c, c->partials, (size_t)grid * 16);
+        ensure(c, c->slots, 16);
+        {
+            Timed t(c, KK_SPARSE, (double)(N * elem_bytes(s->dt)) + 24.0 * nnz + 8.0 * (N + 1));
+            t.done(s->dt == QSV_C128
+                       ? launch_sparse<double>(c->stream, s->ptr, N, (const int64_t*)c->csr_ptr.p,
+                                               (const int64_t*)c->csr_col.p, (const double*)c->csr_val.p,
+                                               (double*)c->partials.p, grid)
+                       : launch_sparse<float>(c->stream, s->ptr, N, (const int64_t*)c->csr_ptr.p,
+                                              (const int64_t*)c->csr_col.p, (const double*)c->csr_val.p,
+                                              (double*)c->partials.p, grid));
+        }
+        Timed tr(c, KK_REDUCE, 16.0 * grid);
+        tr.done(launch_reduce(c->stream, (const double*)c->partials.p, grid, 2, (double*)c->slots.p));
+        HIPCHK(hipMemcpyAsync(out, c->slots.p, 16, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    });
+}
+
+qsv_status qsv_probs(qsv_state* s, const int32_t* wires, int n_wires, double* out) {
+    qsv_ctx* c = s ? s->ctx : nullptr;
+    return guard(c, [&] {
+        state_ctx(s);
+        const int n = s->n;
+        if (!wires || !out) fail(QSV_ERR_ARG, "NULL argument");
+        if (n_wires < 1 || n_wires > std::min(n, 20)) fail(QSV_ERR_ARG, "n_wires must be in [1, min(n, 20)]");
+        std::vector<int> pos;
+        for (int j = 0; j < n_wires; ++j) {
+            if (wires[j] < 0 || wires[j] >= n) fail(QSV_ERR_WIRE, "wire out of range");
+            for (int i = 0; i < j; ++i)
+                if (wires[i] == wires[j]) fail(QSV_ERR_WIRE, "repeated wire");
+            pos.push_back(n - 1 - wires[j]);
+        }
+        set_device(c);
+        const int nb = 1 << n_wires;
+        std::vector<uint64_t> bb(nb);
+        for (int b = 0; b < nb; ++b) {
+            uint64_t x = 0;
+            for (int j = 0; j < n_wires; ++j)  // first listed wire = most significant bit of the bin
+                if ((b >> (n_wires - 1 - j)) & 1) x |= 1ull << pos[j];
+            bb[b] = x;
+        }
+        std::vector<int> sorted = pos;
+        std::sort(sorted.begin(), sorted.end());
+        const Expand ex = make_expand(sorted);
+        const uint64_t n_rest = 1ull << (n - n_wires);
+        const int gx = (int)std::max<uint64_t>(1, std::min<uint64_t>((n_rest + 1023) / 1024,
+                                                                    std::max(1, 4096 / nb)));
+        upload(c, {{&c->binbits, bb.data(), bb.size() * 8}});
+        ensure(c, c->partials, (size_t)nb * gx * 8);
+        ensure(c, c->slots, (size_t)nb * 8);
+        {
+            Timed t(c, KK_PROBS, (double)((1ull << n) * elem_bytes(s->dt)));
+            t.done(s->dt == QSV_C128 ? launch_probs<double>(c->stream, s->ptr, n_rest, ex, (const uint64_t*)c->binbits.p,
+                                                            nb, gx, (double*)c->partials.p)
+                                     : launch_probs<float>(c->stream, s->ptr, n_rest, ex, (const uint64_t*)c->binbits.p,
+                                                           nb, gx, (double*)c->partials.p));
+        }
+        Timed tr(c, KK_REDUCE, 8.0 * nb * gx);
+        tr.done(launch_reduce(c->stream, (const double*)c->partials.p, gx, nb, (double*)c->slots.p));
+        HIPCHK(hipMemcpyAsync(out, c->slots.p, (size_t)nb * 8, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
     });
 }

@@ -24,7 +24,7 @@
 namespace qsv {
 
 const char* const kKernelNames[KK_COUNT] = {"init",  "gate1", "diag1",        "gate2",        "gatek", "tile1",
-                                            "tile2", "pauli_expval", "pauli_lambda", "reduce", "copy"};
+                                            "tile2", "pauli_expval", "pauli_lambda", "reduce", "copy",  "probs", "sparse_expval"};
 
 template <typename T>
 struct alignas(2 * sizeof(T)) cx {
@@ -1034,13 +1034,13 @@ hipError_t launch_tile(hipStream_t s, bool two, bool generic, void* phi, void* l
 
 // (P psi)_i = i^{nY} (-1)^{popcount((i ^ x) & z)} psi_{i ^ x}; terms sharing
 // an x mask share the load of psi_{i ^ x}.  Accumulation in FP64.
-template <typename T, bool WRITE>
+template <typename T, bool WRITE, bool NORM2>
 __global__ __launch_bounds__(256) void k_pauli(const cx<T>* __restrict__ psi, cx<T>* __restrict__ lam, uint64_t N,
                                                const PauliGroupDev* __restrict__ groups, int n_groups,
                                                const PauliTermDev* __restrict__ terms,
                                                double* __restrict__ partials) {
     __shared__ double red[64];
-    double dot = 0.0;
+    double dot = 0.0, nrm = 0.0;
     const uint64_t stride = (uint64_t)gridDim.x * 256;
     for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += stride) {
         const cx<T> pi = psi[i];
@@ -1061,10 +1061,16 @@ __global__ __launch_bounds__(256) void k_pauli(const cx<T>* __restrict__ psi, cx
         }
         if (WRITE) lam[i] = cx<T>{(T)ar, (T)ai};
         dot += (double)pi.re * ar + (double)pi.im * ai;
+        if (NORM2) nrm += ar * ar + ai * ai;
     }
     double tot = 0.0;
     block_add(dot, red, &tot, threadIdx.x, 256);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+    if (NORM2) {  // ||H psi||^2 for the variance
+        double t2 = 0.0;
+        block_add(nrm, red, &t2, threadIdx.x, 256);
+        if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = t2;
+    }
 }
 
 int pauli_grid(uint64_t N) {
@@ -1074,15 +1080,94 @@ int pauli_grid(uint64_t N) {
 }
 
 template <typename T>
-hipError_t launch_pauli(hipStream_t s, bool write_lambda, const void* psi, void* lam, uint64_t N,
+hipError_t launch_pauli(hipStream_t s, bool write_lambda, bool norm2, const void* psi, void* lam, uint64_t N,
                         const PauliGroupDev* groups, int n_groups, const PauliTermDev* terms, double* partials,
                         int grid) {
-    if (write_lambda)
-        hipLaunchKernelGGL((k_pauli<T, true>), dim3(grid), dim3(256), 0, s, (const cx<T>*)psi, (cx<T>*)lam, N, groups,
-                           n_groups, terms, partials);
-    else
-        hipLaunchKernelGGL((k_pauli<T, false>), dim3(grid), dim3(256), 0, s, (const cx<T>*)psi, (cx<T>*)lam, N,
+    if (norm2)
+        hipLaunchKernelGGL((k_pauli<T, false, true>), dim3(grid), dim3(256), 0, s, (const cx<T>*)psi, (cx<T>*)lam, N,
                            groups, n_groups, terms, partials);
+    else if (write_lambda)
+        hipLaunchKernelGGL((k_pauli<T, true, false>), dim3(grid), dim3(256), 0, s, (const cx<T>*)psi, (cx<T>*)lam, N,
+                           groups, n_groups, terms, partials);
+    else
+        hipLaunchKernelGGL((k_pauli<T, false, false>), dim3(grid), dim3(256), 0, s, (const cx<T>*)psi, (cx<T>*)lam,
+                           N, groups, n_groups, terms, partials);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ marginal probabilities
+
+// Block (x, y) sums |psi_i|^2 over its share of the indices whose measured
+// wires hold bin (bin0 + y): i = (rest with zeros at the measured bits) | binbits.
+template <typename T>
+__global__ __launch_bounds__(256) void k_probs(const cx<T>* __restrict__ psi, uint64_t n_rest, Expand ex,
+                                               const uint64_t* __restrict__ binbits, int bin0,
+                                               double* __restrict__ partials) {
+    __shared__ double red[64];
+    const int bin = bin0 + (int)blockIdx.y;
+    const uint64_t bb = binbits[bin];
+    double sum = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t r = (uint64_t)blockIdx.x * 256 + threadIdx.x; r < n_rest; r += stride) {
+        const cx<T> a = psi[expand_idx(r, ex) | bb];
+        sum += (double)a.re * a.re + (double)a.im * a.im;
+    }
+    double tot = 0.0;
+    block_add(sum, red, &tot, threadIdx.x, 256);
+    if (threadIdx.x == 0) partials[(uint64_t)bin * gridDim.x + blockIdx.x] = tot;
+}
+
+template <typename T>
+hipError_t launch_probs(hipStream_t s, const void* psi, uint64_t n_rest, const Expand& ex, const uint64_t* binbits,
+                        int n_bins, int gx, double* partials) {
+    for (int b0 = 0; b0 < n_bins; b0 += 32768) {
+        const int nb = n_bins - b0 < 32768 ? n_bins - b0 : 32768;
+        hipLaunchKernelGGL(k_probs<T>, dim3(gx, nb), dim3(256), 0, s, (const cx<T>*)psi, n_rest, ex, binbits, b0,
+                           partials);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------------ sparse Hamiltonian
+
+// <psi|S|psi> for a CSR matrix S (rows = basis indices): one row per thread,
+// FP64 accumulation of conj(psi_i) * sum_j S_ij psi_j; real and imaginary
+// block partials at partials[b] and partials[grid + b].
+template <typename T>
+__global__ __launch_bounds__(256) void k_sparse(const cx<T>* __restrict__ psi, uint64_t N,
+                                                const int64_t* __restrict__ row_ptr,
+                                                const int64_t* __restrict__ col,
+                                                const double* __restrict__ val, double* __restrict__ partials) {
+    __shared__ double red[64];
+    double sr = 0.0, si = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += stride) {
+        double vr = 0.0, vi = 0.0;
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            const cx<T> a = psi[col[k]];
+            const double mr = val[2 * k], mi = val[2 * k + 1];
+            vr += mr * (double)a.re - mi * (double)a.im;
+            vi += mr * (double)a.im + mi * (double)a.re;
+        }
+        const cx<T> p = psi[i];
+        sr += (double)p.re * vr + (double)p.im * vi;
+        si += (double)p.re * vi - (double)p.im * vr;
+    }
+    double tr = 0.0, ti = 0.0;
+    block_add(sr, red, &tr, threadIdx.x, 256);
+    block_add(si, red, &ti, threadIdx.x, 256);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = tr;
+        partials[gridDim.x + blockIdx.x] = ti;
+    }
+}
+
+template <typename T>
+hipError_t launch_sparse(hipStream_t s, const void* psi, uint64_t N, const int64_t* row_ptr, const int64_t* col,
+                         const double* val, double* partials, int grid) {
+    hipLaunchKernelGGL(k_sparse<T>, dim3(grid), dim3(256), 0, s, (const cx<T>*)psi, N, row_ptr, col, val, partials);
     return hipGetLastError();
 }
 
@@ -1118,8 +1203,12 @@ hipError_t launch_reduce(hipStream_t s, const double* partials, int n_blocks, in
                                         const int32_t*, const void*);                                           \
     template hipError_t launch_tile<T>(hipStream_t, bool, bool, void*, void*, const TileArgs&, const TOp*,      \
                                        const void*, const uint64_t*, double*, int, int, int, size_t);           \
-    template hipError_t launch_pauli<T>(hipStream_t, bool, const void*, void*, uint64_t, const PauliGroupDev*,  \
-                                        int, const PauliTermDev*, double*, int);
+    template hipError_t launch_pauli<T>(hipStream_t, bool, bool, const void*, void*, uint64_t,                  \
+                                        const PauliGroupDev*, int, const PauliTermDev*, double*, int);          \
+    template hipError_t launch_probs<T>(hipStream_t, const void*, uint64_t, const Expand&, const uint64_t*, int, \
+                                        int, double*);                                                          \
+    template hipError_t launch_sparse<T>(hipStream_t, const void*, uint64_t, const int64_t*, const int64_t*,    \
+                                         const double*, double*, int);
 
 QSV_INST(double)
 QSV_INST(float)

@@ -95,7 +95,7 @@ struct PauliTermDev {
 
 enum KernelKind : int {
     KK_INIT = 0, KK_GATE1, KK_DIAG1, KK_GATE2, KK_GATEK, KK_TILE1, KK_TILE2,
-    KK_PAULI, KK_PAULI_LAMBDA, KK_REDUCE, KK_COPY, KK_COUNT
+    KK_PAULI, KK_PAULI_LAMBDA, KK_REDUCE, KK_COPY, KK_PROBS, KK_SPARSE, KK_COUNT
 };
 extern const char* const kKernelNames[KK_COUNT];
 
@@ -117,9 +117,13 @@ template <typename T> hipError_t launch_gatek(hipStream_t s, void* psi, uint64_t
 template <typename T> hipError_t launch_tile(hipStream_t s, bool two, bool generic, void* phi, void* lam, const TileArgs& a,
                                              const TOp* ops, const void* coef, const uint64_t* words,
                                              double* partials, int grid, int nthr, int R, size_t lds_bytes);
-template <typename T> hipError_t launch_pauli(hipStream_t s, bool write_lambda, const void* psi, void* lam,
-                                              uint64_t N, const PauliGroupDev* groups, int n_groups,
+template <typename T> hipError_t launch_pauli(hipStream_t s, bool write_lambda, bool norm2, const void* psi,
+                                              void* lam, uint64_t N, const PauliGroupDev* groups, int n_groups,
                                               const PauliTermDev* terms, double* partials, int grid);
+template <typename T> hipError_t launch_sparse(hipStream_t s, const void* psi, uint64_t N, const int64_t* row_ptr,
+                                               const int64_t* col, const double* val, double* partials, int grid);
+template <typename T> hipError_t launch_probs(hipStream_t s, const void* psi, uint64_t n_rest, const Expand& ex,
+                                              const uint64_t* binbits, int n_bins, int gx, double* partials);
 hipError_t launch_reduce(hipStream_t s, const double* partials, int n_blocks, int n_slots, double* out);
 
 int tile_lds_bytes(int b, bool two, int elem_bytes, int nslots, int zt_n);

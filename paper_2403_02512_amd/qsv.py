@@ -78,7 +78,8 @@ EXPORTS = [
     "qsv_kernel_name", "qsv_ctx_kernel_stats", "qsv_ctx_reset_stats", "qsv_state_create", "qsv_state_wrap",
     "qsv_state_destroy", "qsv_state_n_qubits", "qsv_state_device_ptr", "qsv_state_reset", "qsv_state_copy",
     "qsv_state_to_host", "qsv_state_from_host", "qsv_validate_ops", "qsv_validate_obs", "qsv_apply",
-    "qsv_expval", "qsv_adjoint_jacobian", "qsv_adjoint_vjp", "qsv_plan_stats", "qsv_plan_json",
+    "qsv_expval", "qsv_adjoint_jacobian", "qsv_adjoint_vjp", "qsv_plan_stats", "qsv_plan_json", "qsv_var",
+    "qsv_probs", "qsv_expval_sparse",
 ]
 
 
@@ -113,6 +114,9 @@ def lib():
         "qsv_validate_ops": ([i32, opp, sz, sz, sz], i32), "qsv_validate_obs": ([i32, obp, sz], i32),
         "qsv_apply": ([vp, opp, sz, dp, sz, dp, sz], i32),
         "qsv_expval": ([vp, obp, sz, dp], i32),
+        "qsv_var": ([vp, obp, sz, dp], i32),
+        "qsv_probs": ([vp, ctypes.POINTER(ctypes.c_int32), i32, dp], i32),
+        "qsv_expval_sparse": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64), dp, i64, dp], i32),
         "qsv_adjoint_jacobian": ([vp, opp, sz, dp, sz, dp, sz, obp, sz, dp, dp, u32], i32),
         "qsv_adjoint_vjp": ([vp, opp, sz, dp, sz, dp, sz, obp, sz, dp, dp, dp, u32], i32),
         "qsv_plan_stats": ([i32, i32, opp, sz, dp, sz, dp, sz, i32, i32, i32, i32, ctypes.POINTER(i64),
@@ -398,6 +402,37 @@ def expval(state: State, observables, marshalled: Optional[MarshalledObs] = None
     out = np.zeros(max(1, mo.n))
     _check(lib().qsv_expval(state.h, mo.arr, mo.n, _dptr(out)), state.ctx.h)
     return out[: mo.n]
+
+
+def var(state: State, observables, marshalled: Optional[MarshalledObs] = None) -> np.ndarray:
+    mo = marshalled or MarshalledObs(observables)
+    out = np.zeros(max(1, mo.n))
+    _check(lib().qsv_var(state.h, mo.arr, mo.n, _dptr(out)), state.ctx.h)
+    return out[: mo.n]
+
+
+def expval_sparse(state: State, matrix) -> complex:
+    """<psi|S|psi> for a scipy.sparse matrix S (converted to CSR, complex128)."""
+    import scipy.sparse as sp
+    m = sp.csr_matrix(matrix, dtype=np.complex128)
+    m.sort_indices()
+    rp = np.ascontiguousarray(m.indptr, dtype=np.int64)
+    ci = np.ascontiguousarray(m.indices, dtype=np.int64)
+    va = np.ascontiguousarray(m.data, dtype=np.complex128).view(np.float64)
+    out = np.zeros(2)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    _check(lib().qsv_expval_sparse(state.h, rp.ctypes.data_as(i64p), ci.ctypes.data_as(i64p), _dptr(va), m.nnz,
+                                   _dptr(out)), state.ctx.h)
+    return complex(out[0], out[1])
+
+
+def probs(state: State, wires: Sequence[int]) -> np.ndarray:
+    """Marginal probabilities of the listed wires (first wire = msb)."""
+    w = np.ascontiguousarray(wires, dtype=np.int32)
+    out = np.zeros(1 << len(w))
+    _check(lib().qsv_probs(state.h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(w), _dptr(out)),
+           state.ctx.h)
+    return out
 
 
 def adjoint_jacobian(state: State, ops, params, observables, inplace: bool = False,

@@ -142,6 +142,10 @@ def test_mirror_and_ghz_full_size(ctx, n, dt):
     want = [1.0, 1.0, math.cos(n * math.pi / 2)]
     _report("ghz", n=n, err=float(np.max(np.abs(ev - want))))
     assert np.max(np.abs(ev - want)) <= tol
+    # Listing 3: probabilities on wires [0, n//2, n-1] of the GHZ state
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "ghz_probs_listing3.txt")) if not l.startswith("#")]
+    p = qsv.probs(st, [0, n // 2, n - 1])
+    assert np.max(np.abs(p - np.array([float(r[1]) for r in rows]))) <= tol
     st.close()
 
 

@@ -247,3 +247,64 @@ def test_invalid_call_leaves_state_untouched(ctx):
     with pytest.raises(qsv.QsvError):
         qsv.apply(st, [W.op("RX", [0], (3, 1.0))], [0.3])
     np.testing.assert_array_equal(st.to_numpy(), before)
+
+
+# ------------------------------------------------------------------ probabilities and variance
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_marginal_probabilities(ctx, dt):
+    n = 11
+    psi = W.random_state(n, 21)
+    st = qsv.State(ctx, n, dt)
+    st.from_numpy(psi)
+    p = (np.abs(psi.astype(np.complex64).astype(np.complex128) if dt == qsv.C64 else psi) ** 2).reshape([2] * n)
+    for wires in ([0], [n - 1], [3, 7], [n - 1, 0, 5], list(range(n)), [9, 1, 4, 2, 10, 0]):
+        rest = tuple(w for w in range(n) if w not in wires)
+        want = np.transpose(p.sum(axis=rest), np.argsort(np.argsort(wires))).reshape(-1) if rest else \
+            np.transpose(p, wires).reshape(-1)
+        if rest:
+            kept = sorted(wires)
+            want = np.transpose(p.sum(axis=rest), [kept.index(w) for w in wires]).reshape(-1)
+        got = qsv.probs(st, wires)
+        assert np.max(np.abs(got - want)) <= TOL[dt], wires
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_variance(ctx, dt):
+    n = 9
+    psi = W.random_state(n, 5)
+    obs = W.random_observables(n, np.random.default_rng(4), n_obs=3, n_terms=6)
+    st = qsv.State(ctx, n, dt)
+    st.from_numpy(psi)
+    ref_psi = psi.astype(np.complex64).astype(np.complex128) if dt == qsv.C64 else psi
+    want = []
+    for o in obs:
+        lam = oracle.apply_pauli_sum(ref_psi, o)
+        want.append(np.vdot(lam, lam).real - oracle.expval(ref_psi, [o])[0] ** 2)
+    got = qsv.var(st, obs)
+    assert np.all(np.abs(got - np.array(want)) <= TOL[dt] * obs_scale(obs) ** 2)
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_sparse_hamiltonian_expval(ctx, dt):
+    """CSR observable: the Pauli sum's dense matrix in sparse form, and a
+    random Hermitian sparse matrix, against plain numpy on the same state."""
+    import scipy.sparse as sp
+    from tests import dense_ref as D
+    n = 8
+    psi = W.random_state(n, 8)
+    st = qsv.State(ctx, n, dt)
+    st.from_numpy(psi)
+    ref_psi = psi.astype(np.complex64).astype(np.complex128) if dt == qsv.C64 else psi
+    obs = W.random_observables(n, np.random.default_rng(3), n_obs=1, n_terms=5)[0]
+    H = sp.csr_matrix(D.pauli_sum_matrix(obs))
+    got = qsv.expval_sparse(st, H)
+    assert abs(got.real - oracle.expval(ref_psi, [obs])[0]) <= TOL[dt] * np.sum(np.abs(obs.coeffs))
+    rng = np.random.default_rng(1)
+    A = sp.random(1 << n, 1 << n, density=0.02, random_state=2) + 1j * sp.random(1 << n, 1 << n, density=0.02,
+                                                                                  random_state=3)
+    S = (A + A.conj().T).tocsr()
+    got = qsv.expval_sparse(st, S)
+    want = np.vdot(ref_psi, S @ ref_psi)
+    scale = abs(S).sum(axis=1).max()
+    assert abs(got - want) <= TOL[dt] * scale * 10
