@@ -137,6 +137,69 @@ def micro(n: int, reps: int = 5, dtype_name: str = "c128"):
           flush=True)
 
 
+def batch_bench(args):
+    """Batched VQE sweep: every circuit's <H> and full adjoint gradient, new
+    random angles each step.  Three executions of the same work: a loop over
+    circuits through the single-state entry points, batched launches, and the
+    batched launches replayed from a captured HIP graph."""
+    import torch
+    from paper_2403_02512_amd import qsv
+    from paper_2403_02512_amd import workloads as W
+    ctx = qsv.Context(0)
+    cs = W.config4(n_circuits=args.batch_circuits)
+    rng = np.random.default_rng(7)
+    sets = [[rng.uniform(0, 2 * np.pi, c.n_params) for c in cs] for _ in range(args.warmup + args.steps)]
+    states = {}
+    for c in cs:
+        if c.n_qubits not in states:
+            states[c.n_qubits] = qsv.State(ctx, c.n_qubits)
+    marsh = [(qsv.MarshalledOps(c.ops, c.params), qsv.MarshalledObs(c.observables[:1])) for c in cs]
+
+    def loop(params):
+        ev = np.zeros(len(cs))
+        for i, c in enumerate(cs):
+            st = states[c.n_qubits]
+            st.reset(0)
+            m = marsh[i][0]
+            m.params[:c.n_params] = params[i]
+            qsv.apply(st, c.ops, marshalled=m)
+            _, e = qsv.adjoint_jacobian(st, c.ops, None, None, inplace=True, marshalled=m,
+                                        marshalled_obs=marsh[i][1])
+            ev[i] = e[0]
+        return ev
+
+    b = qsv.Batch(ctx, cs)
+    results = {}
+    for mode in ("loop", "batch", "graph"):
+        for w in range(args.warmup):
+            (loop(sets[w]) if mode == "loop" else b.run(sets[w], graph=(mode == "graph")))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            p = sets[args.warmup + k]
+            ev = loop(p) if mode == "loop" else b.run(p, graph=(mode == "graph"))[0]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        results[mode] = (dt, ev)
+    ev_loop = results["loop"][1]
+    for mode in ("batch", "graph"):
+        assert np.allclose(results[mode][1], ev_loop, atol=1e-10), mode
+    n_grad = sum(c.n_params for c in cs)
+    widths = [c.n_qubits for c in cs]
+    for mode, (dt, _) in results.items():
+        print(json.dumps({
+            "metric": "batched VQE sweep throughput", "value": round(len(cs) / dt, 2), "unit": "circuits/s",
+            "gradients_per_s": round(len(cs) / dt, 2), "grad_entries_per_s": round(n_grad / dt, 1),
+            "ms_per_step": round(1e3 * dt, 3), "mode": mode, "steps": args.steps, "warmup": args.warmup,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"{len(cs)} VQE-like circuits (RY + Givens layers x6), {min(widths)}-"
+                                   f"{max(widths)} qubits, 200-term Pauli Hamiltonians, complex128: <H> and "
+                                   f"adjoint gradient per circuit", "n_params_total": n_grad},
+            "speedup_vs_loop": round(results["loop"][0] / dt, 2)}), flush=True)
+    b.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,12 +213,19 @@ def main():
     ap.add_argument("--low-bits", type=int, default=0, help="coalescing low bits per tile (0: default)")
     ap.add_argument("--micro", action="store_true", help="per-kernel-class gate-apply bandwidth sweep")
     ap.add_argument("--micro-dtype", default="c128", choices=["c128", "c64"])
+    ap.add_argument("--batch", action="store_true",
+                    help="batched VQE sweep (512 circuits, 12-22 qubits): per-circuit loop vs batched launches "
+                         "vs captured graph, circuits/s and gradients/s")
+    ap.add_argument("--batch-circuits", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU state-vector "
               f"sharding is a design note, not part of this build", file=sys.stderr)
         sys.exit(2)
 
+    if args.batch:
+        batch_bench(args)
+        return
     if args.micro:
         micro(args.n, dtype_name=args.micro_dtype)
         return

@@ -239,6 +239,32 @@ qsv_status qsv_adjoint_vjp(qsv_state *s, const qsv_op *ops, size_t n_ops, const 
                            const qsv_pauli_sum *obs, size_t n_obs, const double *cotangent,
                            double *grad, double *expval, uint32_t flags);
 
+/* ---------------------------------------------------------------- batched circuits */
+/* A batch of independent circuits of possibly different widths (paper Sec.
+ * 4.1-4.2: batched task execution of many circuits and observables).
+ * Circuit i has n_qubits[i] qubits, the ops ops[op_offsets[i] ..
+ * op_offsets[i+1]) (op_offsets has n_circuits + 1 entries), n_params[i]
+ * parameters, one Pauli-sum observable obs[i], and shares the matrices array
+ * (for QubitUnitary ops).  Host arrays are copied; the batch owns one pooled
+ * device allocation holding every circuit's state and adjoint workspace
+ * (3 x 2^n amplitudes each).  Released by qsv_batch_destroy. */
+typedef struct qsv_batch qsv_batch;
+qsv_status qsv_batch_create(qsv_ctx *ctx, qsv_dtype dtype, size_t n_circuits, const int32_t *n_qubits,
+                            const qsv_op *ops, const size_t *op_offsets, const size_t *n_params,
+                            const double *matrices, size_t n_matrix_elems, const qsv_pauli_sum *obs,
+                            qsv_batch **out);
+void qsv_batch_destroy(qsv_batch *b);
+
+/* Run every circuit from |0..0> with params (concatenated in circuit order):
+ * expval[i] = <H_i>; if grad != NULL also the adjoint gradient of each
+ * circuit, concatenated like params.  Pass s of every circuit runs in one
+ * launch.  QSV_BATCH_GRAPH: capture the launch sequence in a HIP graph on the
+ * first call and replay it while the batch's gate structure is unchanged (new
+ * parameter values only update the uploaded coefficient table).  Host
+ * outputs; synchronises the context stream. */
+#define QSV_BATCH_GRAPH 1u
+qsv_status qsv_batch_run(qsv_batch *b, const double *params, double *expval, double *grad, uint32_t flags);
+
 #ifdef __cplusplus
 }
 #endif

@@ -440,7 +440,12 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
                 while (e < order.size() && pr.z.size() < 64) {
                     const Item& jt = items[order[e]];
                     const Factor& g = F[jt.f];
-                    if (!(!jt.dot && !jt.xbits && g.zrot && (dagger ? -g.zangle : g.zangle) == pr.angle)) break;
+                    // merge rotations with the same symbolic angle (parameter
+                    // and scale), or equal constant angles: the grouping does
+                    // not depend on the parameter values
+                    const bool same = f.zparam >= 0 ? (g.zparam == f.zparam && g.zscale == f.zscale)
+                                                    : (g.zparam < 0 && g.zangle == f.zangle);
+                    if (!(!jt.dot && !jt.xbits && g.zrot && same)) break;
                     pr.z.push_back(zmask_of(g));
                     ++e;
                 }
@@ -721,12 +726,12 @@ PlanOptions plan_opts(qsv_ctx* c, qsv_dtype dt, bool two) {
 }
 
 Program build_program(const PlanOptions& po, const std::vector<Factor>& F, const std::vector<Item>& items, int n,
-                      qsv_dtype dt, bool two, bool dagger) {
+                      qsv_dtype dt, bool two, bool dagger, bool allow_streaming = true) {
     Program P;
     const size_t eb = elem_bytes(dt);
     std::vector<Pass> passes = plan_passes(items, n, po);
     for (const Pass& p : passes) {
-        if (!two && p.items.size() == 1 && !items[p.items[0]].dot) {
+        if (allow_streaming && !two && p.items.size() == 1 && !items[p.items[0]].dot) {
             if (lower_single(P, F[items[p.items[0]].f], n, eb)) continue;
         }
         lower_tile(P, F, items, p, n, two, dagger, eb);
@@ -1577,6 +1582,452 @@ qsv_status qsv_adjoint_vjp(qsv_state* s, const qsv_op* ops, size_t n_ops, const 
         std::vector<double> g(std::max<size_t>(n_params, 1));
         adjoint_impl(s, ops, n_ops, params, n_params, matrices, rows, sc, true, g.data(), expval, flags);
         if (n_params) std::memcpy(grad, g.data(), n_params * 8);
+    });
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batched circuits
+//
+// Many independent circuits of uneven width (paper Sec. 4.1 and 4.2: batches
+// of circuits and observables distributed as tasks) run as one sequence of
+// batched launches: launch s carries pass s of every circuit that has one,
+// each block serving one (circuit, pass) entry.  States live in one pooled
+// allocation; the first forward pass synthesises |0..0> instead of reading a
+// reset state, and the first adjoint pass reads the post-circuit state and
+// writes phi, so no copy pass is needed.  All tables (ops, coefficients,
+// entries) travel in one host->device copy; with QSV_BATCH_GRAPH the whole
+// sequence is captured once in a HIP graph and replayed for new parameters.
+
+struct qsv_batch {
+    qsv_ctx* ctx = nullptr;
+    qsv_dtype dt = QSV_C128;
+    std::vector<int> n;
+    std::vector<std::vector<qsv_op>> ops;
+    std::vector<size_t> n_params, p_off;
+    std::vector<double> matrices;
+    size_t n_mat = 0;
+    std::vector<std::vector<double>> ocoef;
+    std::vector<std::vector<uint64_t>> ox, oz;
+    DevBuf pool, tables, partials, results;
+    std::vector<size_t> off_psi, off_phi, off_lam;
+    void* stage_in = nullptr;
+    size_t stage_in_bytes = 0;
+    void* stage_out = nullptr;
+    size_t stage_out_bytes = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t graph_key = 0;
+    bool graph_grad = false;
+};
+
+namespace {
+
+uint64_t fnv(uint64_t h, const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    return h;
+}
+
+struct BatchLaunch {
+    enum { TILE, PAULI, REDUCE } kind;
+    bool two = false, generic = false;
+    int R = 1, nthr = 256, blocks = 0;
+    size_t lds = 0;
+    size_t entries_off = 0, blk_off = 0;  // byte offsets in the table buffer
+    int n_entries = 0;
+    double bytes = 0;
+};
+
+struct BatchPlan {
+    std::vector<char> tab;           // the device table image
+    size_t off_tops = 0, off_coef = 0, off_words = 0, off_args = 0, off_pg = 0, off_pt = 0, off_re = 0;
+    int n_reduce = 0;
+    std::vector<BatchLaunch> launches;
+    size_t n_partials = 0, n_results = 0;
+    std::vector<std::vector<std::pair<int, double>>> slot_param;  // per circuit
+    std::vector<size_t> slot_base;                                // per circuit, in results
+    uint64_t key = 0;                                             // structure hash (all but coefficients)
+};
+
+template <typename V>
+size_t append_bytes(std::vector<char>& tab, const std::vector<V>& v) {
+    const size_t off = (tab.size() + 255) & ~(size_t)255;
+    tab.resize(off + v.size() * sizeof(V));
+    if (!v.empty()) std::memcpy(tab.data() + off, v.data(), v.size() * sizeof(V));
+    return off;
+}
+
+BatchPlan plan_batch(qsv_batch* B, const double* params, bool grad) {
+    BatchPlan bp;
+    qsv_ctx* c = B->ctx;
+    const size_t nc = B->n.size();
+    const size_t eb = elem_bytes(B->dt);
+    std::vector<TOp> tops;
+    std::vector<cd> coef;
+    std::vector<uint64_t> words;
+    std::vector<TileArgs> args;
+    struct StepRef {
+        int args_idx, grid, R, nthr, nslots, slot_base;
+        size_t lds;
+        bool generic;
+        double bytes;
+        int64_t part_off;
+    };
+    std::vector<std::vector<StepRef>> fwd(nc), adj(nc);
+    size_t n_part = 0;
+    bp.slot_param.resize(nc);
+    bp.slot_base.resize(nc);
+    size_t n_res = nc;  // expvals first
+    auto append_program = [&](Program& P, std::vector<StepRef>& out, bool synth_first) {
+        const size_t tb = tops.size(), cb = coef.size(), wb = words.size();
+        for (TOp op : P.tops) {
+            op.coff += (int64_t)cb;
+            op.woff += (int64_t)wb;
+            tops.push_back(op);
+        }
+        coef.insert(coef.end(), P.coef.begin(), P.coef.end());
+        words.insert(words.end(), P.words.begin(), P.words.end());
+        for (size_t i = 0; i < P.steps.size(); ++i) {
+            const Step& st = P.steps[i];
+            TileArgs a = st.ta;
+            a.op0 += (int)tb;
+            a.zt_off += (int64_t)cb;
+            if (synth_first && i == 0) {
+                a.flags |= TILE_SYNTH;
+                a.basis = 0;
+            }
+            StepRef r{(int)args.size(), st.grid, st.R, st.nthr, st.nslots, st.slot_base, st.lds, st.generic,
+                      st.bytes, (int64_t)n_part};
+            n_part += (size_t)st.nslots * st.grid;
+            args.push_back(a);
+            out.push_back(r);
+        }
+    };
+    for (size_t ci = 0; ci < nc; ++ci) {
+        const int n = B->n[ci];
+        const double* pp = params + B->p_off[ci];
+        const auto& ops = B->ops[ci];
+        std::vector<Factor> F = forward_factors(ops.data(), ops.size(), pp, B->matrices.data(), false);
+        std::vector<Item> it = forward_items(F, n);
+        PlanOptions po = plan_opts(c, B->dt, false);
+        Program P = build_program(po, F, it, n, B->dt, false, false, false);
+        if (P.steps.empty()) {  // no gates: one empty pass that writes |0..0>
+            Pass p;
+            const int b = std::min(po.b, n);
+            p.S = (b >= 64 ? ~0ull : ((1ull << b) - 1));
+            lower_tile(P, F, it, p, n, false, false, eb);
+        }
+        append_program(P, fwd[ci], true);
+        if (grad && B->n_params[ci]) {
+            std::vector<Factor> Fa = forward_factors(ops.data(), ops.size(), pp, B->matrices.data(), true);
+            std::vector<Item> ia = adjoint_items(Fa, n);
+            Program Pa = build_program(plan_opts(c, B->dt, true), Fa, ia, n, B->dt, true, true, false);
+            bp.slot_param[ci] = Pa.slot_param;
+            bp.slot_base[ci] = n_res;
+            n_res += Pa.slot_param.size();
+            append_program(Pa, adj[ci], false);
+        }
+    }
+    // Pauli tables (one observable per circuit)
+    PauliTables T;
+    for (size_t ci = 0; ci < nc; ++ci) {
+        qsv_pauli_sum h{(int64_t)B->ocoef[ci].size(), B->ocoef[ci].data(), B->ox[ci].data(), B->oz[ci].data()};
+        add_pauli(T, h, 1.0);
+    }
+    std::vector<char>& tab = bp.tab;
+    std::vector<char> coef_b = coef_bytes(coef, B->dt);
+    bp.off_tops = append_bytes(tab, tops);
+    bp.off_coef = append_bytes(tab, coef_b);
+    bp.off_words = append_bytes(tab, words);
+    bp.off_args = append_bytes(tab, args);
+    bp.off_pg = append_bytes(tab, T.groups);
+    bp.off_pt = append_bytes(tab, T.terms);
+    const uintptr_t pool = (uintptr_t)B->pool.p;
+    std::vector<ReduceEntry> reds;
+    auto tile_launches = [&](std::vector<std::vector<StepRef>>& steps, bool two) {
+        size_t max_steps = 0;
+        for (auto& v : steps) max_steps = std::max(max_steps, v.size());
+        for (size_t si = 0; si < max_steps; ++si) {
+            // group the circuits' si-th passes by kernel variant
+            std::map<std::tuple<int, int, bool>, std::vector<size_t>> groups;
+            for (size_t ci = 0; ci < nc; ++ci)
+                if (si < steps[ci].size()) {
+                    const StepRef& r = steps[ci][si];
+                    groups[{r.R, r.nthr, r.generic}].push_back(ci);
+                }
+            for (auto& kv : groups) {
+                BatchLaunch L;
+                L.kind = BatchLaunch::TILE;
+                L.two = two;
+                L.R = std::get<0>(kv.first);
+                L.nthr = std::get<1>(kv.first);
+                L.generic = std::get<2>(kv.first);
+                std::vector<TileEntry> ents;
+                std::vector<int32_t> blk;
+                for (size_t ci : kv.second) {
+                    const StepRef& r = steps[ci][si];
+                    TileEntry e;
+                    std::memset(&e, 0, sizeof e);
+                    void* psi = (void*)(pool + B->off_psi[ci]);
+                    if (two) {
+                        e.phi_src = si == 0 ? psi : (void*)(pool + B->off_phi[ci]);
+                        e.phi = (void*)(pool + B->off_phi[ci]);
+                        e.lam = (void*)(pool + B->off_lam[ci]);
+                    } else {
+                        e.phi_src = psi;
+                        e.phi = psi;
+                        e.lam = nullptr;
+                    }
+                    e.part_off = r.part_off;
+                    e.args = r.args_idx;
+                    e.blk0 = (int32_t)blk.size();
+                    e.nblk = r.grid;
+                    for (int b = 0; b < r.grid; ++b) blk.push_back((int32_t)ents.size());
+                    ents.push_back(e);
+                    L.lds = std::max(L.lds, r.lds);
+                    L.bytes += r.bytes;
+                    // slot sums: result index = circuit's slot base + step's first slot + local slot
+                    for (int sl = 0; sl < r.nslots; ++sl)
+                        reds.push_back({r.part_off + (int64_t)sl * r.grid, r.grid,
+                                        (int32_t)(bp.slot_base[ci] + (size_t)(r.slot_base + sl))});
+                }
+                L.blocks = (int)blk.size();
+                L.n_entries = (int)ents.size();
+                L.entries_off = append_bytes(tab, ents);
+                L.blk_off = append_bytes(tab, blk);
+                bp.launches.push_back(L);
+            }
+        }
+    };
+    tile_launches(fwd, false);
+    // <H> (and lambda = H psi when differentiating), one entry per circuit
+    {
+        BatchLaunch L;
+        L.kind = BatchLaunch::PAULI;
+        L.two = grad;
+        std::vector<PauliEntry> ents;
+        std::vector<int32_t> blk;
+        for (size_t ci = 0; ci < nc; ++ci) {
+            const uint64_t N = 1ull << B->n[ci];
+            PauliEntry e;
+            std::memset(&e, 0, sizeof e);
+            e.psi = (void*)(pool + B->off_psi[ci]);
+            e.lam = grad ? (void*)(pool + B->off_lam[ci]) : nullptr;
+            e.N = N;
+            e.g0 = T.obs_groups[ci].first;
+            e.ng = T.obs_groups[ci].second;
+            e.nblk = std::max(1, std::min(pauli_grid(N), 256));
+            e.blk0 = (int32_t)blk.size();
+            e.part_off = (int64_t)n_part;
+            reds.push_back({(int64_t)n_part, e.nblk, (int32_t)ci});
+            n_part += (size_t)e.nblk;
+            for (int b = 0; b < e.nblk; ++b) blk.push_back((int32_t)ents.size());
+            ents.push_back(e);
+            L.bytes += (1.0 + T.n_x_groups[ci] + (grad ? 1.0 : 0.0)) * (double)N * eb;
+        }
+        L.blocks = (int)blk.size();
+        L.n_entries = (int)ents.size();
+        L.entries_off = append_bytes(tab, ents);
+        L.blk_off = append_bytes(tab, blk);
+        bp.launches.push_back(L);
+    }
+    if (grad) tile_launches(adj, true);
+    bp.n_reduce = (int)reds.size();
+    bp.off_re = append_bytes(tab, reds);
+    bp.n_partials = std::max<size_t>(n_part, 1);
+    bp.n_results = n_res;
+    // structure key: everything but the coefficient values
+    uint64_t h = 1469598103934665603ull;
+    h = fnv(h, tab.data(), bp.off_coef);
+    h = fnv(h, tab.data() + bp.off_words, tab.size() - bp.off_words);
+    h = fnv(h, &grad, sizeof grad);
+    bp.key = h;
+    return bp;
+}
+
+void pin_grow(void** p, size_t* have, size_t want) {
+    if (*have >= want) return;
+    if (*p) HIPCHK(hipHostFree(*p));
+    *p = nullptr;
+    *have = 0;
+    if (hipHostMalloc(p, want, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(QSV_ERR_OOM, "pinned host allocation failed");
+    }
+    *have = want;
+}
+
+// Enqueue the whole batch on the context stream (uploads, launches, download).
+void enqueue_batch(qsv_batch* B, const BatchPlan& bp) {
+    qsv_ctx* c = B->ctx;
+    hipStream_t st = c->stream;
+    HIPCHK(hipMemcpyAsync(B->tables.p, B->stage_in, bp.tab.size(), hipMemcpyHostToDevice, st));
+    const char* T = (const char*)B->tables.p;
+    const bool c128 = B->dt == QSV_C128;
+    double* part = (double*)B->partials.p;
+    for (const BatchLaunch& L : bp.launches) {
+        hipError_t e = hipSuccess;
+        if (L.kind == BatchLaunch::TILE) {
+            Timed t(c, L.two ? KK_TILE2 : KK_TILE1, L.bytes);
+            e = c128 ? launch_tile_batch<double>(st, L.two, L.generic, (const TileEntry*)(T + L.entries_off),
+                                                 (const int32_t*)(T + L.blk_off), (const TileArgs*)(T + bp.off_args),
+                                                 (const TOp*)(T + bp.off_tops), T + bp.off_coef,
+                                                 (const uint64_t*)(T + bp.off_words), part, L.blocks, L.nthr, L.R,
+                                                 L.lds)
+                     : launch_tile_batch<float>(st, L.two, L.generic, (const TileEntry*)(T + L.entries_off),
+                                                (const int32_t*)(T + L.blk_off), (const TileArgs*)(T + bp.off_args),
+                                                (const TOp*)(T + bp.off_tops), T + bp.off_coef,
+                                                (const uint64_t*)(T + bp.off_words), part, L.blocks, L.nthr, L.R,
+                                                L.lds);
+            t.done(e);
+        } else {
+            Timed t(c, L.two ? KK_PAULI_LAMBDA : KK_PAULI, L.bytes);
+            e = c128 ? launch_pauli_batch<double>(st, L.two, (const PauliEntry*)(T + L.entries_off),
+                                                  (const int32_t*)(T + L.blk_off),
+                                                  (const PauliGroupDev*)(T + bp.off_pg),
+                                                  (const PauliTermDev*)(T + bp.off_pt), part, L.blocks)
+                     : launch_pauli_batch<float>(st, L.two, (const PauliEntry*)(T + L.entries_off),
+                                                 (const int32_t*)(T + L.blk_off),
+                                                 (const PauliGroupDev*)(T + bp.off_pg),
+                                                 (const PauliTermDev*)(T + bp.off_pt), part, L.blocks);
+            t.done(e);
+        }
+    }
+    {
+        Timed t(c, KK_REDUCE, 8.0 * bp.n_partials);
+        t.done(launch_reduce_batch(st, (const ReduceEntry*)(T + bp.off_re), bp.n_reduce, part,
+                                   (double*)B->results.p));
+    }
+    HIPCHK(hipMemcpyAsync(B->stage_out, B->results.p, bp.n_results * 8, hipMemcpyDeviceToHost, st));
+}
+
+}  // namespace
+
+extern "C" {
+
+qsv_status qsv_batch_create(qsv_ctx* c, qsv_dtype dt, size_t n_circuits, const int32_t* n_qubits, const qsv_op* ops,
+                            const size_t* op_offsets, const size_t* n_params, const double* matrices,
+                            size_t n_matrix_elems, const qsv_pauli_sum* obs, qsv_batch** out) {
+    return guard(c, [&] {
+        if (!c || !out || !n_qubits || !op_offsets || !n_params || !obs) fail(QSV_ERR_ARG, "NULL argument");
+        *out = nullptr;
+        if (dt != QSV_C64 && dt != QSV_C128) fail(QSV_ERR_DTYPE, "unknown dtype");
+        if (n_circuits == 0) fail(QSV_ERR_ARG, "empty batch");
+        static const double dummy = 0.0;
+        std::unique_ptr<qsv_batch> B(new qsv_batch);
+        B->ctx = c;
+        B->dt = dt;
+        size_t poff = 0, soff = 0;
+        const size_t eb = elem_bytes(dt);
+        for (size_t i = 0; i < n_circuits; ++i) {
+            const int n = n_qubits[i];
+            if (n < 1 || n > QSV_MAX_QUBITS) fail(QSV_ERR_ARG, "n_qubits out of range (circuit " + std::to_string(i) + ")");
+            if (op_offsets[i + 1] < op_offsets[i]) fail(QSV_ERR_ARG, "op_offsets not monotone");
+            const size_t no = op_offsets[i + 1] - op_offsets[i];
+            validate_ops_impl(n, ops + op_offsets[i], no, n_params[i], n_matrix_elems, &dummy,
+                              matrices ? matrices : &dummy);
+            validate_obs_impl(n, &obs[i], 1);
+            B->n.push_back(n);
+            B->ops.emplace_back(ops + op_offsets[i], ops + op_offsets[i + 1]);
+            B->n_params.push_back(n_params[i]);
+            B->p_off.push_back(poff);
+            poff += n_params[i];
+            B->ocoef.emplace_back(obs[i].coeff, obs[i].coeff + obs[i].n_terms);
+            B->ox.emplace_back(obs[i].x_mask, obs[i].x_mask + obs[i].n_terms);
+            B->oz.emplace_back(obs[i].z_mask, obs[i].z_mask + obs[i].n_terms);
+            const size_t bytes = (((size_t)1 << n) * eb + 255) & ~(size_t)255;
+            B->off_psi.push_back(soff);
+            B->off_phi.push_back(soff + bytes);
+            B->off_lam.push_back(soff + 2 * bytes);
+            soff += 3 * bytes;
+        }
+        B->p_off.push_back(poff);
+        if (matrices && n_matrix_elems) B->matrices.assign(matrices, matrices + 2 * n_matrix_elems);
+        else B->matrices.assign(2, 0.0);
+        B->n_mat = n_matrix_elems;
+        set_device(c);
+        ensure(c, B->pool, soff);
+        *out = B.release();
+    });
+}
+
+void qsv_batch_destroy(qsv_batch* B) {
+    if (!B) return;
+    (void)hipSetDevice(B->ctx->device);
+    (void)hipStreamSynchronize(B->ctx->stream);
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    for (DevBuf* b : {&B->pool, &B->tables, &B->partials, &B->results}) release(*b);
+    if (B->stage_in) (void)hipHostFree(B->stage_in);
+    if (B->stage_out) (void)hipHostFree(B->stage_out);
+    delete B;
+}
+
+qsv_status qsv_batch_run(qsv_batch* B, const double* params, double* expval, double* grad, uint32_t flags) {
+    qsv_ctx* c = B ? B->ctx : nullptr;
+    return guard(c, [&] {
+        if (!B || !expval) fail(QSV_ERR_ARG, "NULL argument");
+        if (flags & ~(uint32_t)QSV_BATCH_GRAPH) fail(QSV_ERR_ARG, "unknown flags");
+        if (B->p_off.back() && !params) fail(QSV_ERR_ARG, "params is NULL");
+        static const double dummy = 0.0;
+        const double* pp = params ? params : &dummy;
+        const bool want_grad = grad != nullptr;
+        set_device(c);
+        BatchPlan bp = plan_batch(B, pp, want_grad);
+        const bool use_graph = (flags & QSV_BATCH_GRAPH) != 0;
+        const bool same = use_graph && B->exec && B->graph_key == bp.key && B->graph_grad == want_grad;
+        if (!same) {
+            // (re)allocate device and staging buffers: pointers baked into a
+            // graph must stay valid, so a new structure rebuilds the graph
+            HIPCHK(hipStreamSynchronize(c->stream));
+            if (B->exec) HIPCHK(hipGraphExecDestroy(B->exec));
+            if (B->graph) HIPCHK(hipGraphDestroy(B->graph));
+            B->exec = nullptr;
+            B->graph = nullptr;
+            ensure(c, B->tables, bp.tab.size());
+            ensure(c, B->partials, bp.n_partials * 8);
+            ensure(c, B->results, bp.n_results * 8);
+            pin_grow(&B->stage_in, &B->stage_in_bytes, bp.tab.size());
+            pin_grow(&B->stage_out, &B->stage_out_bytes, bp.n_results * 8);
+        }
+        std::memcpy(B->stage_in, bp.tab.data(), bp.tab.size());
+        if (use_graph) {
+            if (!same) {
+                HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+                const int64_t prof = c->opt_profile;
+                c->opt_profile = 0;  // no event records inside the graph
+                try {
+                    enqueue_batch(B, bp);
+                } catch (...) {
+                    c->opt_profile = prof;
+                    hipGraph_t g = nullptr;
+                    (void)hipStreamEndCapture(c->stream, &g);
+                    if (g) (void)hipGraphDestroy(g);
+                    throw;
+                }
+                c->opt_profile = prof;
+                HIPCHK(hipStreamEndCapture(c->stream, &B->graph));
+                HIPCHK(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+                B->graph_key = bp.key;
+                B->graph_grad = want_grad;
+            }
+            HIPCHK(hipGraphLaunch(B->exec, c->stream));
+        } else {
+            enqueue_batch(B, bp);
+        }
+        HIPCHK(hipStreamSynchronize(c->stream));
+        const double* res = (const double*)B->stage_out;
+        const size_t nc = B->n.size();
+        for (size_t ci = 0; ci < nc; ++ci) expval[ci] = res[ci];
+        if (want_grad) {
+            for (size_t ci = 0; ci < nc; ++ci) {
+                double* g = grad + B->p_off[ci];
+                std::fill(g, g + B->n_params[ci], 0.0);
+                const auto& sp = bp.slot_param[ci];
+                for (size_t q = 0; q < sp.size(); ++q) g[sp[q].first] += sp[q].second * res[bp.slot_base[ci] + q];
+            }
+        }
     });
 }
 

@@ -339,6 +339,10 @@ void op_factors(const qsv_op& op, const double* params, const double* matrices, 
         if (s.zrot && f.nc == 0) {
             f.zrot = true;
             f.zangle = inv ? -s.zangle : s.zangle;
+            if (op.param[s.slot] >= 0) {
+                f.zparam = op.param[s.slot];
+                f.zscale = inv ? -op.scale[s.slot] : op.scale[s.slot];
+            }
         }
         out.push_back(std::move(f));
     }

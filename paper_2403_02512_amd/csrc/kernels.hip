@@ -883,10 +883,15 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
 // GEN: the pass also holds standalone ops (k-qubit matrices, or a tile too
 // small for groups); group-only passes compile without those code paths,
 // which keeps their register footprint (and so their occupancy) lower.
+// One block's share of a tile pass: tiles blk, blk + nblk, ... of the pass
+// described by a.  phi_src is where phi is read from (phi itself, or the
+// post-circuit state for an out-of-place first adjoint pass); with
+// TILE_SYNTH the tile is synthesised as the basis state a.basis instead.
 template <typename T, bool TWO, int LR, bool GEN>
-__global__ __launch_bounds__(256, 2) void k_tile(cx<T>* __restrict__ phi, cx<T>* __restrict__ lam, const TileArgs a,
-                                              const TOp* __restrict__ ops, const cx<T>* __restrict__ coef,
-                                              const uint64_t* __restrict__ words, double* __restrict__ partials) {
+__device__ __forceinline__ void tile_body(const cx<T>* __restrict__ phi_src, cx<T>* __restrict__ phi,
+                                          cx<T>* __restrict__ lam, const TileArgs& a, const TOp* __restrict__ ops,
+                                          const cx<T>* __restrict__ coef, const uint64_t* __restrict__ words,
+                                          double* __restrict__ partials, uint64_t blk, uint64_t nblk) {
     constexpr int R = 1 << LR;
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x;
@@ -914,8 +919,9 @@ __global__ __launch_bounds__(256, 2) void k_tile(cx<T>* __restrict__ phi, cx<T>*
     for (int j = 0; j < a.nthr_log2; ++j) offlo |= (uint64_t)((tid >> j) & 1) << a.sb[j];
     c.offlo = offlo;
     for (int s = tid; s < a.nslots * c.nwaves; s += nthr) c.sacc[s] = 0.0;
+    const bool synth = (a.flags & TILE_SYNTH) != 0;
 
-    for (uint64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    for (uint64_t tile = blk; tile < a.n_tiles; tile += nblk) {
         const uint64_t base = expand_idx(tile, a.outer);
         c.base = base;
         // global -> LDS in chunks of LCH elements per thread: LCH loads in
@@ -926,7 +932,12 @@ __global__ __launch_bounds__(256, 2) void k_tile(cx<T>* __restrict__ phi, cx<T>*
 #pragma unroll
             for (int r = 0; r < LCH; ++r) {
                 const uint64_t g = base | offlo | a.offhi[r0 + r];
-                vp[r] = phi[g];
+                if (synth) {
+                    vp[r].re = g == a.basis ? T(1) : T(0);
+                    vp[r].im = T(0);
+                } else {
+                    vp[r] = phi_src[g];
+                }
                 if (TWO) vl[r] = lam[g];
             }
 #pragma unroll
@@ -973,8 +984,29 @@ __global__ __launch_bounds__(256, 2) void k_tile(cx<T>* __restrict__ phi, cx<T>*
     for (int s = tid; s < a.nslots; s += nthr) {
         double v = 0.0;
         for (int w = 0; w < c.nwaves; ++w) v += c.sacc[s * c.nwaves + w];
-        partials[(uint64_t)s * gridDim.x + blockIdx.x] = v;
+        partials[(uint64_t)s * nblk + blk] = v;
     }
+}
+
+template <typename T, bool TWO, int LR, bool GEN>
+__global__ __launch_bounds__(256, 2) void k_tile(cx<T>* __restrict__ phi, cx<T>* __restrict__ lam, const TileArgs a,
+                                                 const TOp* __restrict__ ops, const cx<T>* __restrict__ coef,
+                                                 const uint64_t* __restrict__ words,
+                                                 double* __restrict__ partials) {
+    tile_body<T, TWO, LR, GEN>(phi, phi, lam, a, ops, coef, words, partials, blockIdx.x, gridDim.x);
+}
+
+// Batched passes: block b serves entry blk_entry[b] (one circuit's pass).
+template <typename T, bool TWO, int LR, bool GEN>
+__global__ __launch_bounds__(256, 2) void k_tile_batch(const TileEntry* __restrict__ entries,
+                                                       const int32_t* __restrict__ blk_entry,
+                                                       const TileArgs* __restrict__ args, const TOp* __restrict__ ops,
+                                                       const cx<T>* __restrict__ coef,
+                                                       const uint64_t* __restrict__ words,
+                                                       double* __restrict__ partials) {
+    const TileEntry& e = entries[blk_entry[blockIdx.x]];
+    tile_body<T, TWO, LR, GEN>((const cx<T>*)e.phi_src, (cx<T>*)e.phi, (cx<T>*)e.lam, args[e.args], ops, coef, words,
+                               partials + e.part_off, blockIdx.x - e.blk0, e.nblk);
 }
 
 int tile_lds_bytes(int b, bool two, int elem_bytes, int nslots, int zt_n) {
@@ -1028,6 +1060,59 @@ hipError_t launch_tile(hipStream_t s, bool two, bool generic, void* phi, void* l
     if (generic)
         return launch_tile_two<T, false, true>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, R, lds_bytes);
     return launch_tile_two<T, false, false>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, R, lds_bytes);
+}
+
+template <typename T, bool TWO, int LR, bool GEN>
+static hipError_t launch_tile_batch_lr(hipStream_t s, const TileEntry* entries, const int32_t* blk_entry,
+                                       const TileArgs* args, const TOp* ops, const void* coef, const uint64_t* words,
+                                       double* partials, int blocks, int nthr, size_t lds) {
+    static bool attr_set = false;
+    if (lds > 65536 && !attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_tile_batch<T, TWO, LR, GEN>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_tile_batch<T, TWO, LR, GEN>), dim3(blocks), dim3(nthr), lds, s, entries, blk_entry, args,
+                       ops, (const cx<T>*)coef, words, partials);
+    return hipGetLastError();
+}
+
+template <typename T, bool TWO, bool GEN>
+static hipError_t launch_tile_batch_two(hipStream_t s, const TileEntry* entries, const int32_t* blk_entry,
+                                        const TileArgs* args, const TOp* ops, const void* coef,
+                                        const uint64_t* words, double* partials, int blocks, int nthr, int R,
+                                        size_t lds) {
+#define QSV_TB(LRV) launch_tile_batch_lr<T, TWO, LRV, GEN>(s, entries, blk_entry, args, ops, coef, words, partials, \
+                                                           blocks, nthr, lds)
+    switch (R) {
+    case 1: return QSV_TB(0);
+    case 2: return QSV_TB(1);
+    case 4: return QSV_TB(2);
+    case 8: return QSV_TB(3);
+    case 16: return QSV_TB(4);
+    case 32: return QSV_TB(5);
+    default: return hipErrorInvalidValue;
+    }
+#undef QSV_TB
+}
+
+template <typename T>
+hipError_t launch_tile_batch(hipStream_t s, bool two, bool generic, const TileEntry* entries,
+                             const int32_t* blk_entry, const TileArgs* args, const TOp* ops, const void* coef,
+                             const uint64_t* words, double* partials, int blocks, int nthr, int R, size_t lds) {
+    if (two) {
+        if (generic)
+            return launch_tile_batch_two<T, true, true>(s, entries, blk_entry, args, ops, coef, words, partials,
+                                                        blocks, nthr, R, lds);
+        return launch_tile_batch_two<T, true, false>(s, entries, blk_entry, args, ops, coef, words, partials, blocks,
+                                                     nthr, R, lds);
+    }
+    if (generic)
+        return launch_tile_batch_two<T, false, true>(s, entries, blk_entry, args, ops, coef, words, partials, blocks,
+                                                     nthr, R, lds);
+    return launch_tile_batch_two<T, false, false>(s, entries, blk_entry, args, ops, coef, words, partials, blocks,
+                                                  nthr, R, lds);
 }
 
 // ------------------------------------------------------------------ Pauli sums
@@ -1092,6 +1177,57 @@ hipError_t launch_pauli(hipStream_t s, bool write_lambda, bool norm2, const void
     else
         hipLaunchKernelGGL((k_pauli<T, false, false>), dim3(grid), dim3(256), 0, s, (const cx<T>*)psi, (cx<T>*)lam,
                            N, groups, n_groups, terms, partials);
+    return hipGetLastError();
+}
+
+// Batched Pauli sums: block b serves entry blk_entry[b] (one circuit).
+template <typename T, bool WRITE>
+__global__ __launch_bounds__(256) void k_pauli_batch(const PauliEntry* __restrict__ entries,
+                                                     const int32_t* __restrict__ blk_entry,
+                                                     const PauliGroupDev* __restrict__ groups,
+                                                     const PauliTermDev* __restrict__ terms,
+                                                     double* __restrict__ partials) {
+    __shared__ double red[64];
+    const PauliEntry& en = entries[blk_entry[blockIdx.x]];
+    const cx<T>* __restrict__ psi = (const cx<T>*)en.psi;
+    cx<T>* __restrict__ lam = (cx<T>*)en.lam;
+    const uint64_t blk = blockIdx.x - en.blk0;
+    double dot = 0.0;
+    const uint64_t stride = (uint64_t)en.nblk * 256;
+    for (uint64_t i = blk * 256 + threadIdx.x; i < en.N; i += stride) {
+        const cx<T> pi = psi[i];
+        double ar = 0.0, ai = 0.0;
+        for (int g = en.g0; g < en.g0 + en.ng; ++g) {
+            const PauliGroupDev gr = groups[g];
+            const uint64_t src = i ^ gr.x;
+            const cx<T> ps = gr.x ? psi[src] : pi;
+            double sr = 0.0, si = 0.0;
+            for (int t = gr.t0; t < gr.t0 + gr.nt; ++t) {
+                const PauliTermDev tm = terms[t];
+                const bool neg = __popcll(src & tm.z) & 1;
+                sr += neg ? -tm.wre : tm.wre;
+                si += neg ? -tm.wim : tm.wim;
+            }
+            ar += sr * (double)ps.re - si * (double)ps.im;
+            ai += sr * (double)ps.im + si * (double)ps.re;
+        }
+        if (WRITE) lam[i] = cx<T>{(T)ar, (T)ai};
+        dot += (double)pi.re * ar + (double)pi.im * ai;
+    }
+    double tot = 0.0;
+    block_add(dot, red, &tot, threadIdx.x, 256);
+    if (threadIdx.x == 0) partials[en.part_off + blk] = tot;
+}
+
+template <typename T>
+hipError_t launch_pauli_batch(hipStream_t s, bool write_lambda, const PauliEntry* entries, const int32_t* blk_entry,
+                              const PauliGroupDev* groups, const PauliTermDev* terms, double* partials, int blocks) {
+    if (write_lambda)
+        hipLaunchKernelGGL((k_pauli_batch<T, true>), dim3(blocks), dim3(256), 0, s, entries, blk_entry, groups, terms,
+                           partials);
+    else
+        hipLaunchKernelGGL((k_pauli_batch<T, false>), dim3(blocks), dim3(256), 0, s, entries, blk_entry, groups,
+                           terms, partials);
     return hipGetLastError();
 }
 
@@ -1184,6 +1320,24 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ parti
     if (threadIdx.x == 0) out[slot] = tot;
 }
 
+// Batched reduction: block b sums partials[re[b].off + j], j < re[b].n, into out[re[b].out].
+__global__ __launch_bounds__(256) void k_reduce_batch(const ReduceEntry* __restrict__ re,
+                                                      const double* __restrict__ partials, double* __restrict__ out) {
+    __shared__ double red[64];
+    const ReduceEntry e = re[blockIdx.x];
+    double s = 0.0;
+    for (int j = threadIdx.x; j < e.n; j += 256) s += partials[e.off + j];
+    double tot = 0.0;
+    block_add(s, red, &tot, threadIdx.x, 256);
+    if (threadIdx.x == 0) out[e.out] = tot;
+}
+
+hipError_t launch_reduce_batch(hipStream_t s, const ReduceEntry* re, int n, const double* partials, double* out) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_batch, dim3(n), dim3(256), 0, s, re, partials, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce(hipStream_t s, const double* partials, int n_blocks, int n_slots, double* out) {
     if (n_slots <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_reduce, dim3(n_slots), dim3(256), 0, s, partials, n_blocks, out);
@@ -1207,6 +1361,11 @@ hipError_t launch_reduce(hipStream_t s, const double* partials, int n_blocks, in
                                         const PauliGroupDev*, int, const PauliTermDev*, double*, int);          \
     template hipError_t launch_probs<T>(hipStream_t, const void*, uint64_t, const Expand&, const uint64_t*, int, \
                                         int, double*);                                                          \
+    template hipError_t launch_tile_batch<T>(hipStream_t, bool, bool, const TileEntry*, const int32_t*,        \
+                                             const TileArgs*, const TOp*, const void*, const uint64_t*, double*, \
+                                             int, int, int, size_t);                                            \
+    template hipError_t launch_pauli_batch<T>(hipStream_t, bool, const PauliEntry*, const int32_t*,             \
+                                              const PauliGroupDev*, const PauliTermDev*, double*, int);         \
     template hipError_t launch_sparse<T>(hipStream_t, const void*, uint64_t, const int64_t*, const int64_t*,    \
                                          const double*, double*, int);
 

@@ -80,6 +80,30 @@ struct TileArgs {
     int32_t nslots;
     int32_t zt_n;           // phase-table entries copied to LDS at kernel start
     int64_t zt_off;         // their offset in the coefficient table
+    int32_t flags;          // TILE_SYNTH: phi tiles start as the basis state `basis`
+    int32_t pad2;
+    uint64_t basis;
+};
+constexpr int32_t TILE_SYNTH = 1;
+
+// One circuit's pass inside a batched launch (blocks blk0 .. blk0+nblk-1).
+struct TileEntry {
+    const void* phi_src;
+    void* phi;
+    void* lam;
+    int64_t part_off;  // first partial of this entry (slot-major, nblk per slot)
+    int32_t args, blk0, nblk, pad;
+};
+struct PauliEntry {
+    const void* psi;
+    void* lam;
+    uint64_t N;
+    int64_t part_off;
+    int32_t g0, ng, blk0, nblk;
+};
+struct ReduceEntry {
+    int64_t off;
+    int32_t n, out;
 };
 
 struct PauliGroupDev {
@@ -117,6 +141,14 @@ template <typename T> hipError_t launch_gatek(hipStream_t s, void* psi, uint64_t
 template <typename T> hipError_t launch_tile(hipStream_t s, bool two, bool generic, void* phi, void* lam, const TileArgs& a,
                                              const TOp* ops, const void* coef, const uint64_t* words,
                                              double* partials, int grid, int nthr, int R, size_t lds_bytes);
+template <typename T> hipError_t launch_tile_batch(hipStream_t s, bool two, bool generic, const TileEntry* entries,
+                                                   const int32_t* blk_entry, const TileArgs* args, const TOp* ops,
+                                                   const void* coef, const uint64_t* words, double* partials,
+                                                   int blocks, int nthr, int R, size_t lds_bytes);
+template <typename T> hipError_t launch_pauli_batch(hipStream_t s, bool write_lambda, const PauliEntry* entries,
+                                                    const int32_t* blk_entry, const PauliGroupDev* groups,
+                                                    const PauliTermDev* terms, double* partials, int blocks);
+hipError_t launch_reduce_batch(hipStream_t s, const ReduceEntry* re, int n, const double* partials, double* out);
 template <typename T> hipError_t launch_pauli(hipStream_t s, bool write_lambda, bool norm2, const void* psi,
                                               void* lam, uint64_t N, const PauliGroupDev* groups, int n_groups,
                                               const PauliTermDev* terms, double* partials, int grid);
@@ -149,6 +181,9 @@ struct Factor {
     // exp(-i zangle/2 Z..Z) on the targets without controls (RZ, IsingZZ, MultiRZ)
     bool zrot = false;
     double zangle = 0.0;
+    // the angle symbolically: zscale * params[zparam] (zparam < 0: constant)
+    int zparam = -1;
+    double zscale = 0.0;
     int src_op = -1;
 };
 

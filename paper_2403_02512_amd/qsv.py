@@ -61,8 +61,8 @@ _live = weakref.WeakSet()   # contexts and states still open, released before in
 
 def _close_all():
     objs = list(_live)
-    for o in objs:              # states first: they belong to contexts
-        if isinstance(o, State):
+    for o in objs:              # states and batches first: they belong to contexts
+        if not isinstance(o, Context):
             o.close()
     for o in objs:
         if isinstance(o, Context):
@@ -79,7 +79,7 @@ EXPORTS = [
     "qsv_state_destroy", "qsv_state_n_qubits", "qsv_state_device_ptr", "qsv_state_reset", "qsv_state_copy",
     "qsv_state_to_host", "qsv_state_from_host", "qsv_validate_ops", "qsv_validate_obs", "qsv_apply",
     "qsv_expval", "qsv_adjoint_jacobian", "qsv_adjoint_vjp", "qsv_plan_stats", "qsv_plan_json", "qsv_var",
-    "qsv_probs", "qsv_expval_sparse",
+    "qsv_probs", "qsv_expval_sparse", "qsv_batch_create", "qsv_batch_destroy", "qsv_batch_run",
 ]
 
 
@@ -123,6 +123,10 @@ def lib():
                             ctypes.POINTER(i64), ctypes.POINTER(i64), dp], i32),
         "qsv_plan_json": ([i32, i32, opp, sz, dp, sz, dp, sz, i32, i32, i32, i32, ctypes.c_char_p, sz,
                            ctypes.POINTER(sz)], i32),
+        "qsv_batch_create": ([vp, i32, sz, ctypes.POINTER(ctypes.c_int32), opp, ctypes.POINTER(sz),
+                              ctypes.POINTER(sz), dp, sz, obp, ctypes.POINTER(vp)], i32),
+        "qsv_batch_destroy": ([vp], None),
+        "qsv_batch_run": ([vp, dp, dp, dp, u32], i32),
     }
     for name in EXPORTS:
         f = getattr(L, name)
@@ -463,3 +467,81 @@ def adjoint_vjp(state: State, ops, params, observables, cotangent: Sequence[floa
                                  mo.n, _dptr(cot), _dptr(grad), _dptr(ev) if want_expval else None,
                                  ADJ_INPLACE if inplace else 0), state.ctx.h)
     return grad[: m.n_params], ev[: mo.n]
+
+
+# ------------------------------------------------------------------ batches
+
+BATCH_GRAPH = 1
+
+
+class Batch:
+    """Independent circuits (each with one observable, possibly of different
+    widths) run together: pass s of every circuit shares one launch, and with
+    ``graph=True`` the launch sequence is captured once in a HIP graph and
+    replayed for new parameters.  circuits: objects with n_qubits, ops,
+    n_params and observables (the first is used)."""
+
+    def __init__(self, ctx: Context, circuits, dtype: int = C128):
+        self.ctx = ctx
+        self.dtype = dtype
+        self.n_circuits = len(circuits)
+        self.n_params = [int(c.n_params) for c in circuits]
+        self.p_off = np.concatenate([[0], np.cumsum(self.n_params)]).astype(np.int64)
+        ms = [MarshalledOps(c.ops, np.zeros(c.n_params)) for c in circuits]
+        n_ops = sum(m.n for m in ms)
+        self._ops = (QsvOp * max(1, n_ops))()
+        offs = np.zeros(self.n_circuits + 1, dtype=np.uintp)
+        mats, moff, k = [], 0, 0
+        for i, m in enumerate(ms):
+            offs[i] = k
+            for j in range(m.n):
+                o = m.arr[j]
+                if o.matrix_offset >= 0:
+                    o.matrix_offset += moff
+                self._ops[k] = o
+                k += 1
+            if m.n_mat:
+                mats.append(m.matrices[:m.n_mat])
+                moff += m.n_mat
+        offs[-1] = k
+        self._mats = np.concatenate(mats) if mats else np.zeros(1, dtype=np.complex128)
+        self._obs = MarshalledObs([c.observables[0] for c in circuits])
+        nq = np.array([c.n_qubits for c in circuits], dtype=np.int32)
+        npar = np.array(self.n_params, dtype=np.uintp)
+        h = ctypes.c_void_p()
+        L = lib()
+        _check(L.qsv_batch_create(ctx.h, dtype, self.n_circuits, nq.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  self._ops, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_size_t)),
+                                  npar.ctypes.data_as(ctypes.POINTER(ctypes.c_size_t)),
+                                  self._mats.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double)), moff,
+                                  self._obs.arr, ctypes.byref(h)), ctx.h)
+        self.h = h
+        ctx.states.add(self)
+        _live.add(self)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().qsv_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, params, grad: bool = True, graph: bool = False):
+        """-> (expvals [n_circuits], list of per-circuit gradients or None)."""
+        p = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.float64).reshape(-1) for x in params])
+                                 if len(params) else np.zeros(0), dtype=np.float64)
+        if p.size != self.p_off[-1]:
+            raise ValueError(f"expected {self.p_off[-1]} parameters in total, got {p.size}")
+        ev = np.zeros(self.n_circuits)
+        g = np.zeros(max(1, p.size)) if grad else None
+        _check(lib().qsv_batch_run(self.h, _dptr(p if p.size else np.zeros(1)), _dptr(ev), _dptr(g),
+                                   BATCH_GRAPH if graph else 0), self.ctx.h)
+        if not grad:
+            return ev, None
+        return ev, [g[self.p_off[i]:self.p_off[i + 1]].copy() for i in range(self.n_circuits)]
