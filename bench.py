@@ -181,6 +181,17 @@ def batch_bench(args):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
         results[mode] = (dt, ev)
+    # one profiled eager batch: time per kernel kind
+    ctx.set_option(qsv.OPT_PROFILE, 1)
+    ctx.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(sets[0])
+    t_prof = time.perf_counter() - t0
+    kstats = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                  "GB_s": round((v["bytes"] / 1e9) / (v["ms"] / 1e3), 1) if v["ms"] > 0 else None}
+              for k, v in ctx.kernel_stats().items()}
+    ctx.set_option(qsv.OPT_PROFILE, 0)
     ev_loop = results["loop"][1]
     for mode in ("batch", "graph"):
         assert np.allclose(results[mode][1], ev_loop, atol=1e-10), mode
@@ -195,7 +206,9 @@ def batch_bench(args):
             "config": {"workload": f"{len(cs)} VQE-like circuits (RY + Givens layers x6), {min(widths)}-"
                                    f"{max(widths)} qubits, 200-term Pauli Hamiltonians, complex128: <H> and "
                                    f"adjoint gradient per circuit", "n_params_total": n_grad},
-            "speedup_vs_loop": round(results["loop"][0] / dt, 2)}), flush=True)
+            "speedup_vs_loop": round(results["loop"][0] / dt, 2),
+            **({"kernels_eager_batch": kstats, "profiled_batch_ms": round(1e3 * t_prof, 2)} if mode == "batch"
+               else {})}), flush=True)
     b.close()
     ctx.close()
 
@@ -277,8 +290,15 @@ def main():
     dom = max(stats, key=lambda k: stats[k]["ms"])
     d = stats[dom]
     achieved = (d["bytes"] / 1e9) / (d["ms"] / 1e3)
+    # measured HBM bytes per launch of the dominant kernel (FETCH_SIZE +
+    # WRITE_SIZE, copy-kernel calibrated), valid only for the kernel source
+    # the counters were taken on
+    from paper_2403_02512_amd.rocprof_summary import read_traffic
+    tr = None
+    if n == 28 and not (args.tile_bits or args.tile_bits_adj or args.low_bits) and args.fusion:
+        tr = (read_traffic(os.path.join(ROOT, "profiles", "hbm_traffic_qaoa28_c128.txt")) or {}).get(dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
                 "alg_bytes_per_launch": d["bytes"] / d["launches"], "avg_launch_ms": d["ms"] / d["launches"]}
 
     cpu = None

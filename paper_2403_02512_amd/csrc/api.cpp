@@ -3,6 +3,9 @@
 // Jacobian (paper Sec. 2.1-2.2; the adjoint method of Jones & Gacon cited in
 // Sec. 2.1 and Sec. 3.1.1).
 #include <algorithm>
+#include <atomic>
+#include <exception>
+#include <thread>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1658,6 +1661,32 @@ size_t append_bytes(std::vector<char>& tab, const std::vector<V>& v) {
     return off;
 }
 
+// Run f(0..n-1) on up to 16 host threads; the first exception is rethrown.
+template <typename Fn>
+void parallel_for(size_t n, Fn f) {
+    const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t nt = std::min<size_t>({hw, 16, (n + 7) / 8});
+    if (nt <= 1) {
+        for (size_t i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::atomic<size_t> next{0};
+    std::vector<std::exception_ptr> err(nt);
+    std::vector<std::thread> th;
+    for (size_t t = 0; t < nt; ++t)
+        th.emplace_back([&, t] {
+            try {
+                for (size_t i; (i = next.fetch_add(1)) < n;) f(i);
+            } catch (...) {
+                err[t] = std::current_exception();
+                next = n;
+            }
+        });
+    for (auto& x : th) x.join();
+    for (auto& e : err)
+        if (e) std::rethrow_exception(e);
+}
+
 BatchPlan plan_batch(qsv_batch* B, const double* params, bool grad) {
     BatchPlan bp;
     qsv_ctx* c = B->ctx;
@@ -1704,29 +1733,35 @@ BatchPlan plan_batch(qsv_batch* B, const double* params, bool grad) {
             out.push_back(r);
         }
     };
-    for (size_t ci = 0; ci < nc; ++ci) {
+    // per-circuit planning and lowering is independent: spread it over host threads
+    std::vector<Program> Pf(nc), Pb(nc);
+    parallel_for(nc, [&](size_t ci) {
         const int n = B->n[ci];
         const double* pp = params + B->p_off[ci];
         const auto& ops = B->ops[ci];
         std::vector<Factor> F = forward_factors(ops.data(), ops.size(), pp, B->matrices.data(), false);
         std::vector<Item> it = forward_items(F, n);
         PlanOptions po = plan_opts(c, B->dt, false);
-        Program P = build_program(po, F, it, n, B->dt, false, false, false);
-        if (P.steps.empty()) {  // no gates: one empty pass that writes |0..0>
+        Pf[ci] = build_program(po, F, it, n, B->dt, false, false, false);
+        if (Pf[ci].steps.empty()) {  // no gates: one empty pass that writes |0..0>
             Pass p;
             const int b = std::min(po.b, n);
             p.S = (b >= 64 ? ~0ull : ((1ull << b) - 1));
-            lower_tile(P, F, it, p, n, false, false, eb);
+            lower_tile(Pf[ci], F, it, p, n, false, false, eb);
         }
-        append_program(P, fwd[ci], true);
         if (grad && B->n_params[ci]) {
             std::vector<Factor> Fa = forward_factors(ops.data(), ops.size(), pp, B->matrices.data(), true);
             std::vector<Item> ia = adjoint_items(Fa, n);
-            Program Pa = build_program(plan_opts(c, B->dt, true), Fa, ia, n, B->dt, true, true, false);
-            bp.slot_param[ci] = Pa.slot_param;
+            Pb[ci] = build_program(plan_opts(c, B->dt, true), Fa, ia, n, B->dt, true, true, false);
+        }
+    });
+    for (size_t ci = 0; ci < nc; ++ci) {
+        append_program(Pf[ci], fwd[ci], true);
+        if (grad && B->n_params[ci]) {
+            bp.slot_param[ci] = Pb[ci].slot_param;
             bp.slot_base[ci] = n_res;
-            n_res += Pa.slot_param.size();
-            append_program(Pa, adj[ci], false);
+            n_res += Pb[ci].slot_param.size();
+            append_program(Pb[ci], adj[ci], false);
         }
     }
     // Pauli tables (one observable per circuit)

@@ -1,0 +1,126 @@
+"""Short text summaries of rocprofv3 CSV output.
+
+  python -m paper_2403_02512_amd.rocprof_summary stats <run_kernel_stats.csv> --cmd "<command>"
+      per-kernel launch count, total and average duration (markdown table)
+
+  python -m paper_2403_02512_amd.rocprof_summary traffic <fetch counter csv> <write counter csv>
+      --copy-bytes B --cmd "<commands>"
+      HBM bytes per dispatch from FETCH_SIZE and WRITE_SIZE (KiB per
+      dispatch), each scaled by the factor that makes the runtime's copy
+      kernel (__amd_rocclr_copyBuffer, which moves B bytes each way) read and
+      write exactly B bytes; one machine-readable line per kernel, plus the
+      SHA-1 of the kernel source the counters were taken on.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import os
+import sys
+
+KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "kernels.hip")
+
+KINDS = [("k_tile<double, true", "tile2"), ("k_tile<double, false", "tile1"), ("k_tile<float, true", "tile2"),
+         ("k_tile<float, false", "tile1"), ("k_pauli<double, true", "pauli_lambda"),
+         ("k_pauli<double, false", "pauli"), ("__amd_rocclr_copyBuffer", "copy"), ("k_init", "init"),
+         ("k_reduce", "reduce"), ("k_gate1", "gate1"), ("k_diag1", "diag1"), ("k_gate2", "gate2"),
+         ("k_gatek", "gatek")]
+
+
+def source_sha1(path: str = KERNEL_SOURCE) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()
+
+
+def short(name: str) -> str:
+    return name.split("(")[0].replace("void ", "").replace("qsv::", "")
+
+
+def kind_of(name: str) -> str:
+    for pat, k in KINDS:
+        if pat in name:
+            return k
+    return "other"
+
+
+def stats(path: str, cmd: str) -> str:
+    rows = list(csv.DictReader(open(path)))
+    out = [f"command: {cmd}", "", "| kernel | kind | calls | total ms | avg us | % |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        out.append(f"| {short(r['Name'])} | {kind_of(r['Name'])} | {r['Calls']} | "
+                   f"{int(r['TotalDurationNs']) / 1e6:.3f} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['Percentage']):.2f} |")
+    return "\n".join(out) + "\n"
+
+
+def _per_dispatch(path: str, counter: str):
+    vals = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            vals[r["Kernel_Name"]].append(float(r["Counter_Value"]) * 1024.0)  # KiB -> bytes
+    return vals
+
+
+def traffic(fetch_csv: str, write_csv: str, copy_bytes: float, cmd: str) -> str:
+    fetch = _per_dispatch(fetch_csv, "FETCH_SIZE")
+    write = _per_dispatch(write_csv, "WRITE_SIZE")
+    cp = [k for k in fetch if "copyBuffer" in k]
+    if not cp:
+        raise SystemExit("no copy kernel in the counter data: cannot calibrate")
+    # the copy runs as several dispatches, only one of which moves the data
+    f_scale = copy_bytes / max(fetch[cp[0]])
+    w_scale = copy_bytes / max(write[cp[0]])
+    out = [f"commands: {cmd}",
+           f"calibration: copy kernel moving {copy_bytes:.0f} B each way reads FETCH_SIZE "
+           f"{max(fetch[cp[0]]):.0f} B and WRITE_SIZE {max(write[cp[0]]):.0f} B -> "
+           f"fetch_scale={f_scale:.4f} write_scale={w_scale:.4f}",
+           f"kernel_source_sha1={source_sha1()}", ""]
+    for k in fetch:
+        if k not in write or "copyBuffer" in k:
+            continue
+        f = sum(fetch[k]) / len(fetch[k]) * f_scale
+        w = sum(write[k]) / len(write[k]) * w_scale
+        out.append(f"kind={kind_of(k)} kernel={short(k).replace(' ', '')} dispatches={len(fetch[k])} "
+                   f"fetch_bytes={f:.4e} write_bytes={w:.4e} traffic_bytes={f + w:.4e}")
+    return "\n".join(out) + "\n"
+
+
+def read_traffic(path: str):
+    """{kind: traffic bytes per dispatch} if the summary was taken on the
+    current kernel source, else None."""
+    if not os.path.exists(path):
+        return None
+    kv, sha = {}, None
+    for line in open(path):
+        if line.startswith("kernel_source_sha1="):
+            sha = line.strip().split("=", 1)[1]
+        elif line.startswith("kind="):
+            d = dict(x.split("=", 1) for x in line.split())
+            kv.setdefault(d["kind"], float(d["traffic_bytes"]))
+    if sha != source_sha1():
+        return None
+    return kv
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="mode", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("csv")
+    a.add_argument("--cmd", required=True)
+    b = sub.add_parser("traffic")
+    b.add_argument("fetch_csv")
+    b.add_argument("write_csv")
+    b.add_argument("--copy-bytes", type=float, required=True)
+    b.add_argument("--cmd", required=True)
+    args = ap.parse_args(argv)
+    if args.mode == "stats":
+        sys.stdout.write(stats(args.csv, args.cmd))
+    else:
+        sys.stdout.write(traffic(args.fetch_csv, args.write_csv, args.copy_bytes, args.cmd))
+
+
+if __name__ == "__main__":
+    main()
