@@ -137,6 +137,69 @@ def micro(n: int, reps: int = 5, dtype_name: str = "c128"):
           flush=True)
 
 
+def micro_tile(n: int, reps: int = 5):
+    """Cost structure of the LDS-tiled passes at n qubits, complex128: for
+    small synthetic circuits that plan into one tile pass, the forward pass
+    time (one vector) and the adjoint pass time (phi and lambda, with one
+    inner product per gate), per launch."""
+    import torch
+    from paper_2403_02512_amd import qsv
+    from paper_2403_02512_amd import workloads as W
+    ctx = qsv.Context(0)
+    st = qsv.State(ctx, n)
+    w = lambda bit: n - 1 - bit
+
+    def rx(bits, reps_=1):
+        ops, p = [], 0
+        for _ in range(reps_):
+            for b in bits:
+                ops.append(W.op("RX", [w(b)], (p, 1.0)))
+                p += 1
+        return ops, p
+
+    cases = [("RX bits 0,1", *rx([0, 1])), ("RX bits 0-3", *rx(range(4))), ("RX bits 0-7", *rx(range(8))),
+             ("RX bits 0-3,16-23", *rx(list(range(4)) + list(range(16, 24)))),
+             ("RX bits 16-19", *rx(range(16, 20))), ("RX bits 0-3 x4", *rx(range(4), 4)),
+             ("RX bits 0-3 x8", *rx(range(4), 8))]
+    zz = [W.op("IsingZZ", [w(b), w((b + 1) % 12)], (2, 1.0)) for b in range(12)]
+    cases.append(("IsingZZ ring bits 0-11 + RX bits 0,1", zz + rx([0, 1])[0], 3))
+    q = W.config3(n=n)
+    cases.append(("QAOA p=4 (308 gates)", q.ops, q.n_params))
+    obs = [W.PauliSum(np.array([1.0]), [W.pauli_word(n, {0: "Z"})])]
+    for name, ops, npar in cases:
+        params = np.linspace(0.1, 0.9, max(1, npar))
+        m = qsv.MarshalledOps(ops, params)
+        mo = qsv.MarshalledObs(obs)
+        for layers in (1, 0):
+            ctx.set_option(qsv.OPT_LAYERS, layers)
+            row = {"case": name, "n_qubits": n, "layers": layers}
+            for mode in ("fwd", "adj"):
+                st.reset(0)
+                qsv.apply(st, ops, None, marshalled=m)
+                if mode == "adj":
+                    qsv.adjoint_jacobian(st, ops, None, None, marshalled=m, marshalled_obs=mo)
+                ctx.synchronize()
+                ctx.set_option(qsv.OPT_PROFILE, 1)
+                ctx.reset_stats()
+                for _ in range(reps):
+                    if mode == "fwd":
+                        qsv.apply(st, ops, None, marshalled=m)
+                    else:
+                        qsv.adjoint_jacobian(st, ops, None, None, marshalled=m, marshalled_obs=mo)
+                stats = ctx.kernel_stats()
+                ctx.set_option(qsv.OPT_PROFILE, 0)
+                k = "tile1" if mode == "fwd" else "tile2"
+                s = stats.get(k)
+                row[mode] = None if s is None else {"launches": s["launches"] // reps,
+                                                   "ms_per_launch": round(s["ms"] / s["launches"], 4),
+                                                   "GB_s": round(s["bytes"] / 1e9 / (s["ms"] / 1e3), 1)}
+                if s is None:
+                    row[mode + "_kernels"] = {kk: v["launches"] // reps for kk, v in stats.items()}
+            print(json.dumps(row), flush=True)
+    st.close()
+    ctx.close()
+
+
 def batch_bench(args):
     """Batched VQE sweep: every circuit's <H> and full adjoint gradient, new
     random angles each step.  Three executions of the same work: a loop over
@@ -230,6 +293,7 @@ def main():
                     help="batched VQE sweep (512 circuits, 12-22 qubits): per-circuit loop vs batched launches "
                          "vs captured graph, circuits/s and gradients/s")
     ap.add_argument("--batch-circuits", type=int, default=512)
+    ap.add_argument("--micro-tile", action="store_true", help="tile-pass cost structure sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU state-vector "
@@ -238,6 +302,9 @@ def main():
 
     if args.batch:
         batch_bench(args)
+        return
+    if args.micro_tile:
+        micro_tile(args.n)
         return
     if args.micro:
         micro(args.n, dtype_name=args.micro_dtype)

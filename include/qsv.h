@@ -124,7 +124,8 @@ enum {
     QSV_OPT_TILE_BITS_ADJ = 3,  /* qubits per LDS tile for two-vector adjoint passes      */
     QSV_OPT_LOW_BITS = 4,       /* low index bits every tile keeps for coalescing         */
     QSV_OPT_PROFILE = 5,        /* 1: time every launch with HIP events                   */
-    QSV_OPT_NONTEMPORAL = 6     /* 1: streaming kernels use non-temporal stores           */
+    QSV_OPT_NONTEMPORAL = 6,    /* 1: streaming kernels use non-temporal stores           */
+    QSV_OPT_LAYERS = 7          /* 1: one-qubit runs in register groups run as layers (default) */
 };
 qsv_status qsv_ctx_set_option(qsv_ctx *ctx, int option, int64_t value);
 qsv_status qsv_ctx_get_option(qsv_ctx *ctx, int option, int64_t *value);
@@ -172,7 +173,8 @@ qsv_status qsv_validate_obs(int n_qubits, const qsv_pauli_sum *obs, size_t n_obs
  * fused passes, the number of lowered tile ops, and the algorithmic HBM
  * bytes of all passes.  adjoint = 0 plans qsv_apply; 1 plans one reverse
  * sweep of qsv_adjoint_jacobian (one observable, without lambda = H psi).
- * tile_bits / low_bits = 0 pick the defaults, fusion = 0 one pass per gate. */
+ * tile_bits / low_bits = 0 pick the defaults, fusion = 0 one pass per gate, 1 fused
+ * (default), 2 fused without one-qubit layers (QSV_OPT_LAYERS = 0). */
 qsv_status qsv_plan_stats(int n_qubits, qsv_dtype dtype, const qsv_op *ops, size_t n_ops, const double *params,
                           size_t n_params, const double *matrices, size_t n_matrix_elems, int adjoint,
                           int tile_bits, int low_bits, int fusion, int64_t *n_passes, int64_t *n_tile_passes,

@@ -46,7 +46,7 @@ struct qsv_ctx {
     bool own_stream = false;
     std::string err;
     int64_t opt_fusion = 1, opt_tile_bits = 0, opt_tile_bits_adj = 0, opt_low_bits = 0, opt_profile = 0,
-            opt_nontemporal = 0;
+            opt_nontemporal = 0, opt_layers = 1;
     DevBuf ops, coef, words, partials, slots, pgroups, pterms, ws0, ws1, binbits, csr_ptr, csr_col, csr_val;
     void* pin = nullptr;
     size_t pin_bytes = 0;
@@ -363,7 +363,7 @@ struct Proto {
 
 // Lower one planned pass into a k_tile step.
 void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item>& items, const Pass& pass, int n,
-                bool two, bool dagger, size_t eb) {
+                bool two, bool dagger, size_t eb, bool layers = true) {
     Step st;
     st.type = Step::TILE;
     int sb[16], b = 0;
@@ -623,6 +623,9 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
             for (int t = 0; t < GB; ++t) gop.tb[t] = Q[t];
             gop.m = (int)(e - i);
             gop.slot = -1;
+            // aux = 1: some sub-op needs the global index of each element
+            for (size_t x = i; x < e; ++x)
+                if (protos[x].kind == Proto::DIAG || protos[x].kind == Proto::DOTDIAG) gop.aux = 1;
             gop.woff = (int64_t)P.words.size();
             for (int el = 0; el < (1 << GB); ++el) {
                 uint64_t off = 0;
@@ -632,9 +635,93 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
             }
             for (int j = 0; j < b; ++j)
                 if (!((qmask >> j) & 1)) P.words.push_back((uint64_t)sb[j]);
+            const size_t gidx = P.tops.size();
             P.tops.push_back(gop);
             int dslot = 0;
-            for (size_t x = i; x < e; ++x) emit(protos[x], &Q, dslot);
+            if (!layers) {
+                for (size_t x = i; x < e; ++x) emit(protos[x], &Q, dslot);
+            } else {
+                // runs of uncontrolled one-qubit matrices and inner products
+                // on distinct group positions become one LAYER1 sub-op (ops on
+                // different positions commute, so the layer may run them in
+                // position order)
+                auto pos_of = [&](const Proto& pr) {
+                    const int tl = rank[n - 1 - F[pr.f].tw[0]];
+                    return (int)(std::find(Q.begin(), Q.end(), tl) - Q.begin());
+                };
+                auto layer_ok = [&](const Proto& pr) {
+                    return (pr.kind == Proto::APPLY || pr.kind == Proto::DOT) && pr.k == 1 && F[pr.f].nc == 0;
+                };
+                int lg[4] = {-1, -1, -1, -1}, ld[4] = {-1, -1, -1, -1};
+                std::vector<size_t> run;
+                auto flush_layer = [&]() {
+                    if (run.empty()) return;
+                    if (run.size() == 1) {
+                        emit(protos[run[0]], &Q, dslot);
+                    } else {
+                        TOp op;
+                        std::memset(&op, 0, sizeof op);
+                        op.kind = OP_LAYER1;
+                        op.k = 1;
+                        op.slot = -1;
+                        op.aux = dslot;
+                        bool real = true, riri = true;
+                        int gcls = 0;
+                        std::vector<cd> mats[4], gens[4];
+                        for (int p = 0; p < GB; ++p) {
+                            op.tb[p] = -1;
+                            mats[p] = {1.0, 0.0, 0.0, 1.0};
+                            if (lg[p] >= 0) mats[p] = maybe_dag(F[protos[lg[p]].f].m, 2, dagger);
+                            const auto& m = mats[p];
+                            real = real && m[0].imag() == 0 && m[1].imag() == 0 && m[2].imag() == 0 &&
+                                   m[3].imag() == 0;
+                            riri = riri && m[0].imag() == 0 && m[3].imag() == 0 && m[1].real() == 0 &&
+                                   m[2].real() == 0;
+                            gens[p] = {0.0, 0.0, 0.0, 0.0};
+                            if (ld[p] >= 0) {
+                                const Factor& f = F[protos[ld[p]].f];
+                                gens[p] = f.g;
+                                const int c = classify_gen1(f.g);
+                                gcls = gcls == 0 ? c : (gcls == c ? c : MC_DENSE);
+                                op.lcmask |= 1u << p;
+                                op.tb[p] = nslots++;
+                                P.slot_param.push_back({f.param, f.coef});
+                                ++dslot;
+                            }
+                        }
+                        op.cls = real ? MC_REAL : (riri ? MC_RIRI : MC_DENSE);
+                        op.lcval = (uint32_t)gcls;
+                        op.coff = (int64_t)P.coef.size();
+                        for (int p = 0; p < GB; ++p) {
+                            if (gcls == MC_DENSE)
+                                for (auto x : gens[p]) P.coef.push_back(x);
+                            for (auto x : mats[p]) P.coef.push_back(x);
+                        }
+                        P.tops.push_back(op);
+                    }
+                    run.clear();
+                    for (int p = 0; p < 4; ++p) lg[p] = ld[p] = -1;
+                };
+                for (size_t x = i; x < e; ++x) {
+                    const Proto& pr = protos[x];
+                    if (!layer_ok(pr)) {
+                        flush_layer();
+                        emit(pr, &Q, dslot);
+                        continue;
+                    }
+                    const int p = pos_of(pr);
+                    if (pr.kind == Proto::DOT) {
+                        if (lg[p] >= 0 || ld[p] >= 0) flush_layer();
+                        ld[p] = (int)x;
+                    } else {
+                        if (lg[p] >= 0) flush_layer();
+                        lg[p] = (int)x;
+                    }
+                    run.push_back(x);
+                }
+                flush_layer();
+            }
+            P.tops[gidx].m = (int)(P.tops.size() - gidx - 1);
             i = e;
         }
     }
@@ -713,7 +800,8 @@ bool lower_single(Program& P, const Factor& f, int n, size_t eb) {
     return true;
 }
 
-PlanOptions plan_opts(int64_t tile_bits, int64_t low_bits, int64_t fusion, qsv_dtype dt, bool two) {
+PlanOptions plan_opts(int64_t tile_bits, int64_t low_bits, int64_t fusion, qsv_dtype dt, bool two,
+                      int64_t layers = 1) {
     PlanOptions o;
     const bool c128 = dt == QSV_C128;
     int b = (int)tile_bits;
@@ -721,11 +809,13 @@ PlanOptions plan_opts(int64_t tile_bits, int64_t low_bits, int64_t fusion, qsv_d
     o.b = std::min(b, 8 + TILE_MAX_R_LOG2);
     o.low = low_bits > 0 ? (int)low_bits : (c128 ? 4 : 5);
     o.fusion = fusion != 0;
+    o.layers = layers != 0;
     return o;
 }
 
 PlanOptions plan_opts(qsv_ctx* c, qsv_dtype dt, bool two) {
-    return plan_opts(two ? c->opt_tile_bits_adj : c->opt_tile_bits, c->opt_low_bits, c->opt_fusion, dt, two);
+    return plan_opts(two ? c->opt_tile_bits_adj : c->opt_tile_bits, c->opt_low_bits, c->opt_fusion, dt, two,
+                     c->opt_layers);
 }
 
 Program build_program(const PlanOptions& po, const std::vector<Factor>& F, const std::vector<Item>& items, int n,
@@ -737,7 +827,7 @@ Program build_program(const PlanOptions& po, const std::vector<Factor>& F, const
         if (allow_streaming && !two && p.items.size() == 1 && !items[p.items[0]].dot) {
             if (lower_single(P, F[items[p.items[0]].f], n, eb)) continue;
         }
-        lower_tile(P, F, items, p, n, two, dagger, eb);
+        lower_tile(P, F, items, p, n, two, dagger, eb, po.layers);
     }
     return P;
 }
@@ -1126,6 +1216,7 @@ qsv_status qsv_ctx_set_option(qsv_ctx* c, int option, int64_t v) {
             break;
         case QSV_OPT_PROFILE: c->opt_profile = v != 0; break;
         case QSV_OPT_NONTEMPORAL: c->opt_nontemporal = v != 0; break;
+        case QSV_OPT_LAYERS: c->opt_layers = v != 0; break;
         default: fail(QSV_ERR_ARG, "unknown option");
         }
     });
@@ -1141,6 +1232,7 @@ qsv_status qsv_ctx_get_option(qsv_ctx* c, int option, int64_t* v) {
         case QSV_OPT_LOW_BITS: *v = c->opt_low_bits; break;
         case QSV_OPT_PROFILE: *v = c->opt_profile; break;
         case QSV_OPT_NONTEMPORAL: *v = c->opt_nontemporal; break;
+        case QSV_OPT_LAYERS: *v = c->opt_layers; break;
         default: fail(QSV_ERR_ARG, "unknown option");
         }
     });
@@ -1312,7 +1404,8 @@ qsv_status qsv_plan_json(int n, qsv_dtype dt, const qsv_op* ops, size_t n_ops, c
         const bool two = adjoint != 0;
         std::vector<Factor> F = forward_factors(ops, n_ops, params, matrices, two);
         std::vector<Item> items = two ? adjoint_items(F, n) : forward_items(F, n);
-        Program P = build_program(plan_opts(tile_bits, low_bits, fusion, dt, two), F, items, n, dt, two, two);
+        Program P = build_program(plan_opts(tile_bits, low_bits, fusion != 0, dt, two, fusion != 2), F, items, n, dt,
+                                  two, two);
         std::string js;
         char buf[512];
         auto add = [&](const char* fmt, auto... a) {
@@ -1391,7 +1484,8 @@ qsv_status qsv_plan_stats(int n, qsv_dtype dt, const qsv_op* ops, size_t n_ops, 
         const bool two = adjoint != 0;
         std::vector<Factor> F = forward_factors(ops, n_ops, params, matrices, two);
         std::vector<Item> items = two ? adjoint_items(F, n) : forward_items(F, n);
-        Program P = build_program(plan_opts(tile_bits, low_bits, fusion, dt, two), F, items, n, dt, two, two);
+        Program P = build_program(plan_opts(tile_bits, low_bits, fusion != 0, dt, two, fusion != 2), F, items, n, dt,
+                                  two, two);
         int64_t tiles = 0;
         double bytes = 0;
         for (const Step& st : P.steps) {

@@ -647,24 +647,6 @@ __device__ __forceinline__ double g_dot2(const cx<T>* a, const cx<T>* l, const c
     return acc;
 }
 
-#define QSV_P1_CASES(F)                                  \
-    switch (p0) {                                        \
-    case 0: F(0); break;                                 \
-    case 1: if constexpr (GB > 1) { F(1); } break;       \
-    case 2: if constexpr (GB > 2) { F(2); } break;       \
-    case 3: if constexpr (GB > 3) { F(3); } break;       \
-    default: break;                                      \
-    }
-#define QSV_P2_CASE(A, B, F) \
-    case A * 4 + B: if constexpr (GB > A && GB > B) { F(A, B); } break;
-#define QSV_P2_CASES(F)                                                                          \
-    switch (p0 * 4 + p1) {                                                                       \
-    QSV_P2_CASE(0, 1, F) QSV_P2_CASE(0, 2, F) QSV_P2_CASE(0, 3, F) QSV_P2_CASE(1, 0, F)          \
-    QSV_P2_CASE(1, 2, F) QSV_P2_CASE(1, 3, F) QSV_P2_CASE(2, 0, F) QSV_P2_CASE(2, 1, F)          \
-    QSV_P2_CASE(2, 3, F) QSV_P2_CASE(3, 0, F) QSV_P2_CASE(3, 1, F) QSV_P2_CASE(3, 2, F)          \
-    default: break;                                                                              \
-    }
-
 // register accumulators of the group's inner products, selected by a runtime
 // index through a switch so they stay in registers
 struct DotAcc {
@@ -695,6 +677,53 @@ struct DotAcc {
     }
 };
 
+// One layer of one-qubit ops over every group position.  Ops on different
+// positions commute (and so do a generator on one position and a matrix on
+// another, for the inner products), so the layer runs positions in a fixed
+// order as straight-line code: no per-gate dispatch, and the register arrays
+// flow through without merges.  Per position p the coefficients are
+// [generator (GCLS == DENSE only)] then the 2x2 matrix.
+template <typename T, bool TWO, int GB, int CLS, int GCLS, int P>
+__device__ __forceinline__ void g_layer_pos(cx<T>* a, cx<T>* l, const cx<T>* m, uint32_t dmask, DotAcc& acc,
+                                            int& ai) {
+    constexpr int NC = GCLS == MC_DENSE ? 8 : 4;
+    const cx<T>* mp = m + P * NC;
+    if constexpr (TWO && GCLS != 0) {
+        if (dmask & (1u << P)) {
+            acc.add(ai, g_dot1<T, GB, P, GCLS, false>(a, l, mp, 0, nullptr, 0, 0));
+            ++ai;
+        }
+    }
+    g_apply1<T, TWO, GB, P, CLS, false>(a, l, mp + (GCLS == MC_DENSE ? 4 : 0), 0, nullptr, 0, 0);
+}
+
+template <typename T, bool TWO, int GB, int CLS, int GCLS>
+__device__ __forceinline__ void g_layer(cx<T>* a, cx<T>* l, const cx<T>* m, uint32_t dmask, DotAcc& acc, int acc0) {
+    int ai = acc0;
+    g_layer_pos<T, TWO, GB, CLS, GCLS, 0>(a, l, m, dmask, acc, ai);
+    if constexpr (GB > 1) g_layer_pos<T, TWO, GB, CLS, GCLS, 1>(a, l, m, dmask, acc, ai);
+    if constexpr (GB > 2) g_layer_pos<T, TWO, GB, CLS, GCLS, 2>(a, l, m, dmask, acc, ai);
+    if constexpr (GB > 3) g_layer_pos<T, TWO, GB, CLS, GCLS, 3>(a, l, m, dmask, acc, ai);
+}
+
+#define QSV_P1_CASES(F)                                  \
+    switch (p0) {                                        \
+    case 0: F(0); break;                                 \
+    case 1: if constexpr (GB > 1) { F(1); } break;       \
+    case 2: if constexpr (GB > 2) { F(2); } break;       \
+    case 3: if constexpr (GB > 3) { F(3); } break;       \
+    default: break;                                      \
+    }
+#define QSV_P2_CASE(A, B, F) \
+    case A * 4 + B: if constexpr (GB > A && GB > B) { F(A, B); } break;
+#define QSV_P2_CASES(F)                                                                          \
+    switch (p0 * 4 + p1) {                                                                       \
+    QSV_P2_CASE(0, 1, F) QSV_P2_CASE(0, 2, F) QSV_P2_CASE(0, 3, F) QSV_P2_CASE(1, 0, F)          \
+    QSV_P2_CASE(1, 2, F) QSV_P2_CASE(1, 3, F) QSV_P2_CASE(2, 0, F) QSV_P2_CASE(2, 1, F)          \
+    QSV_P2_CASE(2, 3, F) QSV_P2_CASE(3, 0, F) QSV_P2_CASE(3, 1, F) QSV_P2_CASE(3, 2, F)          \
+    default: break;                                                                              \
+    }
+
 template <typename T, bool TWO, int R, int GB>
 __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TOp& g, const TOp* __restrict__ subs,
                                            int b) {
@@ -710,10 +739,16 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
             if ((e >> i) & 1) o |= 1u << g.tb[i];
         eo[e] = o;
     }
+    // sw() is linear over GF(2) and tc, eo[e] have disjoint bits, so the
+    // LDS slot of element e is sw(tc) ^ sw(eo[e]) (a uniform XOR)
+    uint32_t swe[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) swe[e] = sw(eo[e]);
     DotAcc acc;
 #pragma unroll
     for (int d = 0; d < GROUP_MAX_DOTS; ++d) acc.v[d] = 0.0;
     const int nq = b - GB;
+    const bool need_gc = g.aux != 0;  // the group holds position-dependent diagonals
 #pragma unroll 1
     for (int sc = c.tid; sc < nsub; sc += c.nthr) {
         uint32_t tc = (uint32_t)sc;
@@ -723,13 +758,15 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
             tc = ((tc >> q) << (q + 1)) | (tc & ((1u << q) - 1));
         }
         uint64_t gc = c.base;
-        for (int j = 0; j < nq; ++j)
-            if ((sc >> j) & 1) gc |= 1ull << w[E + j];
+        if (need_gc)
+            for (int j = 0; j < nq; ++j)
+                if ((sc >> j) & 1) gc |= 1ull << w[E + j];
+        const uint32_t stc = sw(tc);
         cx<T> a[E], l[TWO ? E : 1];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            a[e] = c.tp[sw(tc | eo[e])];
-            if (TWO) l[e] = c.tl[sw(tc | eo[e])];
+            a[e] = c.tp[stc ^ swe[e]];
+            if (TWO) l[e] = c.tl[stc ^ swe[e]];
         }
         for (int si = 0; si < g.m; ++si) {
             const TOp& s = subs[si];
@@ -783,6 +820,30 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
 #undef F
                 }
                 break;
+            case OP_LAYER1: {
+                const int gcls = TWO ? (int)s.lcval : 0;
+#define L(C, G) g_layer<T, TWO, GB, C, G>(a, l, m, s.lcmask, acc, s.aux)
+                if (gcls == 0) {
+                    if (s.cls == MC_REAL) L(MC_REAL, 0);
+                    else if (s.cls == MC_RIRI) L(MC_RIRI, 0);
+                    else L(MC_DENSE, 0);
+                } else if constexpr (TWO) {
+                    if (gcls == MC_PX) {
+                        if (s.cls == MC_REAL) L(MC_REAL, MC_PX);
+                        else if (s.cls == MC_RIRI) L(MC_RIRI, MC_PX);
+                        else L(MC_DENSE, MC_PX);
+                    } else if (gcls == MC_PY) {
+                        if (s.cls == MC_REAL) L(MC_REAL, MC_PY);
+                        else if (s.cls == MC_RIRI) L(MC_RIRI, MC_PY);
+                        else L(MC_DENSE, MC_PY);
+                    } else {
+                        if (s.cls == MC_REAL) L(MC_REAL, MC_DENSE);
+                        else if (s.cls == MC_RIRI) L(MC_RIRI, MC_DENSE);
+                        else L(MC_DENSE, MC_DENSE);
+                    }
+                }
+#undef L
+            } break;
             case OP_DIAG:
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
@@ -859,23 +920,32 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
         }
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            c.tp[sw(tc | eo[e])] = a[e];
-            if (TWO) c.tl[sw(tc | eo[e])] = l[e];
+            c.tp[stc ^ swe[e]] = a[e];
+            if (TWO) c.tl[stc ^ swe[e]] = l[e];
         }
     }
     if constexpr (TWO) {
         // flush: per-wave sums into the wave's accumulator (no barrier when
         // the block is made of whole waves)
-        for (int si = 0; si < g.m; ++si) {
-            const TOp& s = subs[si];
-            if (s.kind < OP_DOT1 || s.kind == OP_DOTK || s.kind > OP_DOTZSUM) continue;
-            const double v = acc.get(s.aux);
+        auto flush = [&](int ai, int slot) {
+            const double v = acc.get(ai);
             if (c.nthr >= 64) {
                 const double tot = wave_sum(v);
-                if ((c.tid & 63) == 0) c.sacc[s.slot * c.nwaves + (c.tid >> 6)] += tot;
+                if ((c.tid & 63) == 0) c.sacc[slot * c.nwaves + (c.tid >> 6)] += tot;
             } else {
-                block_add(v, c.red, c.sacc + s.slot * c.nwaves, c.tid, c.nthr);
+                block_add(v, c.red, c.sacc + slot * c.nwaves, c.tid, c.nthr);
             }
+        };
+        for (int si = 0; si < g.m; ++si) {
+            const TOp& s = subs[si];
+            if (s.kind == OP_LAYER1) {
+                int ai = s.aux;
+                for (int p = 0; p < GB; ++p)
+                    if (s.lcmask & (1u << p)) flush(ai++, s.tb[p]);
+                continue;
+            }
+            if (s.kind < OP_DOT1 || s.kind == OP_DOTK || s.kind > OP_DOTZSUM) continue;
+            flush(s.aux, s.slot);
         }
     }
 }
@@ -895,8 +965,13 @@ __device__ __forceinline__ void tile_body(const cx<T>* __restrict__ phi_src, cx<
     constexpr int R = 1 << LR;
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x;
-    const int nthr = blockDim.x;
+    // tiles of more than 256 elements always run 256 threads: a compile-time
+    // block size turns every per-element LDS offset into an immediate
+    const int nthr = LR > 0 ? 256 : (int)blockDim.x;
     const int tsz = nthr * R;
+    // LDS slot of the thread's element r: sw(tid + r * nthr) = sw(tid) + r * nthr
+    // (r * nthr only has bits at or above bit 8 when R > 1)
+    const uint32_t stid = sw((uint32_t)tid);
     TileCtx<T, TWO, R> c;
     c.tp = reinterpret_cast<cx<T>*>(smem);
     c.tl = c.tp + (TWO ? tsz : 0);
@@ -942,8 +1017,8 @@ __device__ __forceinline__ void tile_body(const cx<T>* __restrict__ phi_src, cx<
             }
 #pragma unroll
             for (int r = 0; r < LCH; ++r) {
-                c.tp[sw(tid + (r0 + r) * nthr)] = vp[r];
-                if (TWO) c.tl[sw(tid + (r0 + r) * nthr)] = vl[r];
+                c.tp[stid + (r0 + r) * nthr] = vp[r];
+                if (TWO) c.tl[stid + (r0 + r) * nthr] = vl[r];
             }
         }
         __syncthreads();
@@ -974,8 +1049,8 @@ __device__ __forceinline__ void tile_body(const cx<T>* __restrict__ phi_src, cx<
 #pragma unroll
             for (int r = 0; r < LCH; ++r) {
                 const uint64_t g = base | offlo | a.offhi[r0 + r];
-                phi[g] = c.tp[sw(tid + (r0 + r) * nthr)];
-                if (TWO) lam[g] = c.tl[sw(tid + (r0 + r) * nthr)];
+                phi[g] = c.tp[stid + (r0 + r) * nthr];
+                if (TWO) lam[g] = c.tl[stid + (r0 + r) * nthr];
             }
         }
         __syncthreads();

@@ -40,7 +40,11 @@ enum TOpKind : int32_t {
     OP_DOTK,
     OP_DOTDIAG,     // slot += Im <lam|D|phi> for diagonal D on global bits
     OP_DOTZSUM,     // slot += Im <lam| sum_j Z^{z_j} |phi>
-    OP_GROUP        // the next m ops act inside register subcubes over the k tile bits tb[0..k-1]
+    OP_GROUP,       // the next m ops act inside register subcubes over the k tile bits tb[0..k-1]
+    OP_LAYER1       // in a group: for each group position p ascending, an optional inner
+                    // product with a one-qubit generator on p (bit p of lcmask; slot tb[p];
+                    // generator class lcval), then a 2x2 matrix of class cls on p
+                    // (identity where the layer has no gate)
 };
 
 // Matrix classes.  DENSE/DIAG/ANTI/MID are used by every kernel; the finer
@@ -213,6 +217,7 @@ struct PlanOptions {
     int b = 12;          // tile bits
     int low = 4;         // coalescing low bits kept in every tile
     bool fusion = true;
+    bool layers = true;  // one-qubit runs inside register groups as LAYER1 sub-ops
     int max_scan = 2048; // look-ahead window of the greedy planner
 };
 

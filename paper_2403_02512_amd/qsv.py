@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libqsv.so")
 C64, C128 = 1, 2
 MAX_QUBITS = 34
 ADJ_INPLACE = 1
-OPT_FUSION, OPT_TILE_BITS, OPT_TILE_BITS_ADJ, OPT_LOW_BITS, OPT_PROFILE, OPT_NONTEMPORAL = 1, 2, 3, 4, 5, 6
+OPT_FUSION, OPT_TILE_BITS, OPT_TILE_BITS_ADJ, OPT_LOW_BITS, OPT_PROFILE, OPT_NONTEMPORAL, OPT_LAYERS = 1, 2, 3, 4, 5, 6, 7
 
 GATE_IDS = {
     "PauliX": 1, "PauliY": 2, "PauliZ": 3, "Hadamard": 4, "S": 5, "T": 6, "SX": 7, "Identity": 8,

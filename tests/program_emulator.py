@@ -10,8 +10,8 @@ The streaming single-gate passes are modelled by their index sets.
 """
 import numpy as np
 
-OP_APPLY1, OP_APPLY2, OP_APPLYK, OP_DIAG, OP_ZPHASE, OP_DOT1, OP_DOT2, OP_DOTK, OP_DOTDIAG, OP_DOTZSUM, OP_GROUP = \
-    range(1, 12)
+OP_APPLY1, OP_APPLY2, OP_APPLYK, OP_DIAG, OP_ZPHASE, OP_DOT1, OP_DOT2, OP_DOTK, OP_DOTDIAG, OP_DOTZSUM, OP_GROUP, \
+    OP_LAYER1 = range(1, 13)
 MC_DENSE, MC_DIAG, MC_ANTI, MC_MID, MC_REAL, MC_RIRI, MC_PX, MC_PY = range(8)
 
 
@@ -186,6 +186,7 @@ def _group(prog, st, g, subs, tp, tl, base, slots):
                     v = sum(np.conj(l[sel, ids[r]]) * sum(m[r, j] * y[j] for j in range(4)) for r in range(4))
                     slots[st["slot_base"] + s["slot"]] += v.imag.sum()
         elif kind in (OP_DIAG, OP_DOTDIAG):
+            assert g["aux"] == 1, "the kernel computes global indices only for groups flagged aux = 1"
             k = s["k"]
             d = _coef(prog, s["coff"], 1 << k)
             j = np.zeros_like(gi)
@@ -215,6 +216,33 @@ def _group(prog, st, g, subs, tp, tl, base, slots):
             else:
                 v = (mz - 2 * cnt) * (np.conj(l) * a).imag
                 slots[st["slot_base"] + s["slot"]] += v.sum()
+        elif kind == OP_LAYER1:
+            # per position P ascending: optional inner product, then the 2x2
+            gcls = s["lcval"]
+            nc = 8 if gcls == MC_DENSE else 4
+            cf = _coef(prog, s["coff"], nc * GB)
+            for P in range(GB):
+                mp = cf[P * nc:(P + 1) * nc]
+                M = mp[4:8] if gcls == MC_DENSE else mp[:4]
+                if s["cls"] == MC_REAL:
+                    assert np.all(M.imag == 0)
+                elif s["cls"] == MC_RIRI:
+                    assert M[0].imag == 0 and M[3].imag == 0 and M[1].real == 0 and M[2].real == 0
+                pairs = [(e0, e0 | (1 << P)) for e0 in range(E) if not e0 & (1 << P)]
+                if (s["lcmask"] >> P) & 1:
+                    assert l is not None and gcls != 0
+                    G = {MC_PX: np.array([0, 1, 1, 0], dtype=complex),
+                         MC_PY: np.array([0, -1j, 1j, 0])}.get(gcls, mp[:4])
+                    v = 0.0
+                    for e0, e1 in pairs:
+                        p0, p1 = a[:, e0], a[:, e1]
+                        v += (np.conj(l[:, e0]) * (G[0] * p0 + G[1] * p1) +
+                              np.conj(l[:, e1]) * (G[2] * p0 + G[3] * p1)).imag.sum()
+                    slots[st["slot_base"] + s["tb"][P]] += v
+                for x in ([a, l] if l is not None else [a]):
+                    for e0, e1 in pairs:
+                        x0, x1 = x[:, e0].copy(), x[:, e1].copy()
+                        x[:, e0], x[:, e1] = M[0] * x0 + M[1] * x1, M[2] * x0 + M[3] * x1
         else:
             raise AssertionError(f"op kind {kind} inside a group")
     tp[idx] = a

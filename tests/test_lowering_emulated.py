@@ -8,7 +8,7 @@ import oracle
 from paper_2403_02512_amd import workloads as W
 from tests.program_emulator import emulate_adjoint, emulate_apply
 
-OPTS = [{}, {"tile_bits": 5, "low_bits": 2}, {"tile_bits": 4, "low_bits": 1}, {"fusion": False}]
+OPTS = [{}, {"tile_bits": 5, "low_bits": 2}, {"tile_bits": 4, "low_bits": 1}, {"fusion": False}, {"fusion": 2}]
 
 
 @pytest.mark.parametrize("opt", range(len(OPTS)))

@@ -58,9 +58,12 @@ def test_non_commuting_gates_keep_order():
 
 def test_adjoint_plan_counts_inner_products():
     c = W.config1()
-    st = qsv.plan_stats(10, c.ops, c.params, adjoint=True)
+    st = qsv.plan_stats(10, c.ops, c.params, adjoint=True, fusion=2)
     # 120 trainable slots + 160 un-applies in a single tile (plus group headers)
     assert st["passes"] == 1 and st["kernel_ops"] >= 280
+    # with one-qubit layers the rotations of a layer share sub-ops
+    lay = qsv.plan_stats(10, c.ops, c.params, adjoint=True)
+    assert lay["passes"] == 1 and lay["kernel_ops"] < st["kernel_ops"]
 
 
 def test_plan_stats_validates():
