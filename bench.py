@@ -137,7 +137,7 @@ def micro(n: int, reps: int = 5, dtype_name: str = "c128"):
           flush=True)
 
 
-def micro_tile(n: int, reps: int = 5):
+def micro_tile(n: int, reps: int = 5, only: str = "", layer_modes=(1, 0)):
     """Cost structure of the LDS-tiled passes at n qubits, complex128: for
     small synthetic circuits that plan into one tile pass, the forward pass
     time (one vector) and the adjoint pass time (phi and lambda, with one
@@ -167,10 +167,12 @@ def micro_tile(n: int, reps: int = 5):
     cases.append(("QAOA p=4 (308 gates)", q.ops, q.n_params))
     obs = [W.PauliSum(np.array([1.0]), [W.pauli_word(n, {0: "Z"})])]
     for name, ops, npar in cases:
+        if only and only != name:
+            continue
         params = np.linspace(0.1, 0.9, max(1, npar))
         m = qsv.MarshalledOps(ops, params)
         mo = qsv.MarshalledObs(obs)
-        for layers in (1, 0):
+        for layers in layer_modes:
             ctx.set_option(qsv.OPT_LAYERS, layers)
             row = {"case": name, "n_qubits": n, "layers": layers}
             for mode in ("fwd", "adj"):
@@ -294,6 +296,7 @@ def main():
                          "vs captured graph, circuits/s and gradients/s")
     ap.add_argument("--batch-circuits", type=int, default=512)
     ap.add_argument("--micro-tile", action="store_true", help="tile-pass cost structure sweep")
+    ap.add_argument("--micro-case", default="", help="run only this micro-tile case (layers on)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU state-vector "
@@ -304,7 +307,7 @@ def main():
         batch_bench(args)
         return
     if args.micro_tile:
-        micro_tile(args.n)
+        micro_tile(args.n, only=args.micro_case, layer_modes=(1,) if args.micro_case else (1, 0))
         return
     if args.micro:
         micro(args.n, dtype_name=args.micro_dtype)

@@ -837,19 +837,25 @@ struct DevT {};
 
 // Launch every step of a program on (phi, lam).  Slot sums land in
 // slots + slot_offset + step.slot_base.
+// phi_src: where the first step reads phi from (the program then runs out of
+// place for its first pass; nullptr: phi itself).  The first step must then be
+// a tile pass.
 void run_program(qsv_ctx* c, const Program& P, qsv_dtype dt, int n, void* phi, void* lam, double* slots,
-                 int slot_offset) {
+                 int slot_offset, const void* phi_src = nullptr) {
     const bool c128 = dt == QSV_C128;
     const size_t cb = c128 ? 16 : 8;
+    if (phi_src && (P.steps.empty() || P.steps[0].type != Step::TILE))
+        fail(QSV_ERR_UNSUPPORTED, "out-of-place program without a leading tile pass");
     for (const Step& st : P.steps) {
         if (st.type == Step::TILE) {
+            const void* src = (phi_src && &st == &P.steps[0]) ? phi_src : phi;
             Timed t(c, lam ? KK_TILE2 : KK_TILE1, st.bytes);
-            hipError_t e = c128 ? launch_tile<double>(c->stream, lam != nullptr, st.generic, phi, lam, st.ta, (const TOp*)c->ops.p,
-                                                      c->coef.p, (const uint64_t*)c->words.p, (double*)c->partials.p,
-                                                      st.grid, st.nthr, st.R, st.lds)
-                                : launch_tile<float>(c->stream, lam != nullptr, st.generic, phi, lam, st.ta, (const TOp*)c->ops.p,
-                                                     c->coef.p, (const uint64_t*)c->words.p, (double*)c->partials.p,
-                                                     st.grid, st.nthr, st.R, st.lds);
+            hipError_t e = c128 ? launch_tile<double>(c->stream, lam != nullptr, st.generic, src, phi, lam, st.ta,
+                                                      (const TOp*)c->ops.p, c->coef.p, (const uint64_t*)c->words.p,
+                                                      (double*)c->partials.p, st.grid, st.nthr, st.R, st.lds)
+                                : launch_tile<float>(c->stream, lam != nullptr, st.generic, src, phi, lam, st.ta,
+                                                     (const TOp*)c->ops.p, c->coef.p, (const uint64_t*)c->words.p,
+                                                     (double*)c->partials.p, st.grid, st.nthr, st.R, st.lds);
             t.done(e);
             if (st.nslots) {
                 Timed tr(c, KK_REDUCE, 8.0 * st.nslots * st.grid);
@@ -1058,11 +1064,13 @@ void adjoint_impl(qsv_state* s, const qsv_op* ops, size_t n_ops, const double* p
         for (size_t o = 0; o < rows.size(); ++o) run_pauli(c, s->dt, n, T, (int)(o + 1), s->ptr, nullptr, evslots + o);
     for (size_t r = 0; r < n_rows; ++r) {
         run_pauli(c, s->dt, n, T, (int)r, s->ptr, lam, vjp ? slots + n_rows * nslot + rows.size() : evslots + r);
-        if (!inplace) {
+        // out of place: the first pass reads the state and writes phi (no copy)
+        const bool oop = !inplace && !P.steps.empty();
+        if (!inplace && P.steps.empty()) {
             Timed t(c, KK_COPY, 2.0 * N * eb);
             t.done(hipMemcpyAsync(phi, s->ptr, N * eb, hipMemcpyDeviceToDevice, c->stream));
         }
-        run_program(c, P, s->dt, n, phi, lam, slots, (int)(r * nslot));
+        run_program(c, P, s->dt, n, phi, lam, slots, (int)(r * nslot), oop ? s->ptr : nullptr);
     }
     std::vector<double> host(n_rows * nslot + n_ev + 1);
     HIPCHK(hipMemcpyAsync(host.data(), slots, host.size() * 8, hipMemcpyDeviceToHost, c->stream));

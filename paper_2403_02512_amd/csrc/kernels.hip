@@ -52,10 +52,32 @@ __device__ __forceinline__ uint64_t expand_idx(uint64_t k, const Expand& e) {
     return r;
 }
 
+// v of the lane `shift` below in the same 16-lane row (0 past the row start):
+// DPP row_shr on both halves of the double, no LDS traffic
+template <int SHIFT>
+__device__ __forceinline__ double row_shr(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x110 + SHIFT, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x110 + SHIFT, 0xF, 0xF, true);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over the 64 lanes (every lane active), returned to all lanes: in-row
+// prefix sums by DPP leave each row's total in its lane 15; the four row
+// totals are read as uniform values.  Fixed order, so reproducible.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += row_shr<1>(v);
+    v += row_shr<2>(v);
+    v += row_shr<4>(v);
+    v += row_shr<8>(v);
+    return (lane_value(v, 15) + lane_value(v, 31)) + (lane_value(v, 47) + lane_value(v, 63));
 }
 
 // Adds the block-wide sum of v to *dst (one thread writes).  Every thread of
@@ -958,7 +980,7 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
 // post-circuit state for an out-of-place first adjoint pass); with
 // TILE_SYNTH the tile is synthesised as the basis state a.basis instead.
 template <typename T, bool TWO, int LR, bool GEN>
-__device__ __forceinline__ void tile_body(const cx<T>* __restrict__ phi_src, cx<T>* __restrict__ phi,
+__device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
                                           cx<T>* __restrict__ lam, const TileArgs& a, const TOp* __restrict__ ops,
                                           const cx<T>* __restrict__ coef, const uint64_t* __restrict__ words,
                                           double* __restrict__ partials, uint64_t blk, uint64_t nblk) {
@@ -1064,11 +1086,11 @@ __device__ __forceinline__ void tile_body(const cx<T>* __restrict__ phi_src, cx<
 }
 
 template <typename T, bool TWO, int LR, bool GEN>
-__global__ __launch_bounds__(256, 2) void k_tile(cx<T>* __restrict__ phi, cx<T>* __restrict__ lam, const TileArgs a,
-                                                 const TOp* __restrict__ ops, const cx<T>* __restrict__ coef,
-                                                 const uint64_t* __restrict__ words,
+__global__ __launch_bounds__(256, 2) void k_tile(const cx<T>* phi_src, cx<T>* phi, cx<T>* __restrict__ lam,
+                                                 const TileArgs a, const TOp* __restrict__ ops,
+                                                 const cx<T>* __restrict__ coef, const uint64_t* __restrict__ words,
                                                  double* __restrict__ partials) {
-    tile_body<T, TWO, LR, GEN>(phi, phi, lam, a, ops, coef, words, partials, blockIdx.x, gridDim.x);
+    tile_body<T, TWO, LR, GEN>(phi_src, phi, lam, a, ops, coef, words, partials, blockIdx.x, gridDim.x);
 }
 
 // Batched passes: block b serves entry blk_entry[b] (one circuit's pass).
@@ -1092,9 +1114,9 @@ int tile_lds_bytes(int b, bool two, int elem_bytes, int nslots, int zt_n) {
 }
 
 template <typename T, bool TWO, int LR, bool GEN>
-static hipError_t launch_tile_lr(hipStream_t s, void* phi, void* lam, const TileArgs& a, const TOp* ops,
-                                 const void* coef, const uint64_t* words, double* partials, int grid, int nthr,
-                                 size_t lds) {
+static hipError_t launch_tile_lr(hipStream_t s, const void* phi_src, void* phi, void* lam, const TileArgs& a,
+                                 const TOp* ops, const void* coef, const uint64_t* words, double* partials, int grid,
+                                 int nthr, size_t lds) {
     static bool attr_set = false;
     if (lds > 65536 && !attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)k_tile<T, TWO, LR, GEN>,
@@ -1102,39 +1124,42 @@ static hipError_t launch_tile_lr(hipStream_t s, void* phi, void* lam, const Tile
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_tile<T, TWO, LR, GEN>), dim3(grid), dim3(nthr), lds, s, (cx<T>*)phi, (cx<T>*)lam, a, ops,
-                       (const cx<T>*)coef, words, partials);
+    hipLaunchKernelGGL((k_tile<T, TWO, LR, GEN>), dim3(grid), dim3(nthr), lds, s, (const cx<T>*)phi_src, (cx<T>*)phi,
+                       (cx<T>*)lam, a, ops, (const cx<T>*)coef, words, partials);
     return hipGetLastError();
 }
 
 template <typename T, bool TWO, bool GEN>
-static hipError_t launch_tile_two(hipStream_t s, void* phi, void* lam, const TileArgs& a, const TOp* ops,
-                                  const void* coef, const uint64_t* words, double* partials, int grid, int nthr,
-                                  int R, size_t lds) {
+static hipError_t launch_tile_two(hipStream_t s, const void* phi_src, void* phi, void* lam, const TileArgs& a,
+                                  const TOp* ops, const void* coef, const uint64_t* words, double* partials, int grid,
+                                  int nthr, int R, size_t lds) {
     switch (R) {
-    case 1: return launch_tile_lr<T, TWO, 0, GEN>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
-    case 2: return launch_tile_lr<T, TWO, 1, GEN>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
-    case 4: return launch_tile_lr<T, TWO, 2, GEN>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
-    case 8: return launch_tile_lr<T, TWO, 3, GEN>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
-    case 16: return launch_tile_lr<T, TWO, 4, GEN>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
-    case 32: return launch_tile_lr<T, TWO, 5, GEN>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
+    case 1: return launch_tile_lr<T, TWO, 0, GEN>(s, phi_src, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
+    case 2: return launch_tile_lr<T, TWO, 1, GEN>(s, phi_src, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
+    case 4: return launch_tile_lr<T, TWO, 2, GEN>(s, phi_src, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
+    case 8: return launch_tile_lr<T, TWO, 3, GEN>(s, phi_src, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
+    case 16: return launch_tile_lr<T, TWO, 4, GEN>(s, phi_src, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
+    case 32: return launch_tile_lr<T, TWO, 5, GEN>(s, phi_src, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T>
-hipError_t launch_tile(hipStream_t s, bool two, bool generic, void* phi, void* lam, const TileArgs& a,
-                       const TOp* ops, const void* coef, const uint64_t* words, double* partials, int grid, int nthr,
-                       int R, size_t lds_bytes) {
+hipError_t launch_tile(hipStream_t s, bool two, bool generic, const void* phi_src, void* phi, void* lam,
+                       const TileArgs& a, const TOp* ops, const void* coef, const uint64_t* words, double* partials,
+                       int grid, int nthr, int R, size_t lds_bytes) {
     if (two) {
         if (generic)
-            return launch_tile_two<T, true, true>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, R,
+            return launch_tile_two<T, true, true>(s, phi_src, phi, lam, a, ops, coef, words, partials, grid, nthr, R,
                                                   lds_bytes);
-        return launch_tile_two<T, true, false>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, R, lds_bytes);
+        return launch_tile_two<T, true, false>(s, phi_src, phi, lam, a, ops, coef, words, partials, grid, nthr, R,
+                                               lds_bytes);
     }
     if (generic)
-        return launch_tile_two<T, false, true>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, R, lds_bytes);
-    return launch_tile_two<T, false, false>(s, phi, lam, a, ops, coef, words, partials, grid, nthr, R, lds_bytes);
+        return launch_tile_two<T, false, true>(s, phi_src, phi, lam, a, ops, coef, words, partials, grid, nthr, R,
+                                               lds_bytes);
+    return launch_tile_two<T, false, false>(s, phi_src, phi, lam, a, ops, coef, words, partials, grid, nthr, R,
+                                            lds_bytes);
 }
 
 template <typename T, bool TWO, int LR, bool GEN>
@@ -1430,7 +1455,7 @@ hipError_t launch_reduce(hipStream_t s, const double* partials, int n_blocks, in
                                         uint64_t, int, const Mat4&);                                            \
     template hipError_t launch_gatek<T>(hipStream_t, void*, uint64_t, const Expand&, uint64_t, int,             \
                                         const int32_t*, const void*);                                           \
-    template hipError_t launch_tile<T>(hipStream_t, bool, bool, void*, void*, const TileArgs&, const TOp*,      \
+    template hipError_t launch_tile<T>(hipStream_t, bool, bool, const void*, void*, void*, const TileArgs&, const TOp*,      \
                                        const void*, const uint64_t*, double*, int, int, int, size_t);           \
     template hipError_t launch_pauli<T>(hipStream_t, bool, bool, const void*, void*, uint64_t,                  \
                                         const PauliGroupDev*, int, const PauliTermDev*, double*, int);          \

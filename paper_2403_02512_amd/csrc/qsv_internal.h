@@ -142,7 +142,8 @@ template <typename T> hipError_t launch_gate2(hipStream_t s, void* psi, uint64_t
                                               uint64_t setmask, uint64_t b0, uint64_t b1, int cls, const Mat4& m);
 template <typename T> hipError_t launch_gatek(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex,
                                               uint64_t setmask, int k, const int32_t* tbits, const void* mat);
-template <typename T> hipError_t launch_tile(hipStream_t s, bool two, bool generic, void* phi, void* lam, const TileArgs& a,
+template <typename T> hipError_t launch_tile(hipStream_t s, bool two, bool generic, const void* phi_src, void* phi,
+                                             void* lam, const TileArgs& a,
                                              const TOp* ops, const void* coef, const uint64_t* words,
                                              double* partials, int grid, int nthr, int R, size_t lds_bytes);
 template <typename T> hipError_t launch_tile_batch(hipStream_t s, bool two, bool generic, const TileEntry* entries,
