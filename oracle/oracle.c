@@ -562,3 +562,32 @@ fail:
     free(phi); free(lam); free(tmp);
     return -1;
 }
+
+/* ------------------------------------------------------------------ sampling */
+
+int orc_sample(int n, const double *psi, int64_t n_samples, const double *u, int64_t *out) {
+    const int64_t N = (int64_t)1 << n;
+    double *cdf = (double *)malloc((size_t)N * sizeof(double));
+    if (!cdf) return -1;
+    double run = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        run += psi[2 * i] * psi[2 * i] + psi[2 * i + 1] * psi[2 * i + 1];
+        cdf[i] = run;
+    }
+    if (!(run > 0.0)) {
+        free(cdf);
+        return -1;
+    }
+    for (int64_t k = 0; k < n_samples; ++k) {
+        const double t = u[k] * run;
+        int64_t lo = 0, hi = N - 1; /* smallest i with cdf[i] > t (cdf[N-1] = run > t) */
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if (cdf[mid] > t) hi = mid;
+            else lo = mid + 1;
+        }
+        out[k] = lo;
+    }
+    free(cdf);
+    return 0;
+}

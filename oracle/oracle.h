@@ -92,6 +92,12 @@ int orc_adjoint_jacobian(int n, const double *psi, const orc_op *ops, int64_t n_
 /* Number of OpenMP threads the oracle loops use (1 without OpenMP). */
 int orc_num_threads(void);
 
+/* Shot sampling by inverse transform (Sec. 4.3, sampling workloads): with
+ * p_i = |psi_i|^2 and the running sum c_i = p_0 + .. + p_i (index order,
+ * sequential FP64), out[k] = the smallest i with c_i > u[k] * c_{N-1}.  The
+ * uniforms u[k] in [0, 1) are inputs.  Returns -1 for a zero state. */
+int orc_sample(int n, const double *psi, int64_t n_samples, const double *u, int64_t *out);
+
 #ifdef __cplusplus
 }
 #endif

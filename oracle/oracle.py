@@ -72,6 +72,7 @@ def lib():
         L.orc_inner.restype = None
         L.orc_expval.argtypes = [ctypes.c_int, dp, ctypes.c_int, i32p, dp, ctypes.c_char_p, dp]
         L.orc_apply_pauli_sum.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, ctypes.c_char_p, dp]
+        L.orc_sample.argtypes = [ctypes.c_int, dp, ctypes.c_int64, dp, ctypes.POINTER(ctypes.c_int64)]
         L.orc_adjoint_jacobian.argtypes = [ctypes.c_int, dp, ctypes.POINTER(OrcOp), ctypes.c_int64, dp,
                                            ctypes.c_int64, dp, ctypes.c_int, i32p, dp, ctypes.c_char_p, dp]
         _lib = L
@@ -226,3 +227,15 @@ def adjoint_jacobian(psi: np.ndarray, ops, params, observables) -> np.ndarray:
                                   _dptr(coeff), words, _dptr(jac)) != 0:
         raise ValueError("oracle rejected an operation")
     return jac[:, :n_params]
+
+
+def sample(psi: np.ndarray, u) -> np.ndarray:
+    """Inverse-transform shot sampling with caller-supplied uniforms u in [0, 1)."""
+    n = int(np.log2(psi.size))
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
+    out = np.zeros(max(1, u.size), dtype=np.int64)
+    if lib().orc_sample(n, _dptr(psi), u.size, _dptr(u if u.size else np.zeros(1)),
+                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))) != 0:
+        raise ValueError("zero state")
+    return out[:u.size]

@@ -409,3 +409,48 @@ def test_last_rz_before_diagonal_observable_has_zero_gradient():
     last = [o for o in c.ops if o.name == "U3"][-6:]
     for o in last:
         assert abs(jac[o.param[1]]) < 1e-15
+
+
+# ------------------------------------------------------------------ sampling (Sec. 4.3 shots)
+
+def test_sample_basis_state_and_ghz_closed_forms():
+    for b in (0, 5, 7):
+        psi = oracle.zero_state(3, b)
+        assert np.all(oracle.sample(psi, [0.0, 0.3, 0.999]) == b)
+    g = W.ghz(3)
+    psi = oracle.apply(3, g.ops, g.params)
+    # p_0 = p_7 = 1/2, nothing in between: u < 1/2 -> 0, u >= 1/2 -> 7
+    assert list(oracle.sample(psi, [0.0, 0.25, 0.4999999, 0.5, 0.75, 0.9999])) == [0, 0, 0, 7, 7, 7]
+
+
+def test_sample_product_state_thresholds():
+    """RY product state: p(i) = prod_w p_w(bit of wire w), wire 0 = msb; every
+    u strictly inside [C(i-1), C(i)) maps to i (C from the closed form)."""
+    th = [0.7, 2.1, 1.3]
+    ops = [W.op("RY", [w], (w, 1.0)) for w in range(3)]
+    psi = oracle.apply(3, ops, np.array(th))
+    p1 = [math.sin(t / 2) ** 2 for t in th]
+    probs = []
+    for i in range(8):
+        pr = 1.0
+        for w in range(3):
+            bit = (i >> (2 - w)) & 1
+            pr *= p1[w] if bit else 1 - p1[w]
+        probs.append(pr)
+    C = np.cumsum(probs)
+    lo = np.concatenate([[0.0], C[:-1]])
+    mids = (lo + C) / 2
+    assert list(oracle.sample(psi, mids)) == list(range(8))
+    # just inside both ends of each interval
+    eps = 1e-9
+    assert list(oracle.sample(psi, lo + eps)) == list(range(8))
+    assert list(oracle.sample(psi, C - eps)) == list(range(8))
+
+
+def test_sample_frequencies_match_probabilities():
+    c = W.random_circuit(4, 30, seed=11)
+    psi = oracle.apply(4, c.ops, c.params)
+    p = np.abs(psi) ** 2
+    u = np.random.default_rng(0).random(40000)
+    counts = np.bincount(oracle.sample(psi, u), minlength=16) / u.size
+    assert np.all(np.abs(counts - p) <= 5 * np.sqrt(p * (1 - p) / u.size) + 1e-12)
