@@ -220,6 +220,17 @@ qsv_status qsv_expval_sparse(qsv_state *s, const int64_t *row_ptr, const int64_t
  * order.  Host output; synchronises the context stream. */
 qsv_status qsv_probs(qsv_state *s, const int32_t *wires, int n_wires, double *out);
 
+/* Shot sampling by inverse transform (paper Sec. 4.3, sampling workloads):
+ * with p_i = |psi_i|^2, out[k] = the basis index i at which the running sum
+ * p_0 + .. + p_i first exceeds u[k] * sum_j p_j.  The uniforms u[k] in [0, 1)
+ * come from the caller's generator (host array of n_samples doubles); out is
+ * a host array of n_samples indices (wire 0 = most significant bit).  Only
+ * indices with p_i > 0 are returned; where a u[k] lands within rounding of a
+ * boundary of the running sum either neighbour may be returned.  Errors:
+ * QSV_ERR_ARG for NULL arrays, u outside [0, 1) or a zero state.
+ * Synchronises the context stream. */
+qsv_status qsv_sample(qsv_state *s, const double *u, size_t n_samples, uint64_t *out);
+
 /* Adjoint-method Jacobian (paper Sec. 2.1 and Sec. 3.1.1; Jones & Gacon):
  * jac[o*n_params + p] = d<psi|H_o|psi>/d params[p], where s holds the state
  * AFTER the ops.  The forward states are recomputed by un-applying the gates.
@@ -266,6 +277,19 @@ void qsv_batch_destroy(qsv_batch *b);
  * outputs; synchronises the context stream. */
 #define QSV_BATCH_GRAPH 1u
 qsv_status qsv_batch_run(qsv_batch *b, const double *params, double *expval, double *grad, uint32_t flags);
+
+/* ---------------------------------------------------------------- tile-width tuner */
+/* Choose the LDS tile widths (QSV_OPT_TILE_BITS and QSV_OPT_TILE_BITS_ADJ) for
+ * a circuit by timing it on this device (paper Sec. 4.2: batch and chunk sizes
+ * chosen per workload): the forward program (reset to |0..0> + ops) for
+ * every width from 2^10 amplitudes up to the LDS limit, then, if obs and
+ * parameters are given, the adjoint sweep for every two-vector width from
+ * 2^9 up.  The fastest widths are set on the context and returned.  The
+ * state's contents are overwritten (it ends as the circuit's output state).
+ * On error the context options are left unchanged. */
+qsv_status qsv_autotune(qsv_state *s, const qsv_op *ops, size_t n_ops, const double *params, size_t n_params,
+                        const double *matrices, size_t n_matrix_elems, const qsv_pauli_sum *obs, size_t n_obs,
+                        int32_t *tile_bits, int32_t *tile_bits_adj);
 
 #ifdef __cplusplus
 }

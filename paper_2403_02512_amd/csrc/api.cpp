@@ -3,6 +3,7 @@
 // Jacobian (paper Sec. 2.1-2.2; the adjoint method of Jones & Gacon cited in
 // Sec. 2.1 and Sec. 3.1.1).
 #include <algorithm>
+#include <chrono>
 #include <atomic>
 #include <exception>
 #include <thread>
@@ -47,7 +48,8 @@ struct qsv_ctx {
     std::string err;
     int64_t opt_fusion = 1, opt_tile_bits = 0, opt_tile_bits_adj = 0, opt_low_bits = 0, opt_profile = 0,
             opt_nontemporal = 0, opt_layers = 1;
-    DevBuf ops, coef, words, partials, slots, pgroups, pterms, ws0, ws1, binbits, csr_ptr, csr_col, csr_val;
+    DevBuf ops, coef, words, partials, slots, pgroups, pterms, ws0, ws1, binbits, csr_ptr, csr_col, csr_val, smp_chunk,
+        smp_resid, smp_out;
     void* pin = nullptr;
     size_t pin_bytes = 0;
     hipEvent_t pin_ev = nullptr;
@@ -1166,7 +1168,7 @@ void qsv_ctx_destroy(qsv_ctx* c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     for (DevBuf* b : {&c->ops, &c->coef, &c->words, &c->partials, &c->slots, &c->pgroups, &c->pterms, &c->ws0, &c->ws1,
-                      &c->binbits, &c->csr_ptr, &c->csr_col, &c->csr_val})
+                      &c->binbits, &c->csr_ptr, &c->csr_col, &c->csr_val, &c->smp_chunk, &c->smp_resid, &c->smp_out})
         release(*b);
     if (c->pin) (void)hipHostFree(c->pin);
     for (auto& r : c->recs) {
@@ -1251,7 +1253,7 @@ qsv_status qsv_ctx_workspace_bytes(qsv_ctx* c, size_t* out) {
         if (!c || !out) fail(QSV_ERR_ARG, "NULL argument");
         size_t t = 0;
         for (DevBuf* b : {&c->ops, &c->coef, &c->words, &c->partials, &c->slots, &c->pgroups, &c->pterms, &c->ws0, &c->ws1,
-                          &c->binbits, &c->csr_ptr, &c->csr_col, &c->csr_val})
+                          &c->binbits, &c->csr_ptr, &c->csr_col, &c->csr_val, &c->smp_chunk, &c->smp_resid, &c->smp_out})
             t += b->bytes;
         *out = t;
     });
@@ -1641,6 +1643,65 @@ qsv_status qsv_probs(qsv_state* s, const int32_t* wires, int n_wires, double* ou
         Timed tr(c, KK_REDUCE, 8.0 * nb * gx);
         tr.done(launch_reduce(c->stream, (const double*)c->partials.p, gx, nb, (double*)c->slots.p));
         HIPCHK(hipMemcpyAsync(out, c->slots.p, (size_t)nb * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    });
+}
+
+qsv_status qsv_sample(qsv_state* s, const double* u, size_t n_samples, uint64_t* out) {
+    qsv_ctx* c = s ? s->ctx : nullptr;
+    return guard(c, [&] {
+        state_ctx(s);
+        if (n_samples == 0) return;
+        if (!u || !out) fail(QSV_ERR_ARG, "NULL argument");
+        for (size_t k = 0; k < n_samples; ++k)
+            if (!(u[k] >= 0.0 && u[k] < 1.0)) fail(QSV_ERR_ARG, "uniforms must lie in [0, 1)");
+        const int n = s->n;
+        // chunks of >= 64 amplitudes, at most 2^16 of them
+        const int clog2 = n <= 6 ? n : std::max(6, n - 16);
+        const uint64_t n_chunks = 1ull << (n - clog2);
+        set_device(c);
+        ensure(c, c->partials, n_chunks * 8);
+        const bool c128 = s->dt == QSV_C128;
+        {
+            Timed t(c, KK_SAMPLE, (double)((1ull << n) * elem_bytes(s->dt)));
+            t.done(c128 ? launch_chunk_norms<double>(c->stream, s->ptr, clog2, n_chunks, (double*)c->partials.p)
+                        : launch_chunk_norms<float>(c->stream, s->ptr, clog2, n_chunks, (double*)c->partials.p));
+        }
+        std::vector<double> cs(n_chunks);
+        HIPCHK(hipMemcpyAsync(cs.data(), c->partials.p, n_chunks * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        // inclusive running sums over chunks in index order
+        std::vector<double> incl(n_chunks);
+        double run = 0.0;
+        size_t last_nz = 0;
+        for (uint64_t i = 0; i < n_chunks; ++i) {
+            run += cs[i];
+            incl[i] = run;
+            if (cs[i] > 0.0) last_nz = i;
+        }
+        if (!(run > 0.0)) fail(QSV_ERR_ARG, "the state has zero norm");
+        std::vector<int64_t> ch(n_samples);
+        std::vector<double> rs(n_samples);
+        for (size_t k = 0; k < n_samples; ++k) {
+            const double t = u[k] * run;
+            size_t j = (size_t)(std::upper_bound(incl.begin(), incl.end(), t) - incl.begin());
+            if (j >= n_chunks) j = last_nz;  // t rounded up to the total
+            ch[k] = (int64_t)j;
+            rs[k] = t - (j ? incl[j - 1] : 0.0);
+        }
+        upload(c, {{&c->smp_chunk, ch.data(), n_samples * 8}, {&c->smp_resid, rs.data(), n_samples * 8}});
+        ensure(c, c->smp_out, n_samples * 8);
+        {
+            Timed t(c, KK_SAMPLE, (double)n_samples * 64.0 * (double)((1ull << clog2) / 64 + 1) *
+                                      (double)elem_bytes(s->dt));
+            t.done(c128 ? launch_sample<double>(c->stream, s->ptr, clog2, (const int64_t*)c->smp_chunk.p,
+                                                (const double*)c->smp_resid.p, (uint64_t*)c->smp_out.p,
+                                                (int64_t)n_samples)
+                        : launch_sample<float>(c->stream, s->ptr, clog2, (const int64_t*)c->smp_chunk.p,
+                                               (const double*)c->smp_resid.p, (uint64_t*)c->smp_out.p,
+                                               (int64_t)n_samples));
+        }
+        HIPCHK(hipMemcpyAsync(out, c->smp_out.p, n_samples * 8, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
     });
 }
@@ -2169,3 +2230,74 @@ qsv_status qsv_batch_run(qsv_batch* B, const double* params, double* expval, dou
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ tile-width tuner
+
+extern "C" qsv_status qsv_autotune(qsv_state* s, const qsv_op* ops, size_t n_ops, const double* params,
+                                   size_t n_params, const double* matrices, size_t n_mat, const qsv_pauli_sum* obs,
+                                   size_t n_obs, int32_t* tile_bits, int32_t* tile_bits_adj) {
+    qsv_ctx* c = s ? s->ctx : nullptr;
+    return guard(c, [&] {
+        state_ctx(s);
+        validate_ops_impl(s->n, ops, n_ops, n_params, n_mat, params, matrices);
+        validate_obs_impl(s->n, obs, n_obs);
+        if (!tile_bits || !tile_bits_adj) fail(QSV_ERR_ARG, "NULL argument");
+        set_device(c);
+        const bool c128 = s->dt == QSV_C128;
+        const int n = s->n;
+        auto check = [&](qsv_status st) {
+            if (st != QSV_OK) fail(st, c->err);
+        };
+        auto seconds = [&](auto&& fn) {
+            fn();  // warm-up (plans, uploads, first-launch costs)
+            check(qsv_ctx_synchronize(c));
+            double best = 1e300;
+            for (int rep = 0; rep < 2; ++rep) {
+                const auto t0 = std::chrono::steady_clock::now();
+                fn();
+                check(qsv_ctx_synchronize(c));
+                best = std::min(best, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+            }
+            return best;
+        };
+        const int64_t keep_f = c->opt_tile_bits, keep_a = c->opt_tile_bits_adj;
+        // candidates: tiles from 2^10 amplitudes up to the LDS limit of two
+        // blocks (one vector) or one block (two vectors) per CU, capped at n
+        const int fmax = std::min(n, c128 ? 13 : 13), amax = std::min(n, c128 ? 12 : 13);
+        int best_f = 0, best_a = 0;
+        try {
+            double tb = 1e300;
+            for (int b = std::min(fmax, 10); b <= fmax; ++b) {
+                c->opt_tile_bits = b;
+                const double t = seconds([&] {
+                    check(qsv_state_reset(s, 0));
+                    check(qsv_apply(s, ops, n_ops, params, n_params, matrices, n_mat));
+                });
+                if (t < tb) tb = t, best_f = b;
+            }
+            c->opt_tile_bits = best_f;
+            check(qsv_state_reset(s, 0));
+            check(qsv_apply(s, ops, n_ops, params, n_params, matrices, n_mat));
+            if (n_obs && n_params) {
+                std::vector<double> jac(n_obs * n_params), ev(n_obs);
+                double ta = 1e300;
+                for (int b = std::min(amax, 9); b <= amax; ++b) {
+                    c->opt_tile_bits_adj = b;
+                    const double t = seconds([&] {
+                        check(qsv_adjoint_jacobian(s, ops, n_ops, params, n_params, matrices, n_mat, obs, n_obs,
+                                                   jac.data(), ev.data(), 0));
+                    });
+                    if (t < ta) ta = t, best_a = b;
+                }
+            }
+        } catch (...) {
+            c->opt_tile_bits = keep_f;
+            c->opt_tile_bits_adj = keep_a;
+            throw;
+        }
+        c->opt_tile_bits = best_f;
+        c->opt_tile_bits_adj = best_a ? best_a : keep_a;
+        *tile_bits = (int32_t)c->opt_tile_bits;
+        *tile_bits_adj = (int32_t)c->opt_tile_bits_adj;
+    });
+}

@@ -24,7 +24,8 @@
 namespace qsv {
 
 const char* const kKernelNames[KK_COUNT] = {"init",  "gate1", "diag1",        "gate2",        "gatek", "tile1",
-                                            "tile2", "pauli_expval", "pauli_lambda", "reduce", "copy",  "probs", "sparse_expval"};
+                                            "tile2", "pauli_expval", "pauli_lambda", "reduce", "copy",  "probs", "sparse_expval",
+                                            "sample"};
 
 template <typename T>
 struct alignas(2 * sizeof(T)) cx {
@@ -1366,6 +1367,104 @@ hipError_t launch_probs(hipStream_t s, const void* psi, uint64_t n_rest, const E
     return hipSuccess;
 }
 
+// ------------------------------------------------------------------ shot sampling
+
+// |psi|^2 summed over each chunk of 2^clog2 amplitudes (one block per chunk).
+template <typename T>
+__global__ __launch_bounds__(256) void k_chunk_norms(const cx<T>* __restrict__ psi, int clog2,
+                                                     double* __restrict__ sums) {
+    __shared__ double red[64];
+    const uint64_t len = 1ull << clog2, base = (uint64_t)blockIdx.x << clog2;
+    double s = 0.0;
+    for (uint64_t j = threadIdx.x; j < len; j += 256) {
+        const cx<T> a = psi[base + j];
+        s += (double)a.re * a.re + (double)a.im * a.im;
+    }
+    double tot = 0.0;
+    block_add(s, red, &tot, threadIdx.x, 256);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// One wavefront per sample: inside chunk chunk[k], the first index whose
+// running |psi|^2 sum exceeds resid[k].  Lanes own consecutive segments; a
+// lane-ordered prefix over the segment totals picks the segment, whose lane
+// then walks it.  Where rounding leaves no index above resid, the last
+// amplitude with non-zero probability of the last non-empty segment is taken,
+// so only indices of non-zero probability are ever returned.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sample(const cx<T>* __restrict__ psi, int clog2,
+                                                const int64_t* __restrict__ chunk, const double* __restrict__ resid,
+                                                uint64_t* __restrict__ out, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (k >= n) return;  // uniform per wavefront
+    const uint64_t len = 1ull << clog2;
+    const uint64_t seg = len >= 64 ? len >> 6 : 1;
+    const uint64_t base = (uint64_t)chunk[k] << clog2;
+    const uint64_t lo = (uint64_t)lane * seg;
+    double s = 0.0;
+    if (lo < len)
+        for (uint64_t j = 0; j < seg; ++j) {
+            const cx<T> a = psi[base + lo + j];
+            s += (double)a.re * a.re + (double)a.im * a.im;
+        }
+    double incl = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    double excl = __shfl_up(incl, 1, 64);
+    if (lane == 0) excl = 0.0;
+    const double r = resid[k];
+    const uint64_t hit = __ballot(incl > r);
+    int pick;
+    if (hit) {
+        pick = __ffsll((unsigned long long)hit) - 1;
+    } else {
+        const uint64_t nz = __ballot(s > 0.0);
+        pick = nz ? 63 - __clzll((long long)nz) : 0;
+    }
+    if (lane == pick) {
+        double acc = excl;
+        uint64_t idx = lo, last_nz = lo;
+        bool found = false;
+        for (uint64_t j = 0; j < seg && lo + j < len; ++j) {
+            const cx<T> a = psi[base + lo + j];
+            const double p = (double)a.re * a.re + (double)a.im * a.im;
+            if (p > 0.0) last_nz = lo + j;
+            acc += p;
+            if (acc > r) {
+                idx = lo + j;
+                found = true;
+                break;
+            }
+        }
+        out[k] = base + (found ? idx : last_nz);
+    }
+}
+
+template <typename T>
+hipError_t launch_chunk_norms(hipStream_t s, const void* psi, int clog2, uint64_t n_chunks, double* sums) {
+    hipLaunchKernelGGL(k_chunk_norms<T>, dim3((unsigned)n_chunks), dim3(256), 0, s, (const cx<T>*)psi, clog2, sums);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sample(hipStream_t s, const void* psi, int clog2, const int64_t* chunk, const double* resid,
+                         uint64_t* out, int64_t n) {
+    const int64_t blocks = (n + 3) / 4;
+    for (int64_t b0 = 0; b0 < blocks; b0 += (1 << 30)) {
+        const int64_t nb = blocks - b0 < (1 << 30) ? blocks - b0 : (1 << 30);
+        const int64_t k0 = b0 * 4;
+        hipLaunchKernelGGL(k_sample<T>, dim3((unsigned)nb), dim3(256), 0, s, (const cx<T>*)psi, clog2, chunk + k0,
+                           resid + k0, out + k0, n - k0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // ------------------------------------------------------------------ sparse Hamiltonian
 
 // <psi|S|psi> for a CSR matrix S (rows = basis indices): one row per thread,
@@ -1467,7 +1566,10 @@ hipError_t launch_reduce(hipStream_t s, const double* partials, int n_blocks, in
     template hipError_t launch_pauli_batch<T>(hipStream_t, bool, const PauliEntry*, const int32_t*,             \
                                               const PauliGroupDev*, const PauliTermDev*, double*, int);         \
     template hipError_t launch_sparse<T>(hipStream_t, const void*, uint64_t, const int64_t*, const int64_t*,    \
-                                         const double*, double*, int);
+                                         const double*, double*, int);                                          \
+    template hipError_t launch_chunk_norms<T>(hipStream_t, const void*, int, uint64_t, double*);              \
+    template hipError_t launch_sample<T>(hipStream_t, const void*, int, const int64_t*, const double*,          \
+                                         uint64_t*, int64_t);
 
 QSV_INST(double)
 QSV_INST(float)

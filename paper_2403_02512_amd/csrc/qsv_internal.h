@@ -123,7 +123,7 @@ struct PauliTermDev {
 
 enum KernelKind : int {
     KK_INIT = 0, KK_GATE1, KK_DIAG1, KK_GATE2, KK_GATEK, KK_TILE1, KK_TILE2,
-    KK_PAULI, KK_PAULI_LAMBDA, KK_REDUCE, KK_COPY, KK_PROBS, KK_SPARSE, KK_COUNT
+    KK_PAULI, KK_PAULI_LAMBDA, KK_REDUCE, KK_COPY, KK_PROBS, KK_SPARSE, KK_SAMPLE, KK_COUNT
 };
 extern const char* const kKernelNames[KK_COUNT];
 
@@ -159,6 +159,10 @@ template <typename T> hipError_t launch_pauli(hipStream_t s, bool write_lambda, 
                                               const PauliTermDev* terms, double* partials, int grid);
 template <typename T> hipError_t launch_sparse(hipStream_t s, const void* psi, uint64_t N, const int64_t* row_ptr,
                                                const int64_t* col, const double* val, double* partials, int grid);
+template <typename T> hipError_t launch_chunk_norms(hipStream_t s, const void* psi, int clog2, uint64_t n_chunks,
+                                                    double* sums);
+template <typename T> hipError_t launch_sample(hipStream_t s, const void* psi, int clog2, const int64_t* chunk,
+                                               const double* resid, uint64_t* out, int64_t n);
 template <typename T> hipError_t launch_probs(hipStream_t s, const void* psi, uint64_t n_rest, const Expand& ex,
                                               const uint64_t* binbits, int n_bins, int gx, double* partials);
 hipError_t launch_reduce(hipStream_t s, const double* partials, int n_blocks, int n_slots, double* out);

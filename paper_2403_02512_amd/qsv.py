@@ -79,7 +79,8 @@ EXPORTS = [
     "qsv_state_destroy", "qsv_state_n_qubits", "qsv_state_device_ptr", "qsv_state_reset", "qsv_state_copy",
     "qsv_state_to_host", "qsv_state_from_host", "qsv_validate_ops", "qsv_validate_obs", "qsv_apply",
     "qsv_expval", "qsv_adjoint_jacobian", "qsv_adjoint_vjp", "qsv_plan_stats", "qsv_plan_json", "qsv_var",
-    "qsv_probs", "qsv_expval_sparse", "qsv_batch_create", "qsv_batch_destroy", "qsv_batch_run",
+    "qsv_probs", "qsv_expval_sparse", "qsv_batch_create", "qsv_batch_destroy", "qsv_batch_run", "qsv_sample",
+    "qsv_autotune",
 ]
 
 
@@ -127,6 +128,9 @@ def lib():
                               ctypes.POINTER(sz), dp, sz, obp, ctypes.POINTER(vp)], i32),
         "qsv_batch_destroy": ([vp], None),
         "qsv_batch_run": ([vp, dp, dp, dp, u32], i32),
+        "qsv_sample": ([vp, dp, sz, ctypes.POINTER(u64)], i32),
+        "qsv_autotune": ([vp, opp, sz, dp, sz, dp, sz, obp, sz, ctypes.POINTER(ctypes.c_int32),
+                          ctypes.POINTER(ctypes.c_int32)], i32),
     }
     for name in EXPORTS:
         f = getattr(L, name)
@@ -437,6 +441,28 @@ def probs(state: State, wires: Sequence[int]) -> np.ndarray:
     _check(lib().qsv_probs(state.h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(w), _dptr(out)),
            state.ctx.h)
     return out
+
+
+def autotune(state: State, ops, params, observables=()) -> tuple:
+    """Time the circuit (and its adjoint, if observables are given) for each
+    LDS tile width, set the fastest on the context; -> (tile_bits,
+    tile_bits_adj).  Overwrites the state with the circuit's output."""
+    m = MarshalledOps(ops, params)
+    mo = MarshalledObs(list(observables))
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().qsv_autotune(state.h, m.arr, m.n, _dptr(m.params), m.n_params, m.mat_ptr(), m.n_mat, mo.arr, mo.n,
+                              ctypes.byref(a), ctypes.byref(b)), state.ctx.h)
+    return a.value, b.value
+
+
+def sample(state: State, u) -> np.ndarray:
+    """Basis indices drawn from |psi|^2 by inverse transform of the caller's
+    uniforms u in [0, 1)."""
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
+    out = np.zeros(max(1, u.size), dtype=np.uint64)
+    _check(lib().qsv_sample(state.h, _dptr(u if u.size else np.zeros(1)), u.size,
+                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))), state.ctx.h)
+    return out[:u.size].astype(np.int64)
 
 
 def adjoint_jacobian(state: State, ops, params, observables, inplace: bool = False,
