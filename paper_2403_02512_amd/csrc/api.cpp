@@ -383,6 +383,7 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
     for (int r = 0; r < R; ++r) a.offhi[r] = deposit((uint64_t)r << nthr_log2, sb, b);
     for (int j = 0; j < b; ++j) a.sb[j] = sb[j];
     a.b = b;
+    a.n_outer = n - b;
     a.nthr_log2 = nthr_log2;
     a.op0 = (int)P.tops.size();
     st.nthr = nthr;
@@ -538,6 +539,11 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
                     P.words.push_back(parity_bits_host(deposit((uint64_t)t, sb, nthr_log2), pr.z));
                 for (int r = 0; r < R; ++r) P.words.push_back(parity_bits_host(a.offhi[r], pr.z));
             }
+            // per index bit outside the tile (ascending = bit k of the tile
+            // number): its parity column; the tile base's parity bits are the
+            // XOR of the columns of the tile number's set bits (linear over GF(2))
+            for (int g = 0; g < n; ++g)
+                if (!((pass.S >> g) & 1)) P.words.push_back(parity_bits_host(1ull << g, pr.z));
             if (pr.kind == Proto::ZPHASE) {
                 const int m = (int)pr.z.size();
                 zpatch.push_back({P.tops.size(), (int)ztab.size()});
@@ -673,7 +679,10 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
                         for (int p = 0; p < GB; ++p) {
                             op.tb[p] = -1;
                             mats[p] = {1.0, 0.0, 0.0, 1.0};
-                            if (lg[p] >= 0) mats[p] = maybe_dag(F[protos[lg[p]].f].m, 2, dagger);
+                            if (lg[p] >= 0) {
+                                mats[p] = maybe_dag(F[protos[lg[p]].f].m, 2, dagger);
+                                op.m |= 1 << p;
+                            }
                             const auto& m = mats[p];
                             real = real && m[0].imag() == 0 && m[1].imag() == 0 && m[2].imag() == 0 &&
                                    m[3].imag() == 0;
@@ -1431,9 +1440,9 @@ qsv_status qsv_plan_json(int n, qsv_dtype dt, const qsv_op* ops, size_t n_ops, c
             if (st.type == Step::TILE) {
                 const TileArgs& a = st.ta;
                 add(",\"b\":%d,\"nthr\":%d,\"R\":%d,\"grid\":%d,\"op0\":%d,\"nops\":%d,\"nslots\":%d,\"slot_base\":%d,"
-                    "\"generic\":%d,\"n_tiles\":%llu,\"sb\":[",
+                    "\"generic\":%d,\"n_tiles\":%llu,\"n_outer\":%d,\"sb\":[",
                     a.b, st.nthr, st.R, st.grid, a.op0, a.nops, a.nslots, st.slot_base, (int)st.generic,
-                    (unsigned long long)a.n_tiles);
+                    (unsigned long long)a.n_tiles, a.n_outer);
                 for (int j = 0; j < a.b; ++j) add(j ? ",%d" : "%d", a.sb[j]);
                 js += "],\"offhi\":[";
                 for (int r = 0; r < st.R; ++r) add(r ? ",%llu" : "%llu", (unsigned long long)a.offhi[r]);

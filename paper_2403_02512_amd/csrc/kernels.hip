@@ -334,10 +334,12 @@ struct TileCtx {
     double* sacc;
     const cx<T>* coef;
     const uint64_t* words;
-    uint64_t base, offlo;
+    uint64_t base, offlo, tile;
     const uint64_t* offhi;
+    int n_outer;
     const cx<T>* ztab;  // the pass's phase tables, in LDS
     int tid, nthr, nwaves;
+    int nacc;  // slot accumulator entries per slot: one per 16-lane row (or 1)
 };
 
 template <typename T, bool TWO, int R>
@@ -470,10 +472,13 @@ __device__ __forceinline__ void tile_diag(const TileCtx<T, TWO, R>& c, const TOp
     }
 }
 
-// parity masks of the op's z masks for this tile's base (uniform)
-__device__ __forceinline__ uint64_t parity_bits(uint64_t x, const uint64_t* z, int m) {
+// Parity bits (bit j = parity of base & z_j) of this tile's base index: the
+// map is linear over GF(2), so it is the XOR of the host's per-outer-bit
+// columns over the set bits of the tile number (uniform, scalar unit).
+__device__ __forceinline__ uint64_t tile_parity(uint64_t tile, const uint64_t* __restrict__ cols, int n_outer) {
     uint64_t p = 0;
-    for (int j = 0; j < m; ++j) p |= (uint64_t)(__popcll(x & z[j]) & 1) << j;
+    for (int k = 0; k < n_outer; ++k)
+        if ((tile >> k) & 1) p ^= cols[k];
     return p;
 }
 
@@ -483,7 +488,7 @@ __device__ __forceinline__ uint64_t parity_bits(uint64_t x, const uint64_t* z, i
 template <typename T, bool TWO, int R>
 __device__ __forceinline__ void tile_zphase(const TileCtx<T, TWO, R>& c, const TOp& op) {
     const uint64_t* w = c.words + op.woff;
-    const uint64_t pb = parity_bits(c.base, w, op.m);
+    const uint64_t pb = tile_parity(c.tile, w + op.m + c.nthr + R, c.n_outer);
     const uint64_t pl = w[op.m + c.tid] ^ pb;
     const uint64_t* ph = w + op.m + c.nthr;
 #pragma unroll
@@ -538,7 +543,7 @@ __device__ __forceinline__ void tile_dot(const TileCtx<T, TWO, R>& c, const TOp&
             }
         } else {  // OP_DOTZSUM: generator sum_j Z^{z_j}, eigenvalue m - 2 * (odd count)
             const uint64_t* w = c.words + op.woff;
-            const uint64_t pb = parity_bits(c.base, w, op.m);
+            const uint64_t pb = tile_parity(c.tile, w + op.m + c.nthr + R, c.n_outer);
             const uint64_t pl = w[op.m + c.tid] ^ pb;
             const uint64_t* ph = w + op.m + c.nthr;
 #pragma unroll
@@ -548,7 +553,7 @@ __device__ __forceinline__ void tile_dot(const TileCtx<T, TWO, R>& c, const TOp&
                 acc += (double)(op.m - 2 * cnt) * im_conj_mul(c.tl[sw(t)], c.tp[sw(t)]);
             }
         }
-        block_add(acc, c.red, c.sacc + op.slot * c.nwaves, c.tid, c.nthr);
+        block_add(acc, c.red, c.sacc + op.slot * c.nacc, c.tid, c.nthr);
     }
 }
 
@@ -707,8 +712,8 @@ struct DotAcc {
 // flow through without merges.  Per position p the coefficients are
 // [generator (GCLS == DENSE only)] then the 2x2 matrix.
 template <typename T, bool TWO, int GB, int CLS, int GCLS, int P>
-__device__ __forceinline__ void g_layer_pos(cx<T>* a, cx<T>* l, const cx<T>* m, uint32_t dmask, DotAcc& acc,
-                                            int& ai) {
+__device__ __forceinline__ void g_layer_pos(cx<T>* a, cx<T>* l, const cx<T>* m, uint32_t dmask, uint32_t gmask,
+                                            DotAcc& acc, int& ai) {
     constexpr int NC = GCLS == MC_DENSE ? 8 : 4;
     const cx<T>* mp = m + P * NC;
     if constexpr (TWO && GCLS != 0) {
@@ -717,16 +722,21 @@ __device__ __forceinline__ void g_layer_pos(cx<T>* a, cx<T>* l, const cx<T>* m, 
             ++ai;
         }
     }
+    // unconditional: positions without a gate hold the identity, which keeps
+    // the layer branch-free (a skipped position would merge two versions of
+    // the register arrays)
+    (void)gmask;
     g_apply1<T, TWO, GB, P, CLS, false>(a, l, mp + (GCLS == MC_DENSE ? 4 : 0), 0, nullptr, 0, 0);
 }
 
 template <typename T, bool TWO, int GB, int CLS, int GCLS>
-__device__ __forceinline__ void g_layer(cx<T>* a, cx<T>* l, const cx<T>* m, uint32_t dmask, DotAcc& acc, int acc0) {
+__device__ __forceinline__ void g_layer(cx<T>* a, cx<T>* l, const cx<T>* m, uint32_t dmask, uint32_t gmask,
+                                        DotAcc& acc, int acc0) {
     int ai = acc0;
-    g_layer_pos<T, TWO, GB, CLS, GCLS, 0>(a, l, m, dmask, acc, ai);
-    if constexpr (GB > 1) g_layer_pos<T, TWO, GB, CLS, GCLS, 1>(a, l, m, dmask, acc, ai);
-    if constexpr (GB > 2) g_layer_pos<T, TWO, GB, CLS, GCLS, 2>(a, l, m, dmask, acc, ai);
-    if constexpr (GB > 3) g_layer_pos<T, TWO, GB, CLS, GCLS, 3>(a, l, m, dmask, acc, ai);
+    g_layer_pos<T, TWO, GB, CLS, GCLS, 0>(a, l, m, dmask, gmask, acc, ai);
+    if constexpr (GB > 1) g_layer_pos<T, TWO, GB, CLS, GCLS, 1>(a, l, m, dmask, gmask, acc, ai);
+    if constexpr (GB > 2) g_layer_pos<T, TWO, GB, CLS, GCLS, 2>(a, l, m, dmask, gmask, acc, ai);
+    if constexpr (GB > 3) g_layer_pos<T, TWO, GB, CLS, GCLS, 3>(a, l, m, dmask, gmask, acc, ai);
 }
 
 #define QSV_P1_CASES(F)                                  \
@@ -845,7 +855,7 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
                 break;
             case OP_LAYER1: {
                 const int gcls = TWO ? (int)s.lcval : 0;
-#define L(C, G) g_layer<T, TWO, GB, C, G>(a, l, m, s.lcmask, acc, s.aux)
+#define L(C, G) g_layer<T, TWO, GB, C, G>(a, l, m, s.lcmask, (uint32_t)s.m, acc, s.aux)
                 if (gcls == 0) {
                     if (s.cls == MC_REAL) L(MC_REAL, 0);
                     else if (s.cls == MC_RIRI) L(MC_RIRI, 0);
@@ -881,7 +891,7 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
                 break;
             case OP_ZPHASE: {
                 const uint64_t* z = c.words + s.woff;
-                const uint64_t pc = parity_bits(c.base, z, s.m) ^ z[s.m + sc];
+                const uint64_t pc = tile_parity(c.tile, z + s.m + nsub + E, c.n_outer) ^ z[s.m + sc];
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const cx<T> d = c.ztab[s.aux + (int)__popcll(pc ^ z[s.m + nsub + e])];
@@ -931,7 +941,7 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
                         }
                     } else {  // OP_DOTZSUM
                         const uint64_t* z = c.words + s.woff;
-                        const uint64_t pc = parity_bits(c.base, z, s.m) ^ z[s.m + sc];
+                        const uint64_t pc = tile_parity(c.tile, z + s.m + nsub + E, c.n_outer) ^ z[s.m + sc];
 #pragma unroll
                         for (int e = 0; e < E; ++e)
                             v += (double)(s.m - 2 * (int)__popcll(pc ^ z[s.m + nsub + e])) * im_conj_mul(l[e], a[e]);
@@ -950,13 +960,19 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
     if constexpr (TWO) {
         // flush: per-wave sums into the wave's accumulator (no barrier when
         // the block is made of whole waves)
+        // per 16-lane row: DPP prefix sums leave the row's total in its last
+        // lane, which adds it to the row's own accumulator (no cross-row
+        // traffic; the block sums the rows once at the end)
         auto flush = [&](int ai, int slot) {
-            const double v = acc.get(ai);
+            double v = acc.get(ai);
             if (c.nthr >= 64) {
-                const double tot = wave_sum(v);
-                if ((c.tid & 63) == 0) c.sacc[slot * c.nwaves + (c.tid >> 6)] += tot;
+                v += row_shr<1>(v);
+                v += row_shr<2>(v);
+                v += row_shr<4>(v);
+                v += row_shr<8>(v);
+                if ((c.tid & 15) == 15) c.sacc[slot * c.nacc + (c.tid >> 4)] += v;
             } else {
-                block_add(v, c.red, c.sacc + slot * c.nwaves, c.tid, c.nthr);
+                block_add(v, c.red, c.sacc + slot * c.nacc, c.tid, c.nthr);
             }
         };
         for (int si = 0; si < g.m; ++si) {
@@ -1003,12 +1019,14 @@ __device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
     c.coef = coef;
     c.words = words;
     c.offhi = a.offhi;
+    c.n_outer = a.n_outer;
     c.tid = tid;
     c.nthr = nthr;
     c.nwaves = nthr >= 64 ? nthr >> 6 : 1;
+    c.nacc = nthr >= 64 ? nthr >> 4 : 1;
     {
         // phase tables after the per-wave slot accumulators, 16-byte aligned
-        const size_t off = (64 + (size_t)a.nslots * c.nwaves) * sizeof(double);
+        const size_t off = (64 + (size_t)a.nslots * c.nacc) * sizeof(double);
         cx<T>* zt = reinterpret_cast<cx<T>*>(reinterpret_cast<unsigned char*>(c.red) + ((off + 15) & ~(size_t)15));
         for (int i = tid; i < a.zt_n; i += nthr) zt[i] = coef[a.zt_off + i];
         c.ztab = zt;
@@ -1016,12 +1034,13 @@ __device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
     uint64_t offlo = 0;
     for (int j = 0; j < a.nthr_log2; ++j) offlo |= (uint64_t)((tid >> j) & 1) << a.sb[j];
     c.offlo = offlo;
-    for (int s = tid; s < a.nslots * c.nwaves; s += nthr) c.sacc[s] = 0.0;
+    for (int s = tid; s < a.nslots * c.nacc; s += nthr) c.sacc[s] = 0.0;
     const bool synth = (a.flags & TILE_SYNTH) != 0;
 
     for (uint64_t tile = blk; tile < a.n_tiles; tile += nblk) {
         const uint64_t base = expand_idx(tile, a.outer);
         c.base = base;
+        c.tile = tile;
         // global -> LDS in chunks of LCH elements per thread: LCH loads in
         // flight per thread without keeping all R values live in registers
         constexpr int LCH = R < 8 ? R : 8;
@@ -1081,7 +1100,7 @@ __device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
     __syncthreads();
     for (int s = tid; s < a.nslots; s += nthr) {
         double v = 0.0;
-        for (int w = 0; w < c.nwaves; ++w) v += c.sacc[s * c.nwaves + w];
+        for (int w = 0; w < c.nacc; ++w) v += c.sacc[s * c.nacc + w];
         partials[(uint64_t)s * nblk + blk] = v;
     }
 }
@@ -1109,8 +1128,8 @@ __global__ __launch_bounds__(256, 2) void k_tile_batch(const TileEntry* __restri
 
 int tile_lds_bytes(int b, bool two, int elem_bytes, int nslots, int zt_n) {
     const int nthr = 1 << (b < 8 ? b : 8);
-    const int nwaves = nthr >= 64 ? nthr / 64 : 1;
-    const int acc = ((64 + nslots * nwaves) * 8 + 15) & ~15;
+    const int nacc = nthr >= 64 ? nthr / 16 : 1;
+    const int acc = ((64 + nslots * nacc) * 8 + 15) & ~15;
     return (two ? 2 : 1) * (1 << b) * elem_bytes + acc + zt_n * elem_bytes;
 }
 

@@ -43,8 +43,9 @@ enum TOpKind : int32_t {
     OP_GROUP,       // the next m ops act inside register subcubes over the k tile bits tb[0..k-1]
     OP_LAYER1       // in a group: for each group position p ascending, an optional inner
                     // product with a one-qubit generator on p (bit p of lcmask; slot tb[p];
-                    // generator class lcval), then a 2x2 matrix of class cls on p
-                    // (identity where the layer has no gate)
+                    // generator class lcval), then the 2x2 matrix of class cls on p
+                    // (bit p of m: the layer has a gate on p; elsewhere the table
+                    // holds the identity)
 };
 
 // Matrix classes.  DENSE/DIAG/ANTI/MID are used by every kernel; the finer
@@ -85,7 +86,7 @@ struct TileArgs {
     int32_t zt_n;           // phase-table entries copied to LDS at kernel start
     int64_t zt_off;         // their offset in the coefficient table
     int32_t flags;          // TILE_SYNTH: phi tiles start as the basis state `basis`
-    int32_t pad2;
+    int32_t n_outer;        // index bits outside the tile (bits of the tile number)
     uint64_t basis;
 };
 constexpr int32_t TILE_SYNTH = 1;

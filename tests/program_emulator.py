@@ -108,17 +108,27 @@ def _tile(prog, st, phi, lam, slots):
         while i < len(tops):
             op = tops[i]
             if op["kind"] == OP_GROUP:
-                _group(prog, st, op, tops[i + 1:i + 1 + op["m"]], tp, tl, base, slots)
+                _group(prog, st, op, tops[i + 1:i + 1 + op["m"]], tp, tl, base, slots, T)
                 i += 1 + op["m"]
                 continue
-            _standalone(prog, st, op, tp, tl, base, dep, slots)
+            _standalone(prog, st, op, tp, tl, base, dep, slots, T)
             i += 1
         phi[g] = tp
         if two:
             lam[g] = tl
 
 
-def _group(prog, st, g, subs, tp, tl, base, slots):
+def _tile_parity(w, off, n_outer, T):
+    """Parity bits of the tile base from the per-outer-bit columns (the
+    kernel's form: XOR of the columns of the tile number's set bits)."""
+    pb = 0
+    for k in range(n_outer):
+        if (T >> k) & 1:
+            pb ^= w[off + k]
+    return pb
+
+
+def _group(prog, st, g, subs, tp, tl, base, slots, T):
     b = st["b"]
     GB = g["k"]
     Q = g["tb"][:GB]
@@ -204,7 +214,8 @@ def _group(prog, st, g, subs, tp, tl, base, slots):
         elif kind in (OP_ZPHASE, OP_DOTZSUM):
             mz = s["m"]
             z = w[s["woff"]:s["woff"] + mz]
-            pb = parity_bits(base, z)
+            pb = _tile_parity(w, s["woff"] + mz + nsub + E, st["n_outer"], T)
+            assert pb == parity_bits(base, z)
             pcs = np.array(w[s["woff"] + mz:s["woff"] + mz + nsub], dtype=np.int64)
             pes = np.array(w[s["woff"] + mz + nsub:s["woff"] + mz + nsub + E], dtype=np.int64)
             cnt = np.vectorize(popc)(pb ^ pcs[:, None] ^ pes[None, :])
@@ -239,6 +250,9 @@ def _group(prog, st, g, subs, tp, tl, base, slots):
                         v += (np.conj(l[:, e0]) * (G[0] * p0 + G[1] * p1) +
                               np.conj(l[:, e1]) * (G[2] * p0 + G[3] * p1)).imag.sum()
                     slots[st["slot_base"] + s["tb"][P]] += v
+                if not (s["m"] >> P) & 1:
+                    assert np.all(M == np.array([1, 0, 0, 1]))  # no gate here: the table holds I
+                    continue
                 for x in ([a, l] if l is not None else [a]):
                     for e0, e1 in pairs:
                         x0, x1 = x[:, e0].copy(), x[:, e1].copy()
@@ -250,7 +264,7 @@ def _group(prog, st, g, subs, tp, tl, base, slots):
         tl[idx] = l
 
 
-def _standalone(prog, st, op, tp, tl, base, dep, slots):
+def _standalone(prog, st, op, tp, tl, base, dep, slots, T):
     kind = op["kind"]
     b, nthr, R = st["b"], st["nthr"], st["R"]
     tsz = 1 << b
@@ -291,7 +305,8 @@ def _standalone(prog, st, op, tp, tl, base, dep, slots):
         w = prog["words"]
         mz = op["m"]
         z = w[op["woff"]:op["woff"] + mz]
-        pb = parity_bits(base, z)
+        pb = _tile_parity(w, op["woff"] + mz + nthr + R, st["n_outer"], T)
+        assert pb == parity_bits(base, z)
         plo = w[op["woff"] + mz:op["woff"] + mz + nthr]
         phi_r = w[op["woff"] + mz + nthr:op["woff"] + mz + nthr + R]
         cnt = np.array([popc(pb ^ plo[int(x) % nthr] ^ phi_r[int(x) // nthr]) for x in t])
