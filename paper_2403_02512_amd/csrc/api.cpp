@@ -48,8 +48,8 @@ struct qsv_ctx {
     std::string err;
     int64_t opt_fusion = 1, opt_tile_bits = 0, opt_tile_bits_adj = 0, opt_low_bits = 0, opt_profile = 0,
             opt_nontemporal = 0, opt_layers = 1;
-    DevBuf ops, coef, words, partials, slots, pgroups, pterms, ws0, ws1, binbits, csr_ptr, csr_col, csr_val, smp_chunk,
-        smp_resid, smp_out;
+    DevBuf ops, coef, words, partials, slots, pgroups, pterms, paux, ws0, ws1, binbits, csr_ptr, csr_col, csr_val,
+        smp_chunk, smp_resid, smp_out;
     void* pin = nullptr;
     size_t pin_bytes = 0;
     hipEvent_t pin_ev = nullptr;
@@ -927,20 +927,26 @@ std::vector<char> coef_bytes(const std::vector<cd>& coef, qsv_dtype dt) {
 struct PauliTables {
     std::vector<PauliGroupDev> groups;
     std::vector<PauliTermDev> terms;
+    std::vector<uint64_t> aux;                    // byte tables (complex FP64) and parity columns
     std::vector<std::pair<int, int>> obs_groups;  // (first group, count)
     std::vector<int> n_x_groups;                  // groups with x != 0
+    std::vector<int> lut_tables;                  // byte tables per observable (LDS of its launch)
 };
 
-void add_pauli(PauliTables& T, const qsv_pauli_sum& h, double scale) {
+// allow_lut: groups of many terms (the largest two with 16..64 terms, at most
+// 12 byte tables) are evaluated by table lookups in k_pauli.
+void add_pauli(PauliTables& T, const qsv_pauli_sum& h, double scale, bool allow_lut = true) {
     std::map<uint64_t, std::vector<int64_t>> by_x;
     for (int64_t t = 0; t < h.n_terms; ++t) by_x[h.x_mask[t]].push_back(t);
     const int g0 = (int)T.groups.size();
     int nx = 0;
     for (auto& kv : by_x) {
         PauliGroupDev g;
+        std::memset(&g, 0, sizeof g);
         g.x = kv.first;
         g.t0 = (int)T.terms.size();
         g.nt = (int)kv.second.size();
+        g.lut = -1;
         if (g.x) ++nx;
         for (int64_t t : kv.second) {
             const uint64_t z = h.z_mask[t];
@@ -955,8 +961,49 @@ void add_pauli(PauliTables& T, const qsv_pauli_sum& h, double scale) {
         }
         T.groups.push_back(g);
     }
+    int tables = 0;
+    if (allow_lut) {
+        std::vector<int> cand;
+        for (int gi = g0; gi < (int)T.groups.size(); ++gi)
+            if (T.groups[gi].nt >= PAULI_LUT_MIN_TERMS && T.groups[gi].nt <= 64) cand.push_back(gi);
+        std::sort(cand.begin(), cand.end(), [&](int a, int b) { return T.groups[a].nt > T.groups[b].nt; });
+        int slot = 0;
+        for (int gi : cand) {
+            PauliGroupDev& g = T.groups[gi];
+            const int nb = (g.nt + 7) / 8;
+            if (slot == 2 || tables + nb > PAULI_LUT_MAX_TABLES) continue;
+            g.lut = slot++;
+            g.nb = nb;
+            if (T.aux.size() & 1) T.aux.push_back(0);  // 16-byte aligned complex entries
+            g.lut_off = (int64_t)T.aux.size();
+            for (int b = 0; b < nb; ++b)
+                for (int v = 0; v < 256; ++v) {
+                    double re = 0.0, im = 0.0;
+                    for (int j = 0; j < 8 && 8 * b + j < g.nt; ++j) {
+                        const PauliTermDev& tm = T.terms[g.t0 + 8 * b + j];
+                        const double sgn = ((v >> j) & 1) ? -1.0 : 1.0;
+                        re += sgn * tm.wre;
+                        im += sgn * tm.wim;
+                    }
+                    uint64_t ur, ui;
+                    std::memcpy(&ur, &re, 8);
+                    std::memcpy(&ui, &im, 8);
+                    T.aux.push_back(ur);
+                    T.aux.push_back(ui);
+                }
+            g.col_off = (int64_t)T.aux.size();
+            for (int k = 0; k < 64; ++k) {
+                uint64_t col = 0;
+                for (int t = 0; t < g.nt; ++t)
+                    if ((T.terms[g.t0 + t].z >> k) & 1) col |= 1ull << t;
+                T.aux.push_back(col);
+            }
+            tables += nb;
+        }
+    }
     T.obs_groups.push_back({g0, (int)T.groups.size() - g0});
     T.n_x_groups.push_back(nx);
+    T.lut_tables.push_back(tables);
 }
 
 // expval (or lambda) of observable o into slots[out_slot]
@@ -971,10 +1018,13 @@ void run_pauli(qsv_ctx* c, qsv_dtype dt, int n, const PauliTables& T, int o, con
     const PauliGroupDev* g = (const PauliGroupDev*)c->pgroups.p + T.obs_groups[o].first;
     const PauliTermDev* tm = (const PauliTermDev*)c->pterms.p;
     Timed t(c, lam ? KK_PAULI_LAMBDA : KK_PAULI, bytes);
+    const uint64_t* aux = (const uint64_t*)c->paux.p;
     t.done(dt == QSV_C128 ? launch_pauli<double>(c->stream, lam != nullptr, norm2, psi, lam, N, g,
-                                                 T.obs_groups[o].second, tm, (double*)c->partials.p, grid)
+                                                 T.obs_groups[o].second, tm, aux, T.lut_tables[o],
+                                                 (double*)c->partials.p, grid)
                           : launch_pauli<float>(c->stream, lam != nullptr, norm2, psi, lam, N, g,
-                                                T.obs_groups[o].second, tm, (double*)c->partials.p, grid));
+                                                T.obs_groups[o].second, tm, aux, T.lut_tables[o],
+                                                (double*)c->partials.p, grid));
     Timed tr(c, KK_REDUCE, 8.0 * grid);
     tr.done(launch_reduce(c->stream, (const double*)c->partials.p, grid, norm2 ? 2 : 1, slot));
 }
@@ -986,7 +1036,8 @@ void upload_program(qsv_ctx* c, const Program& P, qsv_dtype dt, const PauliTable
                    {&c->coef, cf.data(), cf.size()},
                    {&c->words, P.words.data(), P.words.size() * 8},
                    {&c->pgroups, T->groups.data(), T->groups.size() * sizeof(PauliGroupDev)},
-                   {&c->pterms, T->terms.data(), T->terms.size() * sizeof(PauliTermDev)}});
+                   {&c->pterms, T->terms.data(), T->terms.size() * sizeof(PauliTermDev)},
+                   {&c->paux, T->aux.data(), T->aux.size() * 8}});
     else
         upload(c, {{&c->ops, P.tops.data(), P.tops.size() * sizeof(TOp)},
                    {&c->coef, cf.data(), cf.size()},
@@ -1176,7 +1227,7 @@ void qsv_ctx_destroy(qsv_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (DevBuf* b : {&c->ops, &c->coef, &c->words, &c->partials, &c->slots, &c->pgroups, &c->pterms, &c->ws0, &c->ws1,
+    for (DevBuf* b : {&c->ops, &c->coef, &c->words, &c->partials, &c->slots, &c->pgroups, &c->pterms, &c->paux, &c->ws0, &c->ws1,
                       &c->binbits, &c->csr_ptr, &c->csr_col, &c->csr_val, &c->smp_chunk, &c->smp_resid, &c->smp_out})
         release(*b);
     if (c->pin) (void)hipHostFree(c->pin);
@@ -1261,7 +1312,7 @@ qsv_status qsv_ctx_workspace_bytes(qsv_ctx* c, size_t* out) {
     return guard(c, [&] {
         if (!c || !out) fail(QSV_ERR_ARG, "NULL argument");
         size_t t = 0;
-        for (DevBuf* b : {&c->ops, &c->coef, &c->words, &c->partials, &c->slots, &c->pgroups, &c->pterms, &c->ws0, &c->ws1,
+        for (DevBuf* b : {&c->ops, &c->coef, &c->words, &c->partials, &c->slots, &c->pgroups, &c->pterms, &c->paux, &c->ws0, &c->ws1,
                           &c->binbits, &c->csr_ptr, &c->csr_col, &c->csr_val, &c->smp_chunk, &c->smp_resid, &c->smp_out})
             t += b->bytes;
         *out = t;
@@ -1545,7 +1596,8 @@ qsv_status qsv_expval(qsv_state* s, const qsv_pauli_sum* obs, size_t n_obs, doub
         PauliTables T;
         for (size_t o = 0; o < n_obs; ++o) add_pauli(T, obs[o], 1.0);
         upload(c, {{&c->pgroups, T.groups.data(), T.groups.size() * sizeof(PauliGroupDev)},
-                   {&c->pterms, T.terms.data(), T.terms.size() * sizeof(PauliTermDev)}});
+                   {&c->pterms, T.terms.data(), T.terms.size() * sizeof(PauliTermDev)},
+                   {&c->paux, T.aux.data(), T.aux.size() * 8}});
         ensure(c, c->slots, n_obs * 8);
         for (size_t o = 0; o < n_obs; ++o) run_pauli(c, s->dt, s->n, T, (int)o, s->ptr, nullptr, (double*)c->slots.p + o);
         HIPCHK(hipMemcpyAsync(out, c->slots.p, n_obs * 8, hipMemcpyDeviceToHost, c->stream));
@@ -1564,7 +1616,8 @@ qsv_status qsv_var(qsv_state* s, const qsv_pauli_sum* obs, size_t n_obs, double*
         PauliTables T;
         for (size_t o = 0; o < n_obs; ++o) add_pauli(T, obs[o], 1.0);
         upload(c, {{&c->pgroups, T.groups.data(), T.groups.size() * sizeof(PauliGroupDev)},
-                   {&c->pterms, T.terms.data(), T.terms.size() * sizeof(PauliTermDev)}});
+                   {&c->pterms, T.terms.data(), T.terms.size() * sizeof(PauliTermDev)},
+                   {&c->paux, T.aux.data(), T.aux.size() * 8}});
         ensure(c, c->slots, n_obs * 16);
         for (size_t o = 0; o < n_obs; ++o)
             run_pauli(c, s->dt, s->n, T, (int)o, s->ptr, nullptr, (double*)c->slots.p + 2 * o, true);
@@ -1940,7 +1993,7 @@ BatchPlan plan_batch(qsv_batch* B, const double* params, bool grad) {
     PauliTables T;
     for (size_t ci = 0; ci < nc; ++ci) {
         qsv_pauli_sum h{(int64_t)B->ocoef[ci].size(), B->ocoef[ci].data(), B->ox[ci].data(), B->oz[ci].data()};
-        add_pauli(T, h, 1.0);
+        add_pauli(T, h, 1.0, false);  // the batched kernel runs the term loop
     }
     std::vector<char>& tab = bp.tab;
     std::vector<char> coef_b = coef_bytes(coef, B->dt);

@@ -1239,15 +1239,55 @@ hipError_t launch_tile_batch(hipStream_t s, bool two, bool generic, const TileEn
 
 // (P psi)_i = i^{nY} (-1)^{popcount((i ^ x) & z)} psi_{i ^ x}; terms sharing
 // an x mask share the load of psi_{i ^ x}.  Accumulation in FP64.
+//
+// Groups flagged with a table slot (at most two per launch, chosen by the
+// host for many-term groups) skip the term loop: the parity vector of the
+// source index s = i ^ x is linear over GF(2) in s, so for the grid-stride
+// index i = base0 + it * stride it is (the thread's constant part) XOR (the
+// iteration's uniform part), each an XOR of per-bit columns; the group's
+// weight is then the sum of one 256-entry table lookup per byte of it.
 template <typename T, bool WRITE, bool NORM2>
 __global__ __launch_bounds__(256) void k_pauli(const cx<T>* __restrict__ psi, cx<T>* __restrict__ lam, uint64_t N,
                                                const PauliGroupDev* __restrict__ groups, int n_groups,
                                                const PauliTermDev* __restrict__ terms,
-                                               double* __restrict__ partials) {
+                                               const uint64_t* __restrict__ aux, double* __restrict__ partials) {
     __shared__ double red[64];
+    extern __shared__ __align__(16) unsigned char pauli_smem[];
+    cx<double>* tabs = reinterpret_cast<cx<double>*>(pauli_smem);
+    const uint64_t base0 = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * 256;  // a power of two
+    const int lstride = __ffsll((unsigned long long)stride) - 1;
+    // table slots: LDS offset, columns, thread-constant parity part
+    int toff[2] = {0, 0};
+    const uint64_t* cols[2] = {nullptr, nullptr};
+    uint64_t pthr[2] = {0, 0};
+    int nslot = 0, tot_tabs = 0;
+    for (int g = 0; g < n_groups; ++g) {
+        const PauliGroupDev gr = groups[g];
+        if (gr.lut < 0) continue;
+        const cx<double>* src = reinterpret_cast<const cx<double>*>(aux + gr.lut_off);
+        for (int e = threadIdx.x; e < gr.nb * 256; e += 256) tabs[tot_tabs * 256 + e] = src[e];
+        const uint64_t* cl = aux + gr.col_off;
+        uint64_t p = 0;
+        const uint64_t s0 = base0 ^ gr.x;  // the source index without the iteration's bits
+        for (int k = 0; k < 64; ++k)
+            if ((s0 >> k) & 1) p ^= cl[k];
+        if (gr.lut == 0) { toff[0] = tot_tabs * 256; cols[0] = cl; pthr[0] = p; }
+        else { toff[1] = tot_tabs * 256; cols[1] = cl; pthr[1] = p; }
+        tot_tabs += gr.nb;
+        ++nslot;
+    }
+    __syncthreads();
     double dot = 0.0, nrm = 0.0;
-    const uint64_t stride = (uint64_t)gridDim.x * 256;
-    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += stride) {
+    uint64_t it = 0;
+    for (uint64_t i = base0; i < N; i += stride, ++it) {
+        // uniform part of the parity vectors: columns of the iteration's bits
+        uint64_t pit[2] = {0, 0};
+        for (int sl = 0; sl < nslot; ++sl) {
+            uint64_t p = 0;
+            for (uint64_t r = it; r; r &= r - 1) p ^= cols[sl][lstride + __ffsll((unsigned long long)r) - 1];
+            pit[sl] = p;
+        }
         const cx<T> pi = psi[i];
         double ar = 0.0, ai = 0.0;
         for (int g = 0; g < n_groups; ++g) {
@@ -1255,11 +1295,22 @@ __global__ __launch_bounds__(256) void k_pauli(const cx<T>* __restrict__ psi, cx
             const uint64_t src = i ^ gr.x;
             const cx<T> ps = gr.x ? psi[src] : pi;
             double sr = 0.0, si = 0.0;
-            for (int t = gr.t0; t < gr.t0 + gr.nt; ++t) {
-                const PauliTermDev tm = terms[t];
-                const bool neg = __popcll(src & tm.z) & 1;
-                sr += neg ? -tm.wre : tm.wre;
-                si += neg ? -tm.wim : tm.wim;
+            if (gr.lut >= 0) {
+                const int sl = gr.lut;
+                const uint64_t p = (sl ? pthr[1] ^ pit[1] : pthr[0] ^ pit[0]);
+                const cx<double>* tb = tabs + (sl ? toff[1] : toff[0]);
+                for (int b = 0; b < gr.nb; ++b) {
+                    const cx<double> e = tb[b * 256 + (int)((p >> (8 * b)) & 255)];
+                    sr += e.re;
+                    si += e.im;
+                }
+            } else {
+                for (int t = gr.t0; t < gr.t0 + gr.nt; ++t) {
+                    const PauliTermDev tm = terms[t];
+                    const bool neg = __popcll(src & tm.z) & 1;
+                    sr += neg ? -tm.wre : tm.wre;
+                    si += neg ? -tm.wim : tm.wim;
+                }
             }
             ar += sr * (double)ps.re - si * (double)ps.im;
             ai += sr * (double)ps.im + si * (double)ps.re;
@@ -1286,17 +1337,18 @@ int pauli_grid(uint64_t N) {
 
 template <typename T>
 hipError_t launch_pauli(hipStream_t s, bool write_lambda, bool norm2, const void* psi, void* lam, uint64_t N,
-                        const PauliGroupDev* groups, int n_groups, const PauliTermDev* terms, double* partials,
-                        int grid) {
+                        const PauliGroupDev* groups, int n_groups, const PauliTermDev* terms, const uint64_t* aux,
+                        int lut_tables, double* partials, int grid) {
+    const size_t lds = (size_t)lut_tables * 256 * sizeof(cx<double>);
     if (norm2)
-        hipLaunchKernelGGL((k_pauli<T, false, true>), dim3(grid), dim3(256), 0, s, (const cx<T>*)psi, (cx<T>*)lam, N,
-                           groups, n_groups, terms, partials);
+        hipLaunchKernelGGL((k_pauli<T, false, true>), dim3(grid), dim3(256), lds, s, (const cx<T>*)psi, (cx<T>*)lam,
+                           N, groups, n_groups, terms, aux, partials);
     else if (write_lambda)
-        hipLaunchKernelGGL((k_pauli<T, true, false>), dim3(grid), dim3(256), 0, s, (const cx<T>*)psi, (cx<T>*)lam, N,
-                           groups, n_groups, terms, partials);
+        hipLaunchKernelGGL((k_pauli<T, true, false>), dim3(grid), dim3(256), lds, s, (const cx<T>*)psi, (cx<T>*)lam,
+                           N, groups, n_groups, terms, aux, partials);
     else
-        hipLaunchKernelGGL((k_pauli<T, false, false>), dim3(grid), dim3(256), 0, s, (const cx<T>*)psi, (cx<T>*)lam,
-                           N, groups, n_groups, terms, partials);
+        hipLaunchKernelGGL((k_pauli<T, false, false>), dim3(grid), dim3(256), lds, s, (const cx<T>*)psi,
+                           (cx<T>*)lam, N, groups, n_groups, terms, aux, partials);
     return hipGetLastError();
 }
 
@@ -1576,7 +1628,8 @@ hipError_t launch_reduce(hipStream_t s, const double* partials, int n_blocks, in
     template hipError_t launch_tile<T>(hipStream_t, bool, bool, const void*, void*, void*, const TileArgs&, const TOp*,      \
                                        const void*, const uint64_t*, double*, int, int, int, size_t);           \
     template hipError_t launch_pauli<T>(hipStream_t, bool, bool, const void*, void*, uint64_t,                  \
-                                        const PauliGroupDev*, int, const PauliTermDev*, double*, int);          \
+                                        const PauliGroupDev*, int, const PauliTermDev*, const uint64_t*, int,  \
+                                        double*, int);                                                          \
     template hipError_t launch_probs<T>(hipStream_t, const void*, uint64_t, const Expand&, const uint64_t*, int, \
                                         int, double*);                                                          \
     template hipError_t launch_tile_batch<T>(hipStream_t, bool, bool, const TileEntry*, const int32_t*,        \

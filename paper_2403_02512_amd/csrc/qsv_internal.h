@@ -114,7 +114,17 @@ struct ReduceEntry {
 struct PauliGroupDev {
     uint64_t x;
     int32_t t0, nt;
+    // Byte-table evaluation for groups with many terms: the group's weight at
+    // source index s is sum_t w_t (-1)^{parity(s & z_t)}; the parity vector
+    // (bit t) is linear in s, so it is the XOR of per-index-bit columns, and
+    // the weight is the sum over its bytes of 256-entry tables.
+    int32_t lut;      // -1: term loop; else table slot (0 or 1) of this observable
+    int32_t nb;       // byte tables (ceil(nt / 8))
+    int64_t lut_off;  // first complex entry of the tables in the aux array (in doubles)
+    int64_t col_off;  // first of the 64 per-index-bit parity columns in the aux array
 };
+constexpr int PAULI_LUT_MIN_TERMS = 16;
+constexpr int PAULI_LUT_MAX_TABLES = 12;  // 12 x 256 x 16 B = 48 KiB of LDS
 struct PauliTermDev {
     uint64_t z;
     double wre, wim;  // coeff * i^{popcount(x & z)}
@@ -157,7 +167,8 @@ template <typename T> hipError_t launch_pauli_batch(hipStream_t s, bool write_la
 hipError_t launch_reduce_batch(hipStream_t s, const ReduceEntry* re, int n, const double* partials, double* out);
 template <typename T> hipError_t launch_pauli(hipStream_t s, bool write_lambda, bool norm2, const void* psi,
                                               void* lam, uint64_t N, const PauliGroupDev* groups, int n_groups,
-                                              const PauliTermDev* terms, double* partials, int grid);
+                                              const PauliTermDev* terms, const uint64_t* aux, int lut_tables,
+                                              double* partials, int grid);
 template <typename T> hipError_t launch_sparse(hipStream_t s, const void* psi, uint64_t N, const int64_t* row_ptr,
                                                const int64_t* col, const double* val, double* partials, int grid);
 template <typename T> hipError_t launch_chunk_norms(hipStream_t s, const void* psi, int clog2, uint64_t n_chunks,
