@@ -359,9 +359,61 @@ struct Proto {
     std::vector<uint64_t> z;     // Z-parity masks (ZPHASE / DOTZSUM)
     double angle = 0.0;          // ZPHASE
     uint32_t tbits = 0;          // tile-local bits mixed (APPLY / DOT)
+    uint32_t dbits = 0;          // tile-local bits acted on diagonally (controls, diagonal targets)
     int k = 0;                   // targets
     bool is_dot() const { return kind == DOT || kind == DOTDIAG || kind == DOTZSUM; }
 };
+
+// Reorder the protos of a grouped pass so that fewer register groups are
+// needed: list scheduling that keeps every pair of non-commuting protos in
+// order (one mixes a bit the other mixes or acts on diagonally; two inner
+// products always commute, and so do two diagonal ops) and, at each step,
+// takes the first ready proto whose mixed bits fit the open group without
+// widening it, else the one that widens it least; a group closes when no
+// ready proto fits.  Passes with a standalone wide matrix keep their order.
+std::vector<Proto> schedule_groups(const std::vector<Proto>& pr, int GB) {
+    const size_t P = pr.size();
+    for (const Proto& p : pr)
+        if ((p.kind == Proto::APPLY || p.kind == Proto::DOT) && p.k > 2) return pr;
+    auto is_dot = [](const Proto& p) { return p.kind == Proto::DOT || p.kind == Proto::DOTDIAG || p.kind == Proto::DOTZSUM; };
+    std::vector<int> npred(P, 0);
+    std::vector<std::vector<int>> succ(P);
+    for (size_t i = 0; i < P; ++i)
+        for (size_t j = i + 1; j < P; ++j) {
+            if (is_dot(pr[i]) && is_dot(pr[j])) continue;
+            const uint32_t ai = pr[i].tbits | pr[i].dbits, aj = pr[j].tbits | pr[j].dbits;
+            if ((pr[i].tbits & aj) || (pr[j].tbits & ai)) {
+                succ[i].push_back((int)j);
+                ++npred[j];
+            }
+        }
+    std::vector<Proto> out;
+    out.reserve(P);
+    std::vector<char> done(P, 0);
+    uint32_t Q = 0;
+    while (out.size() < P) {
+        int pick = -1, best_grow = 99;
+        for (size_t i = 0; i < P; ++i) {
+            if (done[i] || npred[i]) continue;
+            const uint32_t grow = pr[i].tbits & ~Q;
+            if (!grow) {
+                pick = (int)i;
+                break;
+            }
+            const int g = __builtin_popcount(grow);
+            if (__builtin_popcount(Q | pr[i].tbits) <= GB && g < best_grow) best_grow = g, pick = (int)i;
+        }
+        if (pick < 0) {  // nothing fits the open group: start a new one
+            Q = 0;
+            continue;
+        }
+        done[pick] = 1;
+        Q |= pr[pick].tbits;
+        out.push_back(pr[pick]);
+        for (int j : succ[pick]) --npred[j];
+    }
+    return out;
+}
 
 // Lower one planned pass into a k_tile step.
 void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item>& items, const Pass& pass, int n,
@@ -422,6 +474,12 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
         for (int i = 0; i < g.k; ++i) zm |= wire_bit(n, g.tw[i]);
         return zm;
     };
+    auto local_mask = [&](uint64_t global) {
+        uint32_t m = 0;
+        for (int j = 0; j < b; ++j)
+            if ((global >> sb[j]) & 1) m |= 1u << j;
+        return m;
+    };
     size_t q = 0;
     while (q < order.size()) {
         const Item& it = items[order[q]];
@@ -429,6 +487,7 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
         Proto pr;
         pr.f = it.f;
         pr.k = f.k;
+        pr.dbits = local_mask(it.zbits);
         if (!it.xbits && f.zrot && (it.dot || true)) {
             size_t e = q;
             if (it.dot) {
@@ -438,6 +497,7 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
                     const Factor& g = F[jt.f];
                     if (!(jt.dot && !jt.xbits && g.zrot && g.param == f.param && g.coef == f.coef)) break;
                     pr.z.push_back(zmask_of(g));
+                    pr.dbits |= local_mask(jt.zbits);
                     ++e;
                 }
             } else {
@@ -453,6 +513,7 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
                                                     : (g.zparam < 0 && g.zangle == f.zangle);
                     if (!(!jt.dot && !jt.xbits && g.zrot && same)) break;
                     pr.z.push_back(zmask_of(g));
+                    pr.dbits |= local_mask(jt.zbits);
                     ++e;
                 }
             }
@@ -474,6 +535,7 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
 
     const int GB = two ? GROUP_BITS_TWO : GROUP_BITS_ONE;
     const bool grouped = b >= GB;
+    if (grouped && layers) protos = schedule_groups(protos, GB);
     const int nsub = grouped ? (1 << (b - GB)) : 0;
     int nslots = 0;
     // phase tables of the pass, appended contiguously after emission (the
@@ -674,7 +736,7 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
                         op.slot = -1;
                         op.aux = dslot;
                         bool real = true, riri = true;
-                        int gcls = 0;
+                        int gcls = LG_NONE;
                         std::vector<cd> mats[4], gens[4];
                         for (int p = 0; p < GB; ++p) {
                             op.tb[p] = -1;
@@ -692,8 +754,9 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
                             if (ld[p] >= 0) {
                                 const Factor& f = F[protos[ld[p]].f];
                                 gens[p] = f.g;
-                                const int c = classify_gen1(f.g);
-                                gcls = gcls == 0 ? c : (gcls == c ? c : MC_DENSE);
+                                const int cg = classify_gen1(f.g);
+                                const int c = cg == MC_PX ? LG_X : (cg == MC_PY ? LG_Y : LG_DENSE);
+                                gcls = gcls == LG_NONE ? c : (gcls == c ? c : LG_DENSE);
                                 op.lcmask |= 1u << p;
                                 op.tb[p] = nslots++;
                                 P.slot_param.push_back({f.param, f.coef});
@@ -704,7 +767,7 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
                         op.lcval = (uint32_t)gcls;
                         op.coff = (int64_t)P.coef.size();
                         for (int p = 0; p < GB; ++p) {
-                            if (gcls == MC_DENSE)
+                            if (gcls == LG_DENSE)
                                 for (auto x : gens[p]) P.coef.push_back(x);
                             for (auto x : mats[p]) P.coef.push_back(x);
                         }

@@ -716,7 +716,7 @@ __device__ __forceinline__ void g_layer_pos(cx<T>* a, cx<T>* l, const cx<T>* m, 
                                             DotAcc& acc, int& ai) {
     constexpr int NC = GCLS == MC_DENSE ? 8 : 4;
     const cx<T>* mp = m + P * NC;
-    if constexpr (TWO && GCLS != 0) {
+    if constexpr (TWO && GCLS >= 0) {
         if (dmask & (1u << P)) {
             acc.add(ai, g_dot1<T, GB, P, GCLS, false>(a, l, mp, 0, nullptr, 0, 0));
             ++ai;
@@ -854,18 +854,19 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
                 }
                 break;
             case OP_LAYER1: {
-                const int gcls = TWO ? (int)s.lcval : 0;
+                // template GCLS: -1 without inner products, else the generator's class
+                const uint32_t gcode = TWO ? s.lcval : (uint32_t)LG_NONE;
 #define L(C, G) g_layer<T, TWO, GB, C, G>(a, l, m, s.lcmask, (uint32_t)s.m, acc, s.aux)
-                if (gcls == 0) {
-                    if (s.cls == MC_REAL) L(MC_REAL, 0);
-                    else if (s.cls == MC_RIRI) L(MC_RIRI, 0);
-                    else L(MC_DENSE, 0);
+                if (gcode == LG_NONE) {
+                    if (s.cls == MC_REAL) L(MC_REAL, -1);
+                    else if (s.cls == MC_RIRI) L(MC_RIRI, -1);
+                    else L(MC_DENSE, -1);
                 } else if constexpr (TWO) {
-                    if (gcls == MC_PX) {
+                    if (gcode == LG_X) {
                         if (s.cls == MC_REAL) L(MC_REAL, MC_PX);
                         else if (s.cls == MC_RIRI) L(MC_RIRI, MC_PX);
                         else L(MC_DENSE, MC_PX);
-                    } else if (gcls == MC_PY) {
+                    } else if (gcode == LG_Y) {
                         if (s.cls == MC_REAL) L(MC_REAL, MC_PY);
                         else if (s.cls == MC_RIRI) L(MC_RIRI, MC_PY);
                         else L(MC_DENSE, MC_PY);

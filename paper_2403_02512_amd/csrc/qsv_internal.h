@@ -43,7 +43,7 @@ enum TOpKind : int32_t {
     OP_GROUP,       // the next m ops act inside register subcubes over the k tile bits tb[0..k-1]
     OP_LAYER1       // in a group: for each group position p ascending, an optional inner
                     // product with a one-qubit generator on p (bit p of lcmask; slot tb[p];
-                    // generator class lcval), then the 2x2 matrix of class cls on p
+                    // generator class code lcval, LayerGen), then the 2x2 matrix of class cls on p
                     // (bit p of m: the layer has a gate on p; elsewhere the table
                     // holds the identity)
 };
@@ -123,6 +123,8 @@ struct PauliGroupDev {
     int64_t lut_off;  // first complex entry of the tables in the aux array (in doubles)
     int64_t col_off;  // first of the 64 per-index-bit parity columns in the aux array
 };
+// generator class code of a LAYER1 op (its lcval)
+enum LayerGen : uint32_t { LG_NONE = 0, LG_X = 1, LG_Y = 2, LG_DENSE = 3 };
 constexpr int PAULI_LUT_MIN_TERMS = 16;
 constexpr int PAULI_LUT_MAX_TABLES = 12;  // 12 x 256 x 16 B = 48 KiB of LDS
 struct PauliTermDev {

@@ -41,3 +41,19 @@ def test_qaoa_program(n):
     for opts in ({}, {"tile_bits": 6, "low_bits": 2}):
         g, _ = emulate_adjoint(n, c.ops, c.params, psi, lam, **opts)
         np.testing.assert_allclose(g, oracle.adjoint_jacobian(psi, c.ops, c.params, c.observables)[0], atol=1e-11)
+
+
+@pytest.mark.parametrize("opt", [{}, {"fusion": 2}])
+def test_layers_with_mixed_generators(opt):
+    """Layers whose inner products mix X-, Y- and dense generators (RX next
+    to RY and Rot/U3 factors) keep their generator class (regression: a mixed
+    layer was once encoded as having no inner products)."""
+    n = 8
+    c = W.random_circuit(n, 40, seed=9, n_params=6,
+                         gates=["RX", "RY", "RZ", "CNOT", "IsingXX", "CRY", "Rot", "U3", "SingleExcitation"])
+    obs = W.random_observables(n, np.random.default_rng(2), n_obs=2, n_terms=3)
+    psi = oracle.apply(n, c.ops, c.params)
+    want = oracle.adjoint_jacobian(psi, c.ops, c.params, obs)
+    for o in range(2):
+        g, _ = emulate_adjoint(n, c.ops, c.params, psi, oracle.apply_pauli_sum(psi, obs[o]), **opt)
+        np.testing.assert_allclose(g, want[o], atol=1e-11)
