@@ -368,9 +368,11 @@ struct Proto {
 // needed: list scheduling that keeps every pair of non-commuting protos in
 // order (one mixes a bit the other mixes or acts on diagonally; two inner
 // products always commute, and so do two diagonal ops) and, at each step,
-// takes the first ready proto whose mixed bits fit the open group without
-// widening it, else the one that widens it least; a group closes when no
-// ready proto fits.  Passes with a standalone wide matrix keep their order.
+// takes the first ready proto (in the original order) whose mixed bits fit
+// the open group; a group closes when no ready proto fits.  Keeping the
+// original order where possible keeps runs on distinct positions together, so
+// they still form layers.  Passes with a standalone wide matrix keep their
+// order.
 std::vector<Proto> schedule_groups(const std::vector<Proto>& pr, int GB) {
     const size_t P = pr.size();
     for (const Proto& p : pr)
@@ -392,16 +394,14 @@ std::vector<Proto> schedule_groups(const std::vector<Proto>& pr, int GB) {
     std::vector<char> done(P, 0);
     uint32_t Q = 0;
     while (out.size() < P) {
-        int pick = -1, best_grow = 99;
+        // the first ready op (original order) that fits the open group
+        int pick = -1;
         for (size_t i = 0; i < P; ++i) {
             if (done[i] || npred[i]) continue;
-            const uint32_t grow = pr[i].tbits & ~Q;
-            if (!grow) {
+            if (__builtin_popcount(Q | pr[i].tbits) <= GB) {
                 pick = (int)i;
                 break;
             }
-            const int g = __builtin_popcount(grow);
-            if (__builtin_popcount(Q | pr[i].tbits) <= GB && g < best_grow) best_grow = g, pick = (int)i;
         }
         if (pick < 0) {  // nothing fits the open group: start a new one
             Q = 0;
