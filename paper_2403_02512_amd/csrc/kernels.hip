@@ -711,32 +711,27 @@ struct DotAcc {
 // order as straight-line code: no per-gate dispatch, and the register arrays
 // flow through without merges.  Per position p the coefficients are
 // [generator (GCLS == DENSE only)] then the 2x2 matrix.
-template <typename T, bool TWO, int GB, int CLS, int GCLS, int P>
-__device__ __forceinline__ void g_layer_pos(cx<T>* a, cx<T>* l, const cx<T>* m, uint32_t dmask, uint32_t gmask,
-                                            DotAcc& acc, int& ai) {
+template <typename T, bool TWO, int GB, int CLS, int GCLS, int P, typename Sink>
+__device__ __forceinline__ void g_layer_pos(cx<T>* a, cx<T>* l, const cx<T>* m, uint32_t dmask, Sink& sink) {
     constexpr int NC = GCLS == MC_DENSE ? 8 : 4;
     const cx<T>* mp = m + P * NC;
     if constexpr (TWO && GCLS >= 0) {
-        if (dmask & (1u << P)) {
-            acc.add(ai, g_dot1<T, GB, P, GCLS, false>(a, l, mp, 0, nullptr, 0, 0));
-            ++ai;
-        }
+        if (dmask & (1u << P)) sink(P, g_dot1<T, GB, P, GCLS, false>(a, l, mp, 0, nullptr, 0, 0));
     }
     // unconditional: positions without a gate hold the identity, which keeps
     // the layer branch-free (a skipped position would merge two versions of
     // the register arrays)
-    (void)gmask;
     g_apply1<T, TWO, GB, P, CLS, false>(a, l, mp + (GCLS == MC_DENSE ? 4 : 0), 0, nullptr, 0, 0);
 }
 
-template <typename T, bool TWO, int GB, int CLS, int GCLS>
-__device__ __forceinline__ void g_layer(cx<T>* a, cx<T>* l, const cx<T>* m, uint32_t dmask, uint32_t gmask,
-                                        DotAcc& acc, int acc0) {
-    int ai = acc0;
-    g_layer_pos<T, TWO, GB, CLS, GCLS, 0>(a, l, m, dmask, gmask, acc, ai);
-    if constexpr (GB > 1) g_layer_pos<T, TWO, GB, CLS, GCLS, 1>(a, l, m, dmask, gmask, acc, ai);
-    if constexpr (GB > 2) g_layer_pos<T, TWO, GB, CLS, GCLS, 2>(a, l, m, dmask, gmask, acc, ai);
-    if constexpr (GB > 3) g_layer_pos<T, TWO, GB, CLS, GCLS, 3>(a, l, m, dmask, gmask, acc, ai);
+// sink(p, v) receives this thread's inner product at position p (where bit p
+// of dmask is set), right after it is computed
+template <typename T, bool TWO, int GB, int CLS, int GCLS, typename Sink>
+__device__ __forceinline__ void g_layer(cx<T>* a, cx<T>* l, const cx<T>* m, uint32_t dmask, Sink& sink) {
+    g_layer_pos<T, TWO, GB, CLS, GCLS, 0>(a, l, m, dmask, sink);
+    if constexpr (GB > 1) g_layer_pos<T, TWO, GB, CLS, GCLS, 1>(a, l, m, dmask, sink);
+    if constexpr (GB > 2) g_layer_pos<T, TWO, GB, CLS, GCLS, 2>(a, l, m, dmask, sink);
+    if constexpr (GB > 3) g_layer_pos<T, TWO, GB, CLS, GCLS, 3>(a, l, m, dmask, sink);
 }
 
 #define QSV_P1_CASES(F)                                  \
@@ -782,6 +777,17 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
     for (int d = 0; d < GROUP_MAX_DOTS; ++d) acc.v[d] = 0.0;
     const int nq = b - GB;
     const bool need_gc = g.aux != 0;  // the group holds position-dependent diagonals
+    // every thread runs the same number of subcubes (all lanes active inside
+    // the loop): layers reduce their inner products right away, per 16-lane
+    // row by DPP, into the row's own slot accumulator
+    const bool inloop = c.nthr >= 64 && nsub >= c.nthr;
+    auto row_flush = [&](double v, int slot) {
+        v += row_shr<1>(v);
+        v += row_shr<2>(v);
+        v += row_shr<4>(v);
+        v += row_shr<8>(v);
+        if ((c.tid & 15) == 15) c.sacc[slot * c.nacc + (c.tid >> 4)] += v;
+    };
 #pragma unroll 1
     for (int sc = c.tid; sc < nsub; sc += c.nthr) {
         uint32_t tc = (uint32_t)sc;
@@ -856,7 +862,14 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
             case OP_LAYER1: {
                 // template GCLS: -1 without inner products, else the generator's class
                 const uint32_t gcode = TWO ? s.lcval : (uint32_t)LG_NONE;
-#define L(C, G) g_layer<T, TWO, GB, C, G>(a, l, m, s.lcmask, (uint32_t)s.m, acc, s.aux)
+                // every lane active here: reduce per row at once; otherwise
+                // keep the sums for the flush after the loop
+                int ai = s.aux;
+                auto sink = [&](int p, double v) {
+                    if (inloop) row_flush(v, s.tb[p]);
+                    else acc.add(ai++, v);
+                };
+#define L(C, G) g_layer<T, TWO, GB, C, G>(a, l, m, s.lcmask, sink)
                 if (gcode == LG_NONE) {
                     if (s.cls == MC_REAL) L(MC_REAL, -1);
                     else if (s.cls == MC_RIRI) L(MC_RIRI, -1);
@@ -979,6 +992,7 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
         for (int si = 0; si < g.m; ++si) {
             const TOp& s = subs[si];
             if (s.kind == OP_LAYER1) {
+                if (inloop) continue;  // reduced inside the loop
                 int ai = s.aux;
                 for (int p = 0; p < GB; ++p)
                     if (s.lcmask & (1u << p)) flush(ai++, s.tb[p]);
