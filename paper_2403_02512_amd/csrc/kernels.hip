@@ -960,7 +960,8 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
                         for (int e = 0; e < E; ++e)
                             v += (double)(s.m - 2 * (int)__popcll(pc ^ z[s.m + nsub + e])) * im_conj_mul(l[e], a[e]);
                     }
-                    acc.add(s.aux, v);
+                    if (inloop) row_flush(v, s.slot);
+                    else acc.add(s.aux, v);
                 }
                 break;
             }
@@ -999,6 +1000,7 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
                 continue;
             }
             if (s.kind < OP_DOT1 || s.kind == OP_DOTK || s.kind > OP_DOTZSUM) continue;
+            if (inloop) continue;  // reduced inside the loop
             flush(s.aux, s.slot);
         }
     }
