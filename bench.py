@@ -297,6 +297,9 @@ def main():
     ap.add_argument("--batch-circuits", type=int, default=512)
     ap.add_argument("--micro-tile", action="store_true", help="tile-pass cost structure sweep")
     ap.add_argument("--micro-case", default="", help="run only this micro-tile case (layers on)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy one state-sized buffer device to device (the reference kernel that "
+                         "scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU state-vector "
@@ -317,6 +320,15 @@ def main():
     from paper_2403_02512_amd import qsv
     from paper_2403_02512_amd import workloads as W
 
+    if args.copy_calibration:
+        # a plain copy of 2^n complex128 values: its FETCH_SIZE / WRITE_SIZE
+        # readings calibrate the counters against known bytes
+        import torch
+        src = torch.zeros(1 << args.n, dtype=torch.complex128, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     circ = W.config3(n=args.n)
     n = circ.n_qubits
     torch.cuda.init()
