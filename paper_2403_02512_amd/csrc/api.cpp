@@ -816,7 +816,7 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
 }
 
 // Lower a one-factor forward pass into a streaming kernel when one fits.
-bool lower_single(Program& P, const Factor& f, int n, size_t eb) {
+bool lower_single(Program& P, const Factor& f, int n, size_t eb, int low_bits) {
     const int dim = 1 << f.k;
     std::vector<int> pos;
     uint64_t setmask = 0;
@@ -861,6 +861,7 @@ bool lower_single(Program& P, const Factor& f, int n, size_t eb) {
         }
         st.bytes = (st.cls == MC_MID ? 1.0 : 2.0) * N * eb * frac;
     } else if (f.k <= 5) {
+        (void)low_bits;  // measured: the streaming kernel beats the tiled pass here even on low bits
         st.type = Step::GATEK;
         st.k = f.k;
         for (int i = 0; i < f.k; ++i) st.tb[i] = n - 1 - f.tw[i];
@@ -899,7 +900,7 @@ Program build_program(const PlanOptions& po, const std::vector<Factor>& F, const
     std::vector<Pass> passes = plan_passes(items, n, po);
     for (const Pass& p : passes) {
         if (allow_streaming && !two && p.items.size() == 1 && !items[p.items[0]].dot) {
-            if (lower_single(P, F[items[p.items[0]].f], n, eb)) continue;
+            if (lower_single(P, F[items[p.items[0]].f], n, eb, po.low)) continue;
         }
         lower_tile(P, F, items, p, n, two, dagger, eb, po.layers);
     }

@@ -416,17 +416,69 @@ __device__ __forceinline__ uint32_t spread_bits(int j, int k, const int32_t* tb)
     return o;
 }
 
-// k >= 3 (and any k): every thread computes the new values of its own
-// elements, then all threads write back after a barrier.
+// k-qubit matrix (any k) on tile bits tb[0..k-1]: every thread computes
+// output values into registers, then all threads write back after a barrier.
+// With at most one tuple per thread (k >= log2 R), a thread owns R rows of one
+// tuple: tuple = tid mod T, rows from (tid / T) * R, so the rows - and the
+// matrix entries read - are uniform across a wavefront when T >= 64 (scalar
+// loads), and each input is read from LDS once per thread.  Otherwise each
+// element computes its own row.
 template <typename T, bool TWO, int R>
 __device__ __forceinline__ void tile_applyk(const TileCtx<T, TWO, R>& c, const TOp& op) {
     const int k = op.k, dim = 1 << k;
+    const int tsz = c.nthr * R;
+    const int ntup = tsz >> k;
+    cx<T> ap[R], al[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        ap[r] = {T(0), T(0)};
+        al[r] = {T(0), T(0)};
+    }
+    if (ntup <= c.nthr) {
+        // sorted target bits (k <= 8, uniform), then the tuple's base index
+        int srt[8];
+        for (int i = 0; i < k; ++i) srt[i] = op.tb[i];
+        for (int i = 1; i < k; ++i)
+            for (int j = i; j > 0 && srt[j - 1] > srt[j]; --j) {
+                const int t = srt[j];
+                srt[j] = srt[j - 1];
+                srt[j - 1] = t;
+            }
+        uint32_t tb = (uint32_t)(c.tid & (ntup - 1));
+        for (int i = 0; i < k; ++i) {
+            const uint32_t q = (uint32_t)srt[i];
+            tb = ((tb >> q) << (q + 1)) | (tb & ((1u << q) - 1));
+        }
+        const int row0 = (c.tid / ntup) * R;
+        const bool on = (tb & op.lcmask) == op.lcval;
+        for (int j = 0; j < dim; ++j) {
+            const uint32_t sj = sw(tb | spread_bits(j, k, op.tb));
+            const cx<T> x = c.tp[sj];
+            const cx<T> xl = TWO ? c.tl[sj] : x;
+            const cx<T>* mcol = c.coef + op.coff + (size_t)row0 * dim + j;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const cx<T> mm = mcol[(size_t)r * dim];
+                ap[r] = cmad(mm, x, ap[r]);
+                if (TWO) al[r] = cmad(mm, xl, al[r]);
+            }
+        }
+        __syncthreads();
+        if (on) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint32_t so = sw(tb | spread_bits(row0 + r, k, op.tb));
+                c.tp[so] = ap[r];
+                if (TWO) c.tl[so] = al[r];
+            }
+        }
+        return;
+    }
     uint32_t tmask = 0;
     for (int i = 0; i < k; ++i) tmask |= 1u << op.tb[i];
     int row[R];
     uint32_t gb[R];
     bool on[R];
-    cx<T> ap[R], al[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const uint32_t t = c.tid + r * c.nthr;
@@ -435,8 +487,6 @@ __device__ __forceinline__ void tile_applyk(const TileCtx<T, TWO, R>& c, const T
         row[r] = rw;
         gb[r] = t & ~tmask;
         on[r] = (t & op.lcmask) == op.lcval;
-        ap[r] = {T(0), T(0)};
-        al[r] = {T(0), T(0)};
     }
     for (int j = 0; j < dim; ++j) {
         const uint32_t sp = spread_bits(j, k, op.tb);

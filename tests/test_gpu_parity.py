@@ -308,3 +308,40 @@ def test_sparse_hamiltonian_expval(ctx, dt):
     want = np.vdot(ref_psi, S @ ref_psi)
     scale = abs(S).sum(axis=1).max()
     assert abs(got - want) <= TOL[dt] * scale * 10
+
+
+@pytest.mark.parametrize("dt", [qsv.C128, qsv.C64])
+@pytest.mark.parametrize("n", [6, 12, 16])
+def test_dense_unitaries_low_and_high_bits(ctx, n, dt):
+    """Dense 4-, 5- and 6-qubit unitaries on the lowest index bits (the tiled
+    path: one tuple per thread, uniform rows per wavefront), on the highest
+    bits, on mixed bits and with controls; forward and adjoint sweeps."""
+    rng = np.random.default_rng(40 + n)
+    ops = []
+    for k in (4, 5, 6):
+        if k > n:
+            continue
+        ops.append(W.op("QubitUnitary", list(range(n - k, n))[::-1], matrix=W.random_unitary(k, rng)))
+        ops.append(W.op("QubitUnitary", list(range(k)), matrix=W.random_unitary(k, rng)))
+        ops.append(W.op("QubitUnitary", list(rng.choice(n, size=k, replace=False)), matrix=W.random_unitary(k, rng)))
+        if k + 1 <= n:
+            w = list(rng.choice(n, size=k + 1, replace=False))
+            ops.append(W.op("QubitUnitary", w, n_ctrls=1, matrix=W.random_unitary(k, rng)))
+        ops.append(W.op("RY", [int(rng.integers(n))], (0, 1.0)))
+    params = np.array([0.37])
+    psi0 = W.random_state(n, 3)
+    for opts in ({}, {qsv.OPT_TILE_BITS: 10}):
+        reset_options(ctx)
+        got = gpu_run(ctx, n, ops, params, dt, psi0, opts)
+        assert_state_close(got, oracle_state(n, ops, params, psi0), TOL[dt] * (10 if dt == qsv.C64 else 1),
+                           f"n={n} opts={opts}")
+    reset_options(ctx)
+    # adjoint through the same unitaries (un-applied in the two-vector pass)
+    obs = [W.PauliSum(np.array([0.8, -0.3]), [W.pauli_word(n, {0: "Z"}), W.pauli_word(n, {n - 1: "X"})])]
+    st = qsv.State(ctx, n, dt)
+    qsv.apply(st, ops, params)
+    jac, _ = qsv.adjoint_jacobian(st, ops, params, obs)
+    psi = oracle.apply(n, ops, params)
+    want = oracle.adjoint_jacobian(psi, ops, params, obs)
+    assert np.max(np.abs(jac - want)) <= TOL[dt] * 10
+    st.close()

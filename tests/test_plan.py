@@ -32,14 +32,19 @@ def test_small_register_is_one_tile():
         assert st["passes"] == 1
 
 
-@pytest.mark.parametrize("name,k", [("RX", 1), ("IsingXX", 2), ("QubitUnitary", 3), ("QubitUnitary", 5),
-                                    ("QubitUnitary", 6)])
-def test_single_gate_uses_streaming_kernel_up_to_k5(name, k):
+@pytest.mark.parametrize("name,k,low", [("RX", 1, True), ("IsingXX", 2, True), ("QubitUnitary", 3, True),
+                                        ("QubitUnitary", 4, False), ("QubitUnitary", 5, False),
+                                        ("QubitUnitary", 4, True), ("QubitUnitary", 5, True),
+                                        ("QubitUnitary", 6, False)])
+def test_single_gate_kernel_choice(name, k, low):
+    """One pass per single gate: streaming kernels up to k = 5 (on low or high
+    bits), the LDS-tiled pass for 6-qubit matrices."""
     n = 20
     rng = np.random.default_rng(0)
     mat = W.random_unitary(k, rng) if name == "QubitUnitary" else None
     slots = [(0, 1.0)] if name != "QubitUnitary" else []
-    o = W.op(name, list(range(n - k, n))[::-1], *slots, matrix=mat)
+    wires = list(range(n - k, n))[::-1] if low else list(range(k))
+    o = W.op(name, wires, *slots, matrix=mat)
     st = qsv.plan_stats(n, [o], [0.3])
     assert st["passes"] == 1
     assert st["tile_passes"] == (1 if k == 6 else 0)
