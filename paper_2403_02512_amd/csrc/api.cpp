@@ -268,7 +268,7 @@ size_t elem_bytes(qsv_dtype d) { return d == QSV_C128 ? 16 : 8; }
 // ------------------------------------------------------------------ lowering
 
 struct Step {
-    enum Type { TILE, GATE1, DIAG1, GATE2, GATEK } type = TILE;
+    enum Type { TILE, GATE1, DIAG1, GATE2, GATEK, GATEK_LOW } type = TILE;
     // tile
     TileArgs ta{};
     int grid = 1, nthr = 1, R = 1;
@@ -280,6 +280,7 @@ struct Step {
     uint64_t n_items = 0, setmask = 0, tbit = 0, b0 = 0, b1 = 0;
     int cls = 0, k = 0;
     int32_t tb[6] = {0};
+    uint32_t lcm = 0, lcv = 0;  // GATEK_LOW: controls inside the 64-amplitude chunk
     Mat2 m2{};
     Mat4 m4{};
     int64_t coff = 0;
@@ -860,8 +861,39 @@ bool lower_single(Program& P, const Factor& f, int n, size_t eb, int low_bits) {
             st.m4.im[j] = f.m[j].imag();
         }
         st.bytes = (st.cls == MC_MID ? 1.0 : 2.0) * N * eb * frac;
+    } else if (f.k == 3 && n >= 6 && [&] {
+                   for (int i = 0; i < f.k; ++i)
+                       if (n - 1 - f.tw[i] >= 6) return false;
+                   return true;
+               }()) {
+        // targets in the lowest six bits: one wavefront per aligned chunk of 64
+        // (measured faster than one tuple per thread for k = 3; for k >= 4 the
+        // per-lane matrix rows make it LDS-bound, so those keep the other paths)
+        (void)low_bits;
+        st.type = Step::GATEK_LOW;
+        st.k = f.k;
+        for (int i = 0; i < f.k; ++i) st.tb[i] = n - 1 - f.tw[i];
+        std::vector<int> hi;
+        uint64_t set_hi = 0;
+        st.lcm = st.lcv = 0;
+        for (int j = 0; j < f.nc; ++j) {
+            const int p = n - 1 - f.cw[j];
+            if (p >= 6) {
+                hi.push_back(p - 6);
+                if (f.cv[j]) set_hi |= 1ull << (p - 6);
+            } else {
+                st.lcm |= 1u << p;
+                if (f.cv[j]) st.lcv |= 1u << p;
+            }
+        }
+        std::sort(hi.begin(), hi.end());
+        st.ex = make_expand(hi);
+        st.setmask = set_hi;
+        st.n_items = (uint64_t)1 << (n - 6 - (int)hi.size());
+        st.coff = (int64_t)P.coef.size();
+        for (int j = 0; j < dim * dim; ++j) P.coef.push_back(f.m[j]);
+        st.bytes = 2.0 * N * eb * std::ldexp(1.0, -(int)hi.size());
     } else if (f.k <= 5) {
-        (void)low_bits;  // measured: the streaming kernel beats the tiled pass here even on low bits
         st.type = Step::GATEK;
         st.k = f.k;
         for (int i = 0; i < f.k; ++i) st.tb[i] = n - 1 - f.tw[i];
@@ -941,7 +973,7 @@ void run_program(qsv_ctx* c, const Program& P, qsv_dtype dt, int n, void* phi, v
         }
         const int kind = st.type == Step::GATE1 ? KK_GATE1
                          : st.type == Step::DIAG1 ? KK_DIAG1
-                         : st.type == Step::GATE2 ? KK_GATE2 : KK_GATEK;
+                         : st.type == Step::GATE2 ? KK_GATE2 : KK_GATEK;  // GATEK and GATEK_LOW
         Timed t(c, kind, st.bytes);
         hipError_t e = hipSuccess;
         switch (st.type) {
@@ -956,6 +988,12 @@ void run_program(qsv_ctx* c, const Program& P, qsv_dtype dt, int n, void* phi, v
         case Step::GATE2:
             e = c128 ? launch_gate2<double>(c->stream, phi, st.n_items, st.ex, st.setmask, st.b0, st.b1, st.cls, st.m4)
                      : launch_gate2<float>(c->stream, phi, st.n_items, st.ex, st.setmask, st.b0, st.b1, st.cls, st.m4);
+            break;
+        case Step::GATEK_LOW:
+            e = c128 ? launch_gatek_low<double>(c->stream, phi, st.n_items, st.ex, st.setmask, st.k, st.tb, st.lcm,
+                                                st.lcv, (const char*)c->coef.p + st.coff * cb)
+                     : launch_gatek_low<float>(c->stream, phi, st.n_items, st.ex, st.setmask, st.k, st.tb, st.lcm,
+                                               st.lcv, (const char*)c->coef.p + st.coff * cb);
             break;
         case Step::GATEK:
             e = c128 ? launch_gatek<double>(c->stream, phi, st.n_items, st.ex, st.setmask, st.k, st.tb,
@@ -1550,7 +1588,7 @@ qsv_status qsv_plan_json(int n, qsv_dtype dt, const qsv_op* ops, size_t n_ops, c
         for (size_t i = 0; i < P.steps.size(); ++i) {
             const Step& st = P.steps[i];
             if (i) js += ",";
-            static const char* names[] = {"tile", "gate1", "diag1", "gate2", "gatek"};
+            static const char* names[] = {"tile", "gate1", "diag1", "gate2", "gatek", "gatek_low"};
             add("{\"type\":\"%s\",\"bytes\":%.17g", names[st.type], st.bytes);
             if (st.type == Step::TILE) {
                 const TileArgs& a = st.ta;
@@ -1575,7 +1613,7 @@ qsv_status qsv_plan_json(int n, qsv_dtype dt, const qsv_op* ops, size_t n_ops, c
                 for (int j = 0; j < 4; ++j) add(j ? ",%.17g,%.17g" : "%.17g,%.17g", st.m2.re[j], st.m2.im[j]);
                 js += "],\"m4\":[";
                 for (int j = 0; j < 16; ++j) add(j ? ",%.17g,%.17g" : "%.17g,%.17g", st.m4.re[j], st.m4.im[j]);
-                js += "]";
+                add("],\"lcm\":%u,\"lcv\":%u", st.lcm, st.lcv);
             }
             js += "}";
         }

@@ -298,6 +298,78 @@ __global__ __launch_bounds__(256) void k_gatek(cx<T>* __restrict__ psi, uint64_t
     }
 }
 
+// Dense k-qubit matrix (k <= 6) whose targets all lie in the lowest six index
+// bits: a wavefront owns an aligned chunk of 64 amplitudes, which holds whole
+// tuples.  Every lane loads one amplitude (coalesced) into LDS and computes
+// one output - the row given by its own target bits - from the tuple's
+// inputs (LDS reads shared by the lanes of a tuple) and its matrix row (LDS,
+// rows padded by one entry against bank conflicts).  Chunks are enumerated by
+// ex / setmask over the index bits above bit 5 (controls there); controls in
+// the chunk are per lane (lcm / lcv).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gatek_low(cx<T>* __restrict__ psi, uint64_t n_chunks, Expand ex,
+                                                   uint64_t setmask, TBits tb, int k, uint32_t lcm, uint32_t lcv,
+                                                   const cx<T>* __restrict__ mat) {
+    extern __shared__ __align__(16) unsigned char gk_smem[];
+    const int dim = 1 << k, stride = dim + 1;
+    cx<T>* m = reinterpret_cast<cx<T>*>(gk_smem);
+    cx<T>* buf = m + dim * stride;
+    for (int e = threadIdx.x; e < dim * dim; e += 256) m[(e / dim) * stride + (e % dim)] = mat[e];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t tmask = 0;
+    int row = 0;
+    for (int i = 0; i < k; ++i) {
+        tmask |= 1u << tb.tb[i];
+        row = (row << 1) | ((lane >> tb.tb[i]) & 1);
+    }
+    const uint32_t base_t = (uint32_t)lane & ~tmask;
+    const bool on = ((uint32_t)lane & lcm) == lcv;
+    cx<T>* wb = buf + wave * 64;
+    const cx<T>* mr = m + row * stride;
+    __syncthreads();
+    // the block walks 4 chunks per step, one per wavefront, in lockstep
+    for (uint64_t c0 = (uint64_t)blockIdx.x * 4; c0 < n_chunks; c0 += (uint64_t)gridDim.x * 4) {
+        const uint64_t c = c0 + wave;
+        const bool live = c < n_chunks;
+        const uint64_t base = live ? ((expand_idx(c, ex) | setmask) << 6) : 0;
+        if (live) wb[lane] = psi[base + lane];
+        __syncthreads();
+        if (live) {
+            cx<T> acc = {T(0), T(0)};
+            for (int j = 0; j < dim; ++j) {
+                uint32_t o = base_t;
+                for (int i = 0; i < k; ++i)
+                    if ((j >> (k - 1 - i)) & 1) o |= 1u << tb.tb[i];
+                acc = cmad(mr[j], wb[o], acc);
+            }
+            if (on) psi[base + lane] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+hipError_t launch_gatek_low(hipStream_t s, void* psi, uint64_t n_chunks, const Expand& ex, uint64_t setmask, int k,
+                            const int32_t* tbits, uint32_t lcm, uint32_t lcv, const void* mat) {
+    if (k < 1 || k > 6) return hipErrorInvalidValue;
+    TBits tb;
+    for (int i = 0; i < 6; ++i) tb.tb[i] = i < k ? tbits[i] : 0;
+    const int dim = 1 << k;
+    const size_t lds = ((size_t)dim * (dim + 1) + 256) * sizeof(cx<T>);
+    static bool attr_set = false;
+    if (lds > 65536 && !attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_gatek_low<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    uint64_t blocks = (n_chunks + 3) / 4;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_gatek_low<T>, dim3((unsigned)(blocks ? blocks : 1)), dim3(256), lds, s, (cx<T>*)psi,
+                       n_chunks, ex, setmask, tb, k, lcm, lcv, (const cx<T>*)mat);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_gatek(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex, uint64_t setmask, int k,
                         const int32_t* tbits, const void* mat) {
@@ -1692,6 +1764,8 @@ hipError_t launch_reduce(hipStream_t s, const double* partials, int n_blocks, in
                                         uint64_t, int, const Mat4&);                                            \
     template hipError_t launch_gatek<T>(hipStream_t, void*, uint64_t, const Expand&, uint64_t, int,             \
                                         const int32_t*, const void*);                                           \
+    template hipError_t launch_gatek_low<T>(hipStream_t, void*, uint64_t, const Expand&, uint64_t, int,         \
+                                            const int32_t*, uint32_t, uint32_t, const void*);                   \
     template hipError_t launch_tile<T>(hipStream_t, bool, bool, const void*, void*, void*, const TileArgs&, const TOp*,      \
                                        const void*, const uint64_t*, double*, int, int, int, size_t);           \
     template hipError_t launch_pauli<T>(hipStream_t, bool, bool, const void*, void*, uint64_t,                  \

@@ -153,6 +153,9 @@ template <typename T> hipError_t launch_diag1(hipStream_t s, void* psi, uint64_t
                                               uint64_t setmask, double dre, double dim);
 template <typename T> hipError_t launch_gate2(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex,
                                               uint64_t setmask, uint64_t b0, uint64_t b1, int cls, const Mat4& m);
+template <typename T> hipError_t launch_gatek_low(hipStream_t s, void* psi, uint64_t n_chunks, const Expand& ex,
+                                                  uint64_t setmask, int k, const int32_t* tbits, uint32_t lcm,
+                                                  uint32_t lcv, const void* mat);
 template <typename T> hipError_t launch_gatek(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex,
                                               uint64_t setmask, int k, const int32_t* tbits, const void* mat);
 template <typename T> hipError_t launch_tile(hipStream_t s, bool two, bool generic, const void* phi_src, void* phi,

@@ -68,6 +68,33 @@ def _stream(prog, st, psi):
         M = m4.reshape(4, 4)
         for r in range(4):
             psi[ids[r]] = sum(M[r, j] * a[j] for j in range(4))
+    elif st["type"] == "gatek_low":
+        # chunks of 64 amplitudes (index bits above 5 from ex / setmask); one
+        # output per lane: its row from its target bits, inputs from its tuple
+        k = st["k"]
+        D = 1 << k
+        M = _coef(prog, st["coff"], D * D).reshape(D, D)
+        tb = st["tb"][:k]
+        assert max(tb) < 6
+        tmask = sum(1 << t for t in tb)
+        for c in range(st["n_items"]):
+            base = (expand(c, ex) | st["setmask"]) << 6
+            chunk = psi[base:base + 64].copy()
+            for lane in range(64):
+                if (lane & st["lcm"]) != st["lcv"]:
+                    continue
+                row = 0
+                for t in tb:
+                    row = (row << 1) | ((lane >> t) & 1)
+                t0 = lane & ~tmask
+                acc = 0j
+                for j in range(D):
+                    o = t0
+                    for i in range(k):
+                        if (j >> (k - 1 - i)) & 1:
+                            o |= 1 << tb[i]
+                    acc += M[row, j] * chunk[o]
+                psi[base + lane] = acc
     else:
         k = st["k"]
         D = 1 << k
