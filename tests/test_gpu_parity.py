@@ -313,12 +313,13 @@ def test_sparse_hamiltonian_expval(ctx, dt):
 @pytest.mark.parametrize("dt", [qsv.C128, qsv.C64])
 @pytest.mark.parametrize("n", [6, 12, 16])
 def test_dense_unitaries_low_and_high_bits(ctx, n, dt):
-    """Dense 4-, 5- and 6-qubit unitaries on the lowest index bits (the tiled
-    path: one tuple per thread, uniform rows per wavefront), on the highest
-    bits, on mixed bits and with controls; forward and adjoint sweeps."""
+    """Dense 3- to 6-qubit unitaries on the lowest index bits (3 qubits: one
+    lane per amplitude; 6 qubits: the tiled path, one tuple per thread), on
+    the highest bits, on mixed bits and with controls; forward and adjoint
+    sweeps."""
     rng = np.random.default_rng(40 + n)
     ops = []
-    for k in (4, 5, 6):
+    for k in (3, 4, 5, 6):
         if k > n:
             continue
         ops.append(W.op("QubitUnitary", list(range(n - k, n))[::-1], matrix=W.random_unitary(k, rng)))
