@@ -19,6 +19,8 @@
 //
 // Index conventions: wire w is index bit n-1-w; matrix index bit k-1-i
 // belongs to target i.
+#include <atomic>
+
 #include "qsv_internal.h"
 
 namespace qsv {
@@ -26,6 +28,19 @@ namespace qsv {
 const char* const kKernelNames[KK_COUNT] = {"init",  "gate1", "diag1",        "gate2",        "gatek", "tile1",
                                             "tile2", "pauli_expval", "pauli_lambda", "reduce", "copy",  "probs", "sparse_expval",
                                             "sample"};
+
+// Raise a kernel's dynamic-LDS limit to the CU's 160 KiB, once per device (the
+// attribute is per device; `done` holds one bit per device id).
+static hipError_t allow_big_lds(const void* fn, std::atomic<uint64_t>& done) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const uint64_t bit = 1ull << (dev & 63);
+    if (done.load() & bit) return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e == hipSuccess) done.fetch_or(bit);
+    return e;
+}
 
 template <typename T>
 struct alignas(2 * sizeof(T)) cx {
@@ -356,12 +371,10 @@ hipError_t launch_gatek_low(hipStream_t s, void* psi, uint64_t n_chunks, const E
     for (int i = 0; i < 6; ++i) tb.tb[i] = i < k ? tbits[i] : 0;
     const int dim = 1 << k;
     const size_t lds = ((size_t)dim * (dim + 1) + 256) * sizeof(cx<T>);
-    static bool attr_set = false;
-    if (lds > 65536 && !attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_gatek_low<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           160 * 1024);
+    static std::atomic<uint64_t> lds_raised{0};
+    if (lds > 65536) {
+        hipError_t e = allow_big_lds((const void*)k_gatek_low<T>, lds_raised);
         if (e != hipSuccess) return e;
-        attr_set = true;
     }
     uint64_t blocks = (n_chunks + 3) / 4;
     if (blocks > 8192) blocks = 8192;
@@ -1276,12 +1289,10 @@ template <typename T, bool TWO, int LR, bool GEN>
 static hipError_t launch_tile_lr(hipStream_t s, const void* phi_src, void* phi, void* lam, const TileArgs& a,
                                  const TOp* ops, const void* coef, const uint64_t* words, double* partials, int grid,
                                  int nthr, size_t lds) {
-    static bool attr_set = false;
-    if (lds > 65536 && !attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_tile<T, TWO, LR, GEN>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    static std::atomic<uint64_t> lds_raised{0};
+    if (lds > 65536) {
+        hipError_t e = allow_big_lds((const void*)k_tile<T, TWO, LR, GEN>, lds_raised);
         if (e != hipSuccess) return e;
-        attr_set = true;
     }
     hipLaunchKernelGGL((k_tile<T, TWO, LR, GEN>), dim3(grid), dim3(nthr), lds, s, (const cx<T>*)phi_src, (cx<T>*)phi,
                        (cx<T>*)lam, a, ops, (const cx<T>*)coef, words, partials);
@@ -1325,12 +1336,10 @@ template <typename T, bool TWO, int LR, bool GEN>
 static hipError_t launch_tile_batch_lr(hipStream_t s, const TileEntry* entries, const int32_t* blk_entry,
                                        const TileArgs* args, const TOp* ops, const void* coef, const uint64_t* words,
                                        double* partials, int blocks, int nthr, size_t lds) {
-    static bool attr_set = false;
-    if (lds > 65536 && !attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_tile_batch<T, TWO, LR, GEN>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    static std::atomic<uint64_t> lds_raised{0};
+    if (lds > 65536) {
+        hipError_t e = allow_big_lds((const void*)k_tile_batch<T, TWO, LR, GEN>, lds_raised);
         if (e != hipSuccess) return e;
-        attr_set = true;
     }
     hipLaunchKernelGGL((k_tile_batch<T, TWO, LR, GEN>), dim3(blocks), dim3(nthr), lds, s, entries, blk_entry, args,
                        ops, (const cx<T>*)coef, words, partials);
