@@ -91,6 +91,13 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2403_02512_amd.build`")
+    # PyTorch ships its own HIP runtime library; loading it first lets this
+    # library bind to the same one, so that one runtime serves the process
+    # (with two, whichever initialises second can find no devices)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, u32, u64, dp = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64,
                                  ctypes.POINTER(ctypes.c_double))
