@@ -21,8 +21,9 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libqsv.so")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "gates.cpp", "plan.cpp", "api.cpp"]
-HEADERS = ["qsv_internal.h"]
+SOURCES = ["tile_f64_two.hip", "tile_f64_one.hip", "tile_f32_two.hip", "tile_f32_one.hip", "kernels.hip",
+           "gates.cpp", "plan.cpp", "api.cpp"]
+HEADERS = ["qsv_internal.h", "kcommon.h", "k_tile.h"]
 
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

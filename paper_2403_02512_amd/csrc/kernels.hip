@@ -5,129 +5,29 @@
 //            controlled (paper Alg. 1 / Alg. 2): classes dense, diagonal,
 //            anti-diagonal
 //  k_diag1   one phase on the amplitudes whose target and control bits are
-//            fixed (PhaseShift/Z/S/T and their controlled forms touch half
-//            the vector: Listing 1's "arr[i1] *= s")
+//            fixed: PhaseShift/Z/S/T and their controlled forms scale only
+//            the |1> amplitudes, so they read and write half the vector
+//            (Sec. 2.1.1, Listing 1)
 //  k_gate2   4x4 on amplitude quads (Ising gates, SWAP, Givens rotations)
 //  k_gatek   2^k x 2^k on 2^k-tuples, k = 3..5, one tuple per thread
-//  k_tile    LDS-staged pass: a tile of 2^b amplitudes spanning b index bits
-//            (always including the lowest ones, for coalescing) takes a whole
-//            list of gates, diagonal phase layers and adjoint inner products
-//            per HBM round trip; one or two vectors (phi, lambda)
+//  k_tile    (k_tile.h, instantiated in tile_*.hip) LDS-staged pass: a tile
+//            of 2^b amplitudes spanning b index bits (always including the
+//            lowest ones, for coalescing) takes a whole list of gates,
+//            diagonal phase layers and adjoint inner products per HBM round
+//            trip; one or two vectors (phi, lambda)
 //  k_pauli   Pauli-sum expectation value / lambda = H psi, FP64 accumulation
 //            and wavefront-shuffle block reductions
 //  k_reduce  deterministic FP64 reduction of per-block partials
 //
 // Index conventions: wire w is index bit n-1-w; matrix index bit k-1-i
 // belongs to target i.
-#include <atomic>
-
-#include "qsv_internal.h"
+#include "kcommon.h"
 
 namespace qsv {
 
 const char* const kKernelNames[KK_COUNT] = {"init",  "gate1", "diag1",        "gate2",        "gatek", "tile1",
                                             "tile2", "pauli_expval", "pauli_lambda", "reduce", "copy",  "probs", "sparse_expval",
                                             "sample"};
-
-// Raise a kernel's dynamic-LDS limit to the CU's 160 KiB, once per device (the
-// attribute is per device; `done` holds one bit per device id).
-static hipError_t allow_big_lds(const void* fn, std::atomic<uint64_t>& done) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    const uint64_t bit = 1ull << (dev & 63);
-    if (done.load() & bit) return hipSuccess;
-    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e == hipSuccess) done.fetch_or(bit);
-    return e;
-}
-
-template <typename T>
-struct alignas(2 * sizeof(T)) cx {
-    T re, im;
-};
-
-template <typename T>
-__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
-// a * b + c
-template <typename T>
-__device__ __forceinline__ cx<T> cmad(cx<T> a, cx<T> b, cx<T> c) {
-    return {c.re + a.re * b.re - a.im * b.im, c.im + a.re * b.im + a.im * b.re};
-}
-// Im(conj(l) * v) in FP64
-template <typename T>
-__device__ __forceinline__ double im_conj_mul(cx<T> l, cx<T> v) {
-    return (double)l.re * (double)v.im - (double)l.im * (double)v.re;
-}
-
-__device__ __forceinline__ uint64_t expand_idx(uint64_t k, const Expand& e) {
-    uint64_t r = k & e.m[0];
-    for (int i = 1; i < e.nm; ++i) r |= (k << i) & e.m[i];
-    return r;
-}
-
-// v of the lane `shift` below in the same 16-lane row (0 past the row start):
-// DPP row_shr on both halves of the double, no LDS traffic
-template <int SHIFT>
-__device__ __forceinline__ double row_shr(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x110 + SHIFT, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x110 + SHIFT, 0xF, 0xF, true);
-    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-
-__device__ __forceinline__ double lane_value(double v, int lane) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)b, lane);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-
-// Sum over the 64 lanes (every lane active), returned to all lanes: in-row
-// prefix sums by DPP leave each row's total in its lane 15; the four row
-// totals are read as uniform values.  Fixed order, so reproducible.
-__device__ __forceinline__ double wave_sum(double v) {
-    v += row_shr<1>(v);
-    v += row_shr<2>(v);
-    v += row_shr<4>(v);
-    v += row_shr<8>(v);
-    return (lane_value(v, 15) + lane_value(v, 31)) + (lane_value(v, 47) + lane_value(v, 63));
-}
-
-// Adds the block-wide sum of v to *dst (one thread writes).  Every thread of
-// the block must call it; fixed summation order, so results are reproducible.
-__device__ __forceinline__ void block_add(double v, double* red, double* dst, int tid, int nthr) {
-    if (nthr >= 64) {
-        v = wave_sum(v);
-        if ((tid & 63) == 0) red[tid >> 6] = v;
-        __syncthreads();
-        if (tid == 0) {
-            double s = 0.0;
-            for (int w = 0; w < (nthr >> 6); ++w) s += red[w];
-            *dst += s;
-        }
-    } else {
-        red[tid] = v;
-        __syncthreads();
-        if (tid == 0) {
-            double s = 0.0;
-            for (int w = 0; w < nthr; ++w) s += red[w];
-            *dst += s;
-        }
-    }
-    __syncthreads();
-}
-
-template <typename T>
-struct M2T {
-    cx<T> a, b, c, d;
-};
-template <typename T>
-__device__ __forceinline__ M2T<T> to_t(const Mat2& m) {
-    return {{(T)m.re[0], (T)m.im[0]}, {(T)m.re[1], (T)m.im[1]}, {(T)m.re[2], (T)m.im[2]}, {(T)m.re[3], (T)m.im[3]}};
-}
 
 // ------------------------------------------------------------------ init
 
@@ -400,883 +300,7 @@ hipError_t launch_gatek(hipStream_t s, void* psi, uint64_t n_items, const Expand
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ LDS-tiled fused pass
-
-// LDS position of tile element t: bits 4..7 are XOR-ed into bits 0..3, so
-// that threads reading subcubes whose group bits include the lowest tile bits
-// (a lane stride of 16 elements) spread over all banks.  A bijection on any
-// tile size.
-__device__ __forceinline__ uint32_t sw(uint32_t t) { return t ^ ((t >> 4) & 15u); }
-
-// One op of a tile pass.  tp/tl: the phi/lambda tiles in LDS (tl only when
-// TWO).  The thread owns tile elements t = tid + r * nthr, r < R; pair and
-// quad ops address any element of the tile.
-template <typename T, bool TWO, int R>
-struct TileCtx {
-    cx<T>* tp;
-    cx<T>* tl;
-    double* red;
-    double* sacc;
-    const cx<T>* coef;
-    const uint64_t* words;
-    uint64_t base, offlo, tile;
-    const uint64_t* offhi;
-    int n_outer;
-    const cx<T>* ztab;  // the pass's phase tables, in LDS
-    int tid, nthr, nwaves;
-    int nacc;  // slot accumulator entries per slot: one per 16-lane row (or 1)
-};
-
-template <typename T, bool TWO, int R>
-__device__ __forceinline__ void tile_apply1(const TileCtx<T, TWO, R>& c, const TOp& op) {
-    const int q = op.tb[0];
-    const uint32_t qb = 1u << q, lo = qb - 1;
-    const cx<T> m0 = c.coef[op.coff], m1 = c.coef[op.coff + 1], m2 = c.coef[op.coff + 2], m3 = c.coef[op.coff + 3];
-    const int half = (c.nthr * R) >> 1;
-    const int cls = op.cls;
-    for (int p = c.tid; p < half; p += c.nthr) {
-        const uint32_t t0 = (((uint32_t)p & ~lo) << 1) | ((uint32_t)p & lo), t1 = t0 | qb;
-        if ((t0 & op.lcmask) != op.lcval) continue;
-#pragma unroll
-        for (int v = 0; v < (TWO ? 2 : 1); ++v) {
-            cx<T>* t = v ? c.tl : c.tp;
-            const uint32_t s0 = sw(t0), s1 = sw(t1);
-            const cx<T> a0 = t[s0], a1 = t[s1];
-            if (cls == MC_DIAG) {
-                t[s0] = cmul(m0, a0);
-                t[s1] = cmul(m3, a1);
-            } else if (cls == MC_ANTI) {
-                t[s0] = cmul(m1, a1);
-                t[s1] = cmul(m2, a0);
-            } else {
-                t[s0] = cmad(m0, a0, cmul(m1, a1));
-                t[s1] = cmad(m2, a0, cmul(m3, a1));
-            }
-        }
-    }
-}
-
-template <typename T, bool TWO, int R>
-__device__ __forceinline__ void tile_apply2(const TileCtx<T, TWO, R>& c, const TOp& op) {
-    const uint32_t b0 = 1u << op.tb[0], b1 = 1u << op.tb[1];
-    const uint32_t plo = b0 < b1 ? b0 : b1, phi = b0 < b1 ? b1 : b0;
-    const int quarter = (c.nthr * R) >> 2;
-    const cx<T>* m = c.coef + op.coff;
-    const int cls = op.cls;
-    for (int p = c.tid; p < quarter; p += c.nthr) {
-        uint32_t t = (((uint32_t)p & ~(plo - 1)) << 1) | ((uint32_t)p & (plo - 1));
-        t = ((t & ~(phi - 1)) << 1) | (t & (phi - 1));
-        if ((t & op.lcmask) != op.lcval) continue;
-        const uint32_t idx[4] = {sw(t), sw(t | b1), sw(t | b0), sw(t | b0 | b1)};
-#pragma unroll
-        for (int v = 0; v < (TWO ? 2 : 1); ++v) {
-            cx<T>* tt = v ? c.tl : c.tp;
-            if (cls == MC_MID) {
-                const cx<T> x1 = tt[idx[1]], x2 = tt[idx[2]];
-                tt[idx[1]] = cmad(m[5], x1, cmul(m[6], x2));
-                tt[idx[2]] = cmad(m[9], x1, cmul(m[10], x2));
-            } else if (cls == MC_DIAG) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) tt[idx[j]] = cmul(m[j * 5], tt[idx[j]]);
-            } else {
-                cx<T> a[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) a[j] = tt[idx[j]];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    cx<T> acc = {T(0), T(0)};
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) acc = cmad(m[r * 4 + j], a[j], acc);
-                    tt[idx[r]] = acc;
-                }
-            }
-        }
-    }
-}
-
-__device__ __forceinline__ uint32_t spread_bits(int j, int k, const int32_t* tb) {
-    uint32_t o = 0;
-    for (int i = 0; i < k; ++i)
-        if ((j >> (k - 1 - i)) & 1) o |= 1u << tb[i];
-    return o;
-}
-
-// k-qubit matrix (any k) on tile bits tb[0..k-1]: every thread computes
-// output values into registers, then all threads write back after a barrier.
-// With at most one tuple per thread (k >= log2 R), a thread owns R rows of one
-// tuple: tuple = tid mod T, rows from (tid / T) * R, so the rows - and the
-// matrix entries read - are uniform across a wavefront when T >= 64 (scalar
-// loads), and each input is read from LDS once per thread.  Otherwise each
-// element computes its own row.
-template <typename T, bool TWO, int R>
-__device__ __forceinline__ void tile_applyk(const TileCtx<T, TWO, R>& c, const TOp& op) {
-    const int k = op.k, dim = 1 << k;
-    const int tsz = c.nthr * R;
-    const int ntup = tsz >> k;
-    cx<T> ap[R], al[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        ap[r] = {T(0), T(0)};
-        al[r] = {T(0), T(0)};
-    }
-    if (ntup <= c.nthr) {
-        // sorted target bits (k <= 8, uniform), then the tuple's base index
-        int srt[8];
-        for (int i = 0; i < k; ++i) srt[i] = op.tb[i];
-        for (int i = 1; i < k; ++i)
-            for (int j = i; j > 0 && srt[j - 1] > srt[j]; --j) {
-                const int t = srt[j];
-                srt[j] = srt[j - 1];
-                srt[j - 1] = t;
-            }
-        uint32_t tb = (uint32_t)(c.tid & (ntup - 1));
-        for (int i = 0; i < k; ++i) {
-            const uint32_t q = (uint32_t)srt[i];
-            tb = ((tb >> q) << (q + 1)) | (tb & ((1u << q) - 1));
-        }
-        const int row0 = (c.tid / ntup) * R;
-        const bool on = (tb & op.lcmask) == op.lcval;
-        for (int j = 0; j < dim; ++j) {
-            const uint32_t sj = sw(tb | spread_bits(j, k, op.tb));
-            const cx<T> x = c.tp[sj];
-            const cx<T> xl = TWO ? c.tl[sj] : x;
-            const cx<T>* mcol = c.coef + op.coff + (size_t)row0 * dim + j;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const cx<T> mm = mcol[(size_t)r * dim];
-                ap[r] = cmad(mm, x, ap[r]);
-                if (TWO) al[r] = cmad(mm, xl, al[r]);
-            }
-        }
-        __syncthreads();
-        if (on) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const uint32_t so = sw(tb | spread_bits(row0 + r, k, op.tb));
-                c.tp[so] = ap[r];
-                if (TWO) c.tl[so] = al[r];
-            }
-        }
-        return;
-    }
-    uint32_t tmask = 0;
-    for (int i = 0; i < k; ++i) tmask |= 1u << op.tb[i];
-    int row[R];
-    uint32_t gb[R];
-    bool on[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t t = c.tid + r * c.nthr;
-        int rw = 0;
-        for (int i = 0; i < k; ++i) rw = (rw << 1) | ((t >> op.tb[i]) & 1);
-        row[r] = rw;
-        gb[r] = t & ~tmask;
-        on[r] = (t & op.lcmask) == op.lcval;
-    }
-    for (int j = 0; j < dim; ++j) {
-        const uint32_t sp = spread_bits(j, k, op.tb);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const cx<T> mm = c.coef[op.coff + row[r] * dim + j];
-            ap[r] = cmad(mm, c.tp[sw(gb[r] | sp)], ap[r]);
-            if (TWO) al[r] = cmad(mm, c.tl[sw(gb[r] | sp)], al[r]);
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        if (!on[r]) continue;
-        const uint32_t t = c.tid + r * c.nthr;
-        c.tp[sw(t)] = ap[r];
-        if (TWO) c.tl[sw(t)] = al[r];
-    }
-}
-
-template <typename T, bool TWO, int R>
-__device__ __forceinline__ void tile_diag(const TileCtx<T, TWO, R>& c, const TOp& op) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint64_t g = c.base | c.offlo | c.offhi[r];
-        if ((g & op.gcmask) != op.gcval) continue;
-        int j = 0;
-        for (int i = 0; i < op.k; ++i) j = (j << 1) | (int)((g >> op.tb[i]) & 1);
-        const cx<T> d = c.coef[op.coff + j];
-        const int t = c.tid + r * c.nthr;
-        c.tp[sw(t)] = cmul(d, c.tp[sw(t)]);
-        if (TWO) c.tl[sw(t)] = cmul(d, c.tl[sw(t)]);
-    }
-}
-
-// Parity bits (bit j = parity of base & z_j) of this tile's base index: the
-// map is linear over GF(2), so it is the XOR of the host's per-outer-bit
-// columns over the set bits of the tile number (uniform, scalar unit).
-__device__ __forceinline__ uint64_t tile_parity(uint64_t tile, const uint64_t* __restrict__ cols, int n_outer) {
-    uint64_t p = 0;
-    for (int k = 0; k < n_outer; ++k)
-        if ((tile >> k) & 1) p ^= cols[k];
-    return p;
-}
-
-// Z-parity rotation group: the odd-parity bit mask of g = base|offlo|offhi[r]
-// is the XOR of the three parts' masks (parity is linear over GF(2)); the
-// per-thread and per-r parts are precomputed on the host.
-template <typename T, bool TWO, int R>
-__device__ __forceinline__ void tile_zphase(const TileCtx<T, TWO, R>& c, const TOp& op) {
-    const uint64_t* w = c.words + op.woff;
-    const uint64_t pb = tile_parity(c.tile, w + op.m + c.nthr + R, c.n_outer);
-    const uint64_t pl = w[op.m + c.tid] ^ pb;
-    const uint64_t* ph = w + op.m + c.nthr;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int cnt = (int)__popcll(pl ^ ph[r]);
-        const cx<T> d = c.coef[op.coff + cnt];
-        const int t = c.tid + r * c.nthr;
-        c.tp[sw(t)] = cmul(d, c.tp[sw(t)]);
-        if (TWO) c.tl[sw(t)] = cmul(d, c.tl[sw(t)]);
-    }
-}
-
-template <typename T, bool TWO, int R>
-__device__ __forceinline__ void tile_dot(const TileCtx<T, TWO, R>& c, const TOp& op) {
-    if constexpr (TWO) {
-        double acc = 0.0;
-        const cx<T>* G = c.coef + op.coff;
-        if (op.kind == OP_DOT1) {
-            const uint32_t qb = 1u << op.tb[0], lo = qb - 1;
-            const int half = (c.nthr * R) >> 1;
-            for (int p = c.tid; p < half; p += c.nthr) {
-                const uint32_t t0 = (((uint32_t)p & ~lo) << 1) | ((uint32_t)p & lo), t1 = t0 | qb;
-                if ((t0 & op.lcmask) != op.lcval) continue;
-                const cx<T> p0 = c.tp[sw(t0)], p1 = c.tp[sw(t1)];
-                acc += im_conj_mul(c.tl[sw(t0)], cmad(G[0], p0, cmul(G[1], p1)));
-                acc += im_conj_mul(c.tl[sw(t1)], cmad(G[2], p0, cmul(G[3], p1)));
-            }
-        } else if (op.kind == OP_DOT2 || op.kind == OP_DOTK) {
-            const int k = op.k, dim = 1 << k;
-            uint32_t tmask = 0;
-            for (int i = 0; i < k; ++i) tmask |= 1u << op.tb[i];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const uint32_t t = c.tid + r * c.nthr;
-                if ((t & op.lcmask) != op.lcval) continue;
-                int rw = 0;
-                for (int i = 0; i < k; ++i) rw = (rw << 1) | ((t >> op.tb[i]) & 1);
-                const uint32_t gb = t & ~tmask;
-                cx<T> v = {T(0), T(0)};
-                for (int j = 0; j < dim; ++j) v = cmad(G[rw * dim + j], c.tp[sw(gb | spread_bits(j, k, op.tb))], v);
-                acc += im_conj_mul(c.tl[sw(t)], v);
-            }
-        } else if (op.kind == OP_DOTDIAG) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const uint64_t g = c.base | c.offlo | c.offhi[r];
-                if ((g & op.gcmask) != op.gcval) continue;
-                int j = 0;
-                for (int i = 0; i < op.k; ++i) j = (j << 1) | (int)((g >> op.tb[i]) & 1);
-                const int t = c.tid + r * c.nthr;
-                acc += im_conj_mul(c.tl[sw(t)], cmul(G[j], c.tp[sw(t)]));
-            }
-        } else {  // OP_DOTZSUM: generator sum_j Z^{z_j}, eigenvalue m - 2 * (odd count)
-            const uint64_t* w = c.words + op.woff;
-            const uint64_t pb = tile_parity(c.tile, w + op.m + c.nthr + R, c.n_outer);
-            const uint64_t pl = w[op.m + c.tid] ^ pb;
-            const uint64_t* ph = w + op.m + c.nthr;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int cnt = (int)__popcll(pl ^ ph[r]);
-                const int t = c.tid + r * c.nthr;
-                acc += (double)(op.m - 2 * cnt) * im_conj_mul(c.tl[sw(t)], c.tp[sw(t)]);
-            }
-        }
-        block_add(acc, c.red, c.sacc + op.slot * c.nacc, c.tid, c.nthr);
-    }
-}
-
-
-// ------------------------------------------------------------------ register subcube groups
-//
-// A GROUP op names GB tile bits Q.  The tile splits into 2^(b-GB) subcubes
-// of 2^GB elements that agree on the other tile bits; each thread loads whole
-// subcubes from LDS into registers, runs every sub-op of the group on them
-// (1- and 2-qubit matrices on bits of Q, diagonal phases on any global bits,
-// adjoint inner products), and writes them back once: one LDS round trip per
-// group instead of one per gate.  Element e of a subcube is tile index
-// tc | eo[e], eo[e] = sum of bit i of e shifted to Q[i].
-
-// 2x2 update of one register pair, specialised by matrix class
-template <typename T, int CLS>
-__device__ __forceinline__ void bfly(const cx<T>* m, cx<T>& x0, cx<T>& x1) {
-    const cx<T> a0 = x0, a1 = x1;
-    if (CLS == MC_ANTI) {
-        x0 = cmul(m[1], a1);
-        x1 = cmul(m[2], a0);
-    } else if (CLS == MC_REAL) {
-        const T m0 = m[0].re, m1 = m[1].re, m2 = m[2].re, m3 = m[3].re;
-        x0 = {m0 * a0.re + m1 * a1.re, m0 * a0.im + m1 * a1.im};
-        x1 = {m2 * a0.re + m3 * a1.re, m2 * a0.im + m3 * a1.im};
-    } else if (CLS == MC_RIRI) {  // [[r0, i q1], [i q2, r3]]
-        const T r0 = m[0].re, q1 = m[1].im, q2 = m[2].im, r3 = m[3].re;
-        x0 = {r0 * a0.re - q1 * a1.im, r0 * a0.im + q1 * a1.re};
-        x1 = {r3 * a1.re - q2 * a0.im, r3 * a1.im + q2 * a0.re};
-    } else {
-        x0 = cmad(m[0], a0, cmul(m[1], a1));
-        x1 = cmad(m[2], a0, cmul(m[3], a1));
-    }
-}
-
-template <typename T, bool TWO, int GB, int P, int CLS, bool CTRL>
-__device__ __forceinline__ void g_apply1(cx<T>* a, cx<T>* l, const cx<T>* mg, uint32_t tc, const uint32_t* eo,
-                                         uint32_t lcm, uint32_t lcv) {
-    const cx<T> m[4] = {mg[0], mg[1], mg[2], mg[3]};
-#pragma unroll
-    for (int e0 = 0; e0 < (1 << GB); ++e0) {
-        if (e0 & (1 << P)) continue;
-        const int e1 = e0 | (1 << P);
-        if (CTRL && ((tc | eo[e0]) & lcm) != lcv) continue;
-        bfly<T, CLS>(m, a[e0], a[e1]);
-        if (TWO) bfly<T, CLS>(m, l[e0], l[e1]);
-    }
-}
-
-template <typename T, bool TWO, int GB, int P0, int P1, int CLS, bool CTRL>
-__device__ __forceinline__ void g_apply2(cx<T>* a, cx<T>* l, const cx<T>* m, uint32_t tc, const uint32_t* eo,
-                                         uint32_t lcm, uint32_t lcv) {
-#pragma unroll
-    for (int e = 0; e < (1 << GB); ++e) {
-        if (e & ((1 << P0) | (1 << P1))) continue;
-        if (CTRL && ((tc | eo[e]) & lcm) != lcv) continue;
-        const int id[4] = {e, e | (1 << P1), e | (1 << P0), e | (1 << P0) | (1 << P1)};
-#pragma unroll
-        for (int v = 0; v < (TWO ? 2 : 1); ++v) {
-            cx<T>* x = v ? l : a;
-            if (CLS == MC_MID) {
-                const cx<T> x1 = x[id[1]], x2 = x[id[2]];
-                x[id[1]] = cmad(m[5], x1, cmul(m[6], x2));
-                x[id[2]] = cmad(m[9], x1, cmul(m[10], x2));
-            } else {
-                const cx<T> y[4] = {x[id[0]], x[id[1]], x[id[2]], x[id[3]]};
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    cx<T> acc = cmul(m[r * 4], y[0]);
-#pragma unroll
-                    for (int j = 1; j < 4; ++j) acc = cmad(m[r * 4 + j], y[j], acc);
-                    x[id[r]] = acc;
-                }
-            }
-        }
-    }
-}
-
-template <typename T, int GB, int P, int CLS, bool CTRL>
-__device__ __forceinline__ double g_dot1(const cx<T>* a, const cx<T>* l, const cx<T>* G, uint32_t tc,
-                                         const uint32_t* eo, uint32_t lcm, uint32_t lcv) {
-    const cx<T> g0 = G[0], g1 = G[1], g2 = G[2], g3 = G[3];
-    double acc = 0.0;
-#pragma unroll
-    for (int e0 = 0; e0 < (1 << GB); ++e0) {
-        if (e0 & (1 << P)) continue;
-        const int e1 = e0 | (1 << P);
-        if (CTRL && ((tc | eo[e0]) & lcm) != lcv) continue;
-        if (CLS == MC_PX) {         // G = X: Im(l0* p1) + Im(l1* p0)
-            acc += im_conj_mul(l[e0], a[e1]) + im_conj_mul(l[e1], a[e0]);
-        } else if (CLS == MC_PY) {  // G = Y: Re(l1* p0) - Re(l0* p1)
-            acc += (double)l[e1].re * a[e0].re + (double)l[e1].im * a[e0].im -
-                   (double)l[e0].re * a[e1].re - (double)l[e0].im * a[e1].im;
-        } else {
-            acc += im_conj_mul(l[e0], cmad(g0, a[e0], cmul(g1, a[e1])));
-            acc += im_conj_mul(l[e1], cmad(g2, a[e0], cmul(g3, a[e1])));
-        }
-    }
-    return acc;
-}
-
-template <typename T, int GB, int P0, int P1, bool CTRL>
-__device__ __forceinline__ double g_dot2(const cx<T>* a, const cx<T>* l, const cx<T>* G, uint32_t tc,
-                                         const uint32_t* eo, uint32_t lcm, uint32_t lcv) {
-    double acc = 0.0;
-#pragma unroll
-    for (int e = 0; e < (1 << GB); ++e) {
-        if (e & ((1 << P0) | (1 << P1))) continue;
-        if (CTRL && ((tc | eo[e]) & lcm) != lcv) continue;
-        const int id[4] = {e, e | (1 << P1), e | (1 << P0), e | (1 << P0) | (1 << P1)};
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            cx<T> v = cmul(G[r * 4], a[id[0]]);
-#pragma unroll
-            for (int j = 1; j < 4; ++j) v = cmad(G[r * 4 + j], a[id[j]], v);
-            acc += im_conj_mul(l[id[r]], v);
-        }
-    }
-    return acc;
-}
-
-// register accumulators of the group's inner products, selected by a runtime
-// index through a switch so they stay in registers
-struct DotAcc {
-    double v[GROUP_MAX_DOTS];
-    __device__ __forceinline__ void add(int i, double x) {
-        switch (i) {
-        case 0: v[0] += x; break;
-        case 1: v[1] += x; break;
-        case 2: v[2] += x; break;
-        case 3: v[3] += x; break;
-        case 4: v[4] += x; break;
-        case 5: v[5] += x; break;
-        case 6: v[6] += x; break;
-        default: v[7] += x; break;
-        }
-    }
-    __device__ __forceinline__ double get(int i) const {
-        switch (i) {
-        case 0: return v[0];
-        case 1: return v[1];
-        case 2: return v[2];
-        case 3: return v[3];
-        case 4: return v[4];
-        case 5: return v[5];
-        case 6: return v[6];
-        default: return v[7];
-        }
-    }
-};
-
-// One layer of one-qubit ops over every group position.  Ops on different
-// positions commute (and so do a generator on one position and a matrix on
-// another, for the inner products), so the layer runs positions in a fixed
-// order as straight-line code: no per-gate dispatch, and the register arrays
-// flow through without merges.  Per position p the coefficients are
-// [generator (GCLS == DENSE only)] then the 2x2 matrix.
-template <typename T, bool TWO, int GB, int CLS, int GCLS, int P, typename Sink>
-__device__ __forceinline__ void g_layer_pos(cx<T>* a, cx<T>* l, const cx<T>* m, uint32_t dmask, Sink& sink) {
-    constexpr int NC = GCLS == MC_DENSE ? 8 : 4;
-    const cx<T>* mp = m + P * NC;
-    if constexpr (TWO && GCLS >= 0) {
-        if (dmask & (1u << P)) sink(P, g_dot1<T, GB, P, GCLS, false>(a, l, mp, 0, nullptr, 0, 0));
-    }
-    // unconditional: positions without a gate hold the identity, which keeps
-    // the layer branch-free (a skipped position would merge two versions of
-    // the register arrays)
-    g_apply1<T, TWO, GB, P, CLS, false>(a, l, mp + (GCLS == MC_DENSE ? 4 : 0), 0, nullptr, 0, 0);
-}
-
-// sink(p, v) receives this thread's inner product at position p (where bit p
-// of dmask is set), right after it is computed
-template <typename T, bool TWO, int GB, int CLS, int GCLS, typename Sink>
-__device__ __forceinline__ void g_layer(cx<T>* a, cx<T>* l, const cx<T>* m, uint32_t dmask, Sink& sink) {
-    g_layer_pos<T, TWO, GB, CLS, GCLS, 0>(a, l, m, dmask, sink);
-    if constexpr (GB > 1) g_layer_pos<T, TWO, GB, CLS, GCLS, 1>(a, l, m, dmask, sink);
-    if constexpr (GB > 2) g_layer_pos<T, TWO, GB, CLS, GCLS, 2>(a, l, m, dmask, sink);
-    if constexpr (GB > 3) g_layer_pos<T, TWO, GB, CLS, GCLS, 3>(a, l, m, dmask, sink);
-}
-
-#define QSV_P1_CASES(F)                                  \
-    switch (p0) {                                        \
-    case 0: F(0); break;                                 \
-    case 1: if constexpr (GB > 1) { F(1); } break;       \
-    case 2: if constexpr (GB > 2) { F(2); } break;       \
-    case 3: if constexpr (GB > 3) { F(3); } break;       \
-    default: break;                                      \
-    }
-#define QSV_P2_CASE(A, B, F) \
-    case A * 4 + B: if constexpr (GB > A && GB > B) { F(A, B); } break;
-#define QSV_P2_CASES(F)                                                                          \
-    switch (p0 * 4 + p1) {                                                                       \
-    QSV_P2_CASE(0, 1, F) QSV_P2_CASE(0, 2, F) QSV_P2_CASE(0, 3, F) QSV_P2_CASE(1, 0, F)          \
-    QSV_P2_CASE(1, 2, F) QSV_P2_CASE(1, 3, F) QSV_P2_CASE(2, 0, F) QSV_P2_CASE(2, 1, F)          \
-    QSV_P2_CASE(2, 3, F) QSV_P2_CASE(3, 0, F) QSV_P2_CASE(3, 1, F) QSV_P2_CASE(3, 2, F)          \
-    default: break;                                                                              \
-    }
-
-template <typename T, bool TWO, int R, int GB>
-__device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TOp& g, const TOp* __restrict__ subs,
-                                           int b) {
-    constexpr int E = 1 << GB;
-    const int nsub = (c.nthr * R) >> GB;
-    const uint64_t* w = c.words + g.woff;
-    uint32_t eo[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        uint32_t o = 0;
-#pragma unroll
-        for (int i = 0; i < GB; ++i)
-            if ((e >> i) & 1) o |= 1u << g.tb[i];
-        eo[e] = o;
-    }
-    // sw() is linear over GF(2) and tc, eo[e] have disjoint bits, so the
-    // LDS slot of element e is sw(tc) ^ sw(eo[e]) (a uniform XOR)
-    uint32_t swe[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) swe[e] = sw(eo[e]);
-    DotAcc acc;
-#pragma unroll
-    for (int d = 0; d < GROUP_MAX_DOTS; ++d) acc.v[d] = 0.0;
-    const int nq = b - GB;
-    const bool need_gc = g.aux != 0;  // the group holds position-dependent diagonals
-    // every thread runs the same number of subcubes (all lanes active inside
-    // the loop): layers reduce their inner products right away, per 16-lane
-    // row by DPP, into the row's own slot accumulator
-    const bool inloop = c.nthr >= 64 && nsub >= c.nthr;
-    auto row_flush = [&](double v, int slot) {
-        v += row_shr<1>(v);
-        v += row_shr<2>(v);
-        v += row_shr<4>(v);
-        v += row_shr<8>(v);
-        if ((c.tid & 15) == 15) c.sacc[slot * c.nacc + (c.tid >> 4)] += v;
-    };
-#pragma unroll 1
-    for (int sc = c.tid; sc < nsub; sc += c.nthr) {
-        uint32_t tc = (uint32_t)sc;
-#pragma unroll
-        for (int i = 0; i < GB; ++i) {  // Q ascending: insert a zero at each Q bit
-            const uint32_t q = (uint32_t)g.tb[i];
-            tc = ((tc >> q) << (q + 1)) | (tc & ((1u << q) - 1));
-        }
-        uint64_t gc = c.base;
-        if (need_gc)
-            for (int j = 0; j < nq; ++j)
-                if ((sc >> j) & 1) gc |= 1ull << w[E + j];
-        const uint32_t stc = sw(tc);
-        cx<T> a[E], l[TWO ? E : 1];
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            a[e] = c.tp[stc ^ swe[e]];
-            if (TWO) l[e] = c.tl[stc ^ swe[e]];
-        }
-        for (int si = 0; si < g.m; ++si) {
-            const TOp& s = subs[si];
-            const bool local = s.kind == OP_APPLY1 || s.kind == OP_APPLY2 || s.kind == OP_DOT1 || s.kind == OP_DOT2;
-            if (local && (c.base & s.gcmask) != s.gcval) continue;
-            const cx<T>* m = c.coef + s.coff;
-            const int p0 = s.tb[0], p1 = s.tb[1];
-            switch (s.kind) {
-            case OP_APPLY1: {
-                const bool ctrl = s.lcmask != 0;
-                if (ctrl) {
-#define F(P) g_apply1<T, TWO, GB, P, MC_DENSE, true>(a, l, m, tc, eo, s.lcmask, s.lcval)
-                    QSV_P1_CASES(F)
-#undef F
-                } else if (s.cls == MC_ANTI) {
-#define F(P) g_apply1<T, TWO, GB, P, MC_ANTI, false>(a, l, m, tc, eo, 0, 0)
-                    QSV_P1_CASES(F)
-#undef F
-                } else if (s.cls == MC_REAL) {
-#define F(P) g_apply1<T, TWO, GB, P, MC_REAL, false>(a, l, m, tc, eo, 0, 0)
-                    QSV_P1_CASES(F)
-#undef F
-                } else if (s.cls == MC_RIRI) {
-#define F(P) g_apply1<T, TWO, GB, P, MC_RIRI, false>(a, l, m, tc, eo, 0, 0)
-                    QSV_P1_CASES(F)
-#undef F
-                } else {
-#define F(P) g_apply1<T, TWO, GB, P, MC_DENSE, false>(a, l, m, tc, eo, 0, 0)
-                    QSV_P1_CASES(F)
-#undef F
-                }
-            } break;
-            case OP_APPLY2:
-                if (s.lcmask) {
-                    if (s.cls == MC_MID) {
-#define F(A, B) g_apply2<T, TWO, GB, A, B, MC_MID, true>(a, l, m, tc, eo, s.lcmask, s.lcval)
-                        QSV_P2_CASES(F)
-#undef F
-                    } else {
-#define F(A, B) g_apply2<T, TWO, GB, A, B, MC_DENSE, true>(a, l, m, tc, eo, s.lcmask, s.lcval)
-                        QSV_P2_CASES(F)
-#undef F
-                    }
-                } else if (s.cls == MC_MID) {
-#define F(A, B) g_apply2<T, TWO, GB, A, B, MC_MID, false>(a, l, m, tc, eo, 0, 0)
-                    QSV_P2_CASES(F)
-#undef F
-                } else {
-#define F(A, B) g_apply2<T, TWO, GB, A, B, MC_DENSE, false>(a, l, m, tc, eo, 0, 0)
-                    QSV_P2_CASES(F)
-#undef F
-                }
-                break;
-            case OP_LAYER1: {
-                // template GCLS: -1 without inner products, else the generator's class
-                const uint32_t gcode = TWO ? s.lcval : (uint32_t)LG_NONE;
-                // every lane active here: reduce per row at once; otherwise
-                // keep the sums for the flush after the loop
-                int ai = s.aux;
-                auto sink = [&](int p, double v) {
-                    if (inloop) row_flush(v, s.tb[p]);
-                    else acc.add(ai++, v);
-                };
-#define L(C, G) g_layer<T, TWO, GB, C, G>(a, l, m, s.lcmask, sink)
-                if (gcode == LG_NONE) {
-                    if (s.cls == MC_REAL) L(MC_REAL, -1);
-                    else if (s.cls == MC_RIRI) L(MC_RIRI, -1);
-                    else L(MC_DENSE, -1);
-                } else if constexpr (TWO) {
-                    if (gcode == LG_X) {
-                        if (s.cls == MC_REAL) L(MC_REAL, MC_PX);
-                        else if (s.cls == MC_RIRI) L(MC_RIRI, MC_PX);
-                        else L(MC_DENSE, MC_PX);
-                    } else if (gcode == LG_Y) {
-                        if (s.cls == MC_REAL) L(MC_REAL, MC_PY);
-                        else if (s.cls == MC_RIRI) L(MC_RIRI, MC_PY);
-                        else L(MC_DENSE, MC_PY);
-                    } else {
-                        if (s.cls == MC_REAL) L(MC_REAL, MC_DENSE);
-                        else if (s.cls == MC_RIRI) L(MC_RIRI, MC_DENSE);
-                        else L(MC_DENSE, MC_DENSE);
-                    }
-                }
-#undef L
-            } break;
-            case OP_DIAG:
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const uint64_t gi = gc | w[e];
-                    if ((gi & s.gcmask) != s.gcval) continue;
-                    int j = 0;
-                    for (int i = 0; i < s.k; ++i) j = (j << 1) | (int)((gi >> s.tb[i]) & 1);
-                    const cx<T> d = m[j];
-                    a[e] = cmul(d, a[e]);
-                    if (TWO) l[e] = cmul(d, l[e]);
-                }
-                break;
-            case OP_ZPHASE: {
-                const uint64_t* z = c.words + s.woff;
-                const uint64_t pc = tile_parity(c.tile, z + s.m + nsub + E, c.n_outer) ^ z[s.m + sc];
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const cx<T> d = c.ztab[s.aux + (int)__popcll(pc ^ z[s.m + nsub + e])];
-                    a[e] = cmul(d, a[e]);
-                    if (TWO) l[e] = cmul(d, l[e]);
-                }
-            } break;
-            default:
-                if constexpr (TWO) {
-                    double v = 0.0;
-                    if (s.kind == OP_DOT1) {
-                        if (s.lcmask) {
-#define F(P) v = g_dot1<T, GB, P, MC_DENSE, true>(a, l, m, tc, eo, s.lcmask, s.lcval)
-                            QSV_P1_CASES(F)
-#undef F
-                        } else if (s.cls == MC_PX) {
-#define F(P) v = g_dot1<T, GB, P, MC_PX, false>(a, l, m, tc, eo, 0, 0)
-                            QSV_P1_CASES(F)
-#undef F
-                        } else if (s.cls == MC_PY) {
-#define F(P) v = g_dot1<T, GB, P, MC_PY, false>(a, l, m, tc, eo, 0, 0)
-                            QSV_P1_CASES(F)
-#undef F
-                        } else {
-#define F(P) v = g_dot1<T, GB, P, MC_DENSE, false>(a, l, m, tc, eo, 0, 0)
-                            QSV_P1_CASES(F)
-#undef F
-                        }
-                    } else if (s.kind == OP_DOT2) {
-                        if (s.lcmask) {
-#define F(A, B) v = g_dot2<T, GB, A, B, true>(a, l, m, tc, eo, s.lcmask, s.lcval)
-                            QSV_P2_CASES(F)
-#undef F
-                        } else {
-#define F(A, B) v = g_dot2<T, GB, A, B, false>(a, l, m, tc, eo, 0, 0)
-                            QSV_P2_CASES(F)
-#undef F
-                        }
-                    } else if (s.kind == OP_DOTDIAG) {
-#pragma unroll
-                        for (int e = 0; e < E; ++e) {
-                            const uint64_t gi = gc | w[e];
-                            if ((gi & s.gcmask) != s.gcval) continue;
-                            int j = 0;
-                            for (int i = 0; i < s.k; ++i) j = (j << 1) | (int)((gi >> s.tb[i]) & 1);
-                            v += im_conj_mul(l[e], cmul(m[j], a[e]));
-                        }
-                    } else {  // OP_DOTZSUM
-                        const uint64_t* z = c.words + s.woff;
-                        const uint64_t pc = tile_parity(c.tile, z + s.m + nsub + E, c.n_outer) ^ z[s.m + sc];
-#pragma unroll
-                        for (int e = 0; e < E; ++e)
-                            v += (double)(s.m - 2 * (int)__popcll(pc ^ z[s.m + nsub + e])) * im_conj_mul(l[e], a[e]);
-                    }
-                    if (inloop) row_flush(v, s.slot);
-                    else acc.add(s.aux, v);
-                }
-                break;
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            c.tp[stc ^ swe[e]] = a[e];
-            if (TWO) c.tl[stc ^ swe[e]] = l[e];
-        }
-    }
-    if constexpr (TWO) {
-        // flush: per-wave sums into the wave's accumulator (no barrier when
-        // the block is made of whole waves)
-        // per 16-lane row: DPP prefix sums leave the row's total in its last
-        // lane, which adds it to the row's own accumulator (no cross-row
-        // traffic; the block sums the rows once at the end)
-        auto flush = [&](int ai, int slot) {
-            double v = acc.get(ai);
-            if (c.nthr >= 64) {
-                v += row_shr<1>(v);
-                v += row_shr<2>(v);
-                v += row_shr<4>(v);
-                v += row_shr<8>(v);
-                if ((c.tid & 15) == 15) c.sacc[slot * c.nacc + (c.tid >> 4)] += v;
-            } else {
-                block_add(v, c.red, c.sacc + slot * c.nacc, c.tid, c.nthr);
-            }
-        };
-        for (int si = 0; si < g.m; ++si) {
-            const TOp& s = subs[si];
-            if (s.kind == OP_LAYER1) {
-                if (inloop) continue;  // reduced inside the loop
-                int ai = s.aux;
-                for (int p = 0; p < GB; ++p)
-                    if (s.lcmask & (1u << p)) flush(ai++, s.tb[p]);
-                continue;
-            }
-            if (s.kind < OP_DOT1 || s.kind == OP_DOTK || s.kind > OP_DOTZSUM) continue;
-            if (inloop) continue;  // reduced inside the loop
-            flush(s.aux, s.slot);
-        }
-    }
-}
-
-// GEN: the pass also holds standalone ops (k-qubit matrices, or a tile too
-// small for groups); group-only passes compile without those code paths,
-// which keeps their register footprint (and so their occupancy) lower.
-// One block's share of a tile pass: tiles blk, blk + nblk, ... of the pass
-// described by a.  phi_src is where phi is read from (phi itself, or the
-// post-circuit state for an out-of-place first adjoint pass); with
-// TILE_SYNTH the tile is synthesised as the basis state a.basis instead.
-template <typename T, bool TWO, int LR, bool GEN>
-__device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
-                                          cx<T>* __restrict__ lam, const TileArgs& a, const TOp* __restrict__ ops,
-                                          const cx<T>* __restrict__ coef, const uint64_t* __restrict__ words,
-                                          double* __restrict__ partials, uint64_t blk, uint64_t nblk) {
-    constexpr int R = 1 << LR;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int tid = threadIdx.x;
-    // tiles of more than 256 elements always run 256 threads: a compile-time
-    // block size turns every per-element LDS offset into an immediate
-    const int nthr = LR > 0 ? 256 : (int)blockDim.x;
-    const int tsz = nthr * R;
-    // LDS slot of the thread's element r: sw(tid + r * nthr) = sw(tid) + r * nthr
-    // (r * nthr only has bits at or above bit 8 when R > 1)
-    const uint32_t stid = sw((uint32_t)tid);
-    TileCtx<T, TWO, R> c;
-    c.tp = reinterpret_cast<cx<T>*>(smem);
-    c.tl = c.tp + (TWO ? tsz : 0);
-    c.red = reinterpret_cast<double*>(smem + (TWO ? 2 : 1) * (size_t)tsz * sizeof(cx<T>));
-    c.sacc = c.red + 64;
-    c.coef = coef;
-    c.words = words;
-    c.offhi = a.offhi;
-    c.n_outer = a.n_outer;
-    c.tid = tid;
-    c.nthr = nthr;
-    c.nwaves = nthr >= 64 ? nthr >> 6 : 1;
-    c.nacc = nthr >= 64 ? nthr >> 4 : 1;
-    {
-        // phase tables after the per-wave slot accumulators, 16-byte aligned
-        const size_t off = (64 + (size_t)a.nslots * c.nacc) * sizeof(double);
-        cx<T>* zt = reinterpret_cast<cx<T>*>(reinterpret_cast<unsigned char*>(c.red) + ((off + 15) & ~(size_t)15));
-        for (int i = tid; i < a.zt_n; i += nthr) zt[i] = coef[a.zt_off + i];
-        c.ztab = zt;
-    }
-    uint64_t offlo = 0;
-    for (int j = 0; j < a.nthr_log2; ++j) offlo |= (uint64_t)((tid >> j) & 1) << a.sb[j];
-    c.offlo = offlo;
-    for (int s = tid; s < a.nslots * c.nacc; s += nthr) c.sacc[s] = 0.0;
-    const bool synth = (a.flags & TILE_SYNTH) != 0;
-
-    for (uint64_t tile = blk; tile < a.n_tiles; tile += nblk) {
-        const uint64_t base = expand_idx(tile, a.outer);
-        c.base = base;
-        c.tile = tile;
-        // global -> LDS in chunks of LCH elements per thread: LCH loads in
-        // flight per thread without keeping all R values live in registers
-        constexpr int LCH = R < 8 ? R : 8;
-        for (int r0 = 0; r0 < R; r0 += LCH) {
-            cx<T> vp[LCH], vl[LCH];
-#pragma unroll
-            for (int r = 0; r < LCH; ++r) {
-                const uint64_t g = base | offlo | a.offhi[r0 + r];
-                if (synth) {
-                    vp[r].re = g == a.basis ? T(1) : T(0);
-                    vp[r].im = T(0);
-                } else {
-                    vp[r] = phi_src[g];
-                }
-                if (TWO) vl[r] = lam[g];
-            }
-#pragma unroll
-            for (int r = 0; r < LCH; ++r) {
-                c.tp[stid + (r0 + r) * nthr] = vp[r];
-                if (TWO) c.tl[stid + (r0 + r) * nthr] = vl[r];
-            }
-        }
-        __syncthreads();
-        for (int oi = 0; oi < a.nops; ++oi) {
-            const TOp& op = ops[a.op0 + oi];
-            if ((op.kind <= OP_APPLYK || (op.kind >= OP_DOT1 && op.kind <= OP_DOTK)) &&
-                (base & op.gcmask) != op.gcval)
-                continue;  // outer controls fail for this whole tile (uniform)
-            if (op.kind == OP_GROUP) {
-                tile_group<T, TWO, R, TWO ? GROUP_BITS_TWO : GROUP_BITS_ONE>(c, op, ops + a.op0 + oi + 1, a.b);
-                oi += op.m;
-                __syncthreads();
-                continue;
-            }
-            if constexpr (GEN) {
-                switch (op.kind) {
-                case OP_APPLY1: tile_apply1(c, op); break;
-                case OP_APPLY2: tile_apply2(c, op); break;
-                case OP_APPLYK: tile_applyk(c, op); break;
-                case OP_DIAG: tile_diag(c, op); break;
-                case OP_ZPHASE: tile_zphase(c, op); break;
-                default: tile_dot(c, op); break;
-                }
-            }
-            __syncthreads();
-        }
-        for (int r0 = 0; r0 < R; r0 += LCH) {
-#pragma unroll
-            for (int r = 0; r < LCH; ++r) {
-                const uint64_t g = base | offlo | a.offhi[r0 + r];
-                phi[g] = c.tp[stid + (r0 + r) * nthr];
-                if (TWO) lam[g] = c.tl[stid + (r0 + r) * nthr];
-            }
-        }
-        __syncthreads();
-    }
-    __syncthreads();
-    for (int s = tid; s < a.nslots; s += nthr) {
-        double v = 0.0;
-        for (int w = 0; w < c.nacc; ++w) v += c.sacc[s * c.nacc + w];
-        partials[(uint64_t)s * nblk + blk] = v;
-    }
-}
-
-template <typename T, bool TWO, int LR, bool GEN>
-__global__ __launch_bounds__(256, 2) void k_tile(const cx<T>* phi_src, cx<T>* phi, cx<T>* __restrict__ lam,
-                                                 const TileArgs a, const TOp* __restrict__ ops,
-                                                 const cx<T>* __restrict__ coef, const uint64_t* __restrict__ words,
-                                                 double* __restrict__ partials) {
-    tile_body<T, TWO, LR, GEN>(phi_src, phi, lam, a, ops, coef, words, partials, blockIdx.x, gridDim.x);
-}
-
-// Batched passes: block b serves entry blk_entry[b] (one circuit's pass).
-template <typename T, bool TWO, int LR, bool GEN>
-__global__ __launch_bounds__(256, 2) void k_tile_batch(const TileEntry* __restrict__ entries,
-                                                       const int32_t* __restrict__ blk_entry,
-                                                       const TileArgs* __restrict__ args, const TOp* __restrict__ ops,
-                                                       const cx<T>* __restrict__ coef,
-                                                       const uint64_t* __restrict__ words,
-                                                       double* __restrict__ partials) {
-    const TileEntry& e = entries[blk_entry[blockIdx.x]];
-    tile_body<T, TWO, LR, GEN>((const cx<T>*)e.phi_src, (cx<T>*)e.phi, (cx<T>*)e.lam, args[e.args], ops, coef, words,
-                               partials + e.part_off, blockIdx.x - e.blk0, e.nblk);
-}
+// ------------------------------------------------------------------ tile passes (tile_*.hip)
 
 int tile_lds_bytes(int b, bool two, int elem_bytes, int nslots, int zt_n) {
     const int nthr = 1 << (b < 8 ? b : 8);
@@ -1285,102 +309,26 @@ int tile_lds_bytes(int b, bool two, int elem_bytes, int nslots, int zt_n) {
     return (two ? 2 : 1) * (1 << b) * elem_bytes + acc + zt_n * elem_bytes;
 }
 
-template <typename T, bool TWO, int LR, bool GEN>
-static hipError_t launch_tile_lr(hipStream_t s, const void* phi_src, void* phi, void* lam, const TileArgs& a,
-                                 const TOp* ops, const void* coef, const uint64_t* words, double* partials, int grid,
-                                 int nthr, size_t lds) {
-    static std::atomic<uint64_t> lds_raised{0};
-    if (lds > 65536) {
-        hipError_t e = allow_big_lds((const void*)k_tile<T, TWO, LR, GEN>, lds_raised);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL((k_tile<T, TWO, LR, GEN>), dim3(grid), dim3(nthr), lds, s, (const cx<T>*)phi_src, (cx<T>*)phi,
-                       (cx<T>*)lam, a, ops, (const cx<T>*)coef, words, partials);
-    return hipGetLastError();
-}
-
-template <typename T, bool TWO, bool GEN>
-static hipError_t launch_tile_two(hipStream_t s, const void* phi_src, void* phi, void* lam, const TileArgs& a,
-                                  const TOp* ops, const void* coef, const uint64_t* words, double* partials, int grid,
-                                  int nthr, int R, size_t lds) {
-    switch (R) {
-    case 1: return launch_tile_lr<T, TWO, 0, GEN>(s, phi_src, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
-    case 2: return launch_tile_lr<T, TWO, 1, GEN>(s, phi_src, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
-    case 4: return launch_tile_lr<T, TWO, 2, GEN>(s, phi_src, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
-    case 8: return launch_tile_lr<T, TWO, 3, GEN>(s, phi_src, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
-    case 16: return launch_tile_lr<T, TWO, 4, GEN>(s, phi_src, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
-    case 32: return launch_tile_lr<T, TWO, 5, GEN>(s, phi_src, phi, lam, a, ops, coef, words, partials, grid, nthr, lds);
-    default: return hipErrorInvalidValue;
-    }
-}
-
 template <typename T>
 hipError_t launch_tile(hipStream_t s, bool two, bool generic, const void* phi_src, void* phi, void* lam,
                        const TileArgs& a, const TOp* ops, const void* coef, const uint64_t* words, double* partials,
                        int grid, int nthr, int R, size_t lds_bytes) {
-    if (two) {
-        if (generic)
-            return launch_tile_two<T, true, true>(s, phi_src, phi, lam, a, ops, coef, words, partials, grid, nthr, R,
-                                                  lds_bytes);
-        return launch_tile_two<T, true, false>(s, phi_src, phi, lam, a, ops, coef, words, partials, grid, nthr, R,
-                                               lds_bytes);
-    }
-    if (generic)
-        return launch_tile_two<T, false, true>(s, phi_src, phi, lam, a, ops, coef, words, partials, grid, nthr, R,
-                                               lds_bytes);
-    return launch_tile_two<T, false, false>(s, phi_src, phi, lam, a, ops, coef, words, partials, grid, nthr, R,
-                                            lds_bytes);
-}
-
-template <typename T, bool TWO, int LR, bool GEN>
-static hipError_t launch_tile_batch_lr(hipStream_t s, const TileEntry* entries, const int32_t* blk_entry,
-                                       const TileArgs* args, const TOp* ops, const void* coef, const uint64_t* words,
-                                       double* partials, int blocks, int nthr, size_t lds) {
-    static std::atomic<uint64_t> lds_raised{0};
-    if (lds > 65536) {
-        hipError_t e = allow_big_lds((const void*)k_tile_batch<T, TWO, LR, GEN>, lds_raised);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL((k_tile_batch<T, TWO, LR, GEN>), dim3(blocks), dim3(nthr), lds, s, entries, blk_entry, args,
-                       ops, (const cx<T>*)coef, words, partials);
-    return hipGetLastError();
-}
-
-template <typename T, bool TWO, bool GEN>
-static hipError_t launch_tile_batch_two(hipStream_t s, const TileEntry* entries, const int32_t* blk_entry,
-                                        const TileArgs* args, const TOp* ops, const void* coef,
-                                        const uint64_t* words, double* partials, int blocks, int nthr, int R,
-                                        size_t lds) {
-#define QSV_TB(LRV) launch_tile_batch_lr<T, TWO, LRV, GEN>(s, entries, blk_entry, args, ops, coef, words, partials, \
-                                                           blocks, nthr, lds)
-    switch (R) {
-    case 1: return QSV_TB(0);
-    case 2: return QSV_TB(1);
-    case 4: return QSV_TB(2);
-    case 8: return QSV_TB(3);
-    case 16: return QSV_TB(4);
-    case 32: return QSV_TB(5);
-    default: return hipErrorInvalidValue;
-    }
-#undef QSV_TB
+    if (two)
+        return launch_tile_v<T, true>(s, generic, phi_src, phi, lam, a, ops, coef, words, partials, grid, nthr, R,
+                                      lds_bytes);
+    return launch_tile_v<T, false>(s, generic, phi_src, phi, lam, a, ops, coef, words, partials, grid, nthr, R,
+                                   lds_bytes);
 }
 
 template <typename T>
 hipError_t launch_tile_batch(hipStream_t s, bool two, bool generic, const TileEntry* entries,
                              const int32_t* blk_entry, const TileArgs* args, const TOp* ops, const void* coef,
                              const uint64_t* words, double* partials, int blocks, int nthr, int R, size_t lds) {
-    if (two) {
-        if (generic)
-            return launch_tile_batch_two<T, true, true>(s, entries, blk_entry, args, ops, coef, words, partials,
-                                                        blocks, nthr, R, lds);
-        return launch_tile_batch_two<T, true, false>(s, entries, blk_entry, args, ops, coef, words, partials, blocks,
-                                                     nthr, R, lds);
-    }
-    if (generic)
-        return launch_tile_batch_two<T, false, true>(s, entries, blk_entry, args, ops, coef, words, partials, blocks,
-                                                     nthr, R, lds);
-    return launch_tile_batch_two<T, false, false>(s, entries, blk_entry, args, ops, coef, words, partials, blocks,
-                                                  nthr, R, lds);
+    if (two)
+        return launch_tile_batch_v<T, true>(s, generic, entries, blk_entry, args, ops, coef, words, partials, blocks,
+                                            nthr, R, lds);
+    return launch_tile_batch_v<T, false>(s, generic, entries, blk_entry, args, ops, coef, words, partials, blocks,
+                                         nthr, R, lds);
 }
 
 // ------------------------------------------------------------------ Pauli sums

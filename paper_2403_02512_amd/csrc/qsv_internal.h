@@ -162,6 +162,16 @@ template <typename T> hipError_t launch_tile(hipStream_t s, bool two, bool gener
                                              void* lam, const TileArgs& a,
                                              const TOp* ops, const void* coef, const uint64_t* words,
                                              double* partials, int grid, int nthr, int R, size_t lds_bytes);
+// per (precision, one or two vectors): defined in k_tile.h, instantiated in tile_*.hip
+template <typename T, bool TWO> hipError_t launch_tile_v(hipStream_t s, bool generic, const void* phi_src, void* phi,
+                                                         void* lam, const TileArgs& a, const TOp* ops,
+                                                         const void* coef, const uint64_t* words, double* partials,
+                                                         int grid, int nthr, int R, size_t lds_bytes);
+template <typename T, bool TWO> hipError_t launch_tile_batch_v(hipStream_t s, bool generic, const TileEntry* entries,
+                                                               const int32_t* blk_entry, const TileArgs* args,
+                                                               const TOp* ops, const void* coef,
+                                                               const uint64_t* words, double* partials, int blocks,
+                                                               int nthr, int R, size_t lds);
 template <typename T> hipError_t launch_tile_batch(hipStream_t s, bool two, bool generic, const TileEntry* entries,
                                                    const int32_t* blk_entry, const TileArgs* args, const TOp* ops,
                                                    const void* coef, const uint64_t* words, double* partials,

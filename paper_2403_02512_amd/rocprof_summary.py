@@ -8,8 +8,10 @@
       HBM bytes per dispatch from FETCH_SIZE and WRITE_SIZE (KiB per
       dispatch), each scaled by the factor that makes the runtime's copy
       kernel (__amd_rocclr_copyBuffer, which moves B bytes each way) read and
-      write exactly B bytes; one machine-readable line per kernel, plus the
-      SHA-1 of the kernel source the counters were taken on.
+      write exactly B bytes; one machine-readable line per kernel, plus one
+      SHA-1 over every source file of the library (kernels, planner,
+      lowering, gate tables), so that a change to any of them, and with it
+      possibly the launched programs, retires the counters.
 """
 from __future__ import annotations
 
@@ -20,18 +22,28 @@ import hashlib
 import os
 import sys
 
-KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "kernels.hip")
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
-KINDS = [("k_tile<double, true", "tile2"), ("k_tile<double, false", "tile1"), ("k_tile<float, true", "tile2"),
-         ("k_tile<float, false", "tile1"), ("k_pauli<double, true", "pauli_lambda"),
+KINDS = [("k_tile<double, true", "tile2"), ("k_tile<double, false", "tile1"), ("k_tile<float, true", "tile2_c64"),
+         ("k_tile<float, false", "tile1_c64"), ("k_pauli<double, true", "pauli_lambda"),
          ("k_pauli<double, false", "pauli"), ("__amd_rocclr_copyBuffer", "copy"), ("k_init", "init"),
          ("k_reduce", "reduce"), ("k_gate1", "gate1"), ("k_diag1", "diag1"), ("k_gate2", "gate2"),
          ("k_gatek", "gatek")]
 
 
-def source_sha1(path: str = KERNEL_SOURCE) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha1(f.read()).hexdigest()
+def source_sha1(root: str = CSRC) -> str:
+    """SHA-1 over the names and contents of every file under csrc/, in
+    sorted order."""
+    h = hashlib.sha1()
+    for name in sorted(os.listdir(root)):
+        p = os.path.join(root, name)
+        if not os.path.isfile(p):
+            continue
+        h.update(name.encode() + b"\0")
+        with open(p, "rb") as f:
+            h.update(f.read())
+        h.update(b"\0")
+    return h.hexdigest()
 
 
 def short(name: str) -> str:
@@ -76,7 +88,7 @@ def traffic(fetch_csv: str, write_csv: str, copy_bytes: float, cmd: str) -> str:
            f"calibration: copy kernel moving {copy_bytes:.0f} B each way reads FETCH_SIZE "
            f"{max(fetch[cp[0]]):.0f} B and WRITE_SIZE {max(write[cp[0]]):.0f} B -> "
            f"fetch_scale={f_scale:.4f} write_scale={w_scale:.4f}",
-           f"kernel_source_sha1={source_sha1()}", ""]
+           f"library_source_sha1={source_sha1()}", ""]
     for k in fetch:
         if k not in write or "copyBuffer" in k:
             continue
@@ -89,12 +101,12 @@ def traffic(fetch_csv: str, write_csv: str, copy_bytes: float, cmd: str) -> str:
 
 def read_traffic(path: str):
     """{kind: traffic bytes per dispatch} if the summary was taken on the
-    current kernel source, else None."""
+    current library sources, else None."""
     if not os.path.exists(path):
         return None
     kv, sha = {}, None
     for line in open(path):
-        if line.startswith("kernel_source_sha1="):
+        if line.startswith("library_source_sha1="):
             sha = line.strip().split("=", 1)[1]
         elif line.startswith("kind="):
             d = dict(x.split("=", 1) for x in line.split())

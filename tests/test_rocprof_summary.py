@@ -42,3 +42,17 @@ def test_kernel_kinds():
     assert rs.kind_of("void qsv::k_pauli<float, true, false>(x)") == "other"
     assert rs.kind_of("void qsv::k_pauli<double, true, false>(x)") == "pauli_lambda"
     assert rs.kind_of("__amd_rocclr_copyBuffer") == "copy"
+
+
+def test_source_hash_covers_every_library_source(tmp_path):
+    # the counters are retired by a change to any source under csrc/, not
+    # only the kernels: the planner and lowering decide the launched programs
+    for name in ("kernels.hip", "plan.cpp", "api.cpp"):
+        (tmp_path / name).write_text("x")
+    h0 = rs.source_sha1(str(tmp_path))
+    (tmp_path / "plan.cpp").write_text("y")
+    h1 = rs.source_sha1(str(tmp_path))
+    (tmp_path / "new.h").write_text("")
+    h2 = rs.source_sha1(str(tmp_path))
+    assert len({h0, h1, h2}) == 3
+    assert rs.source_sha1() == rs.source_sha1(rs.CSRC)
