@@ -268,7 +268,7 @@ size_t elem_bytes(qsv_dtype d) { return d == QSV_C128 ? 16 : 8; }
 // ------------------------------------------------------------------ lowering
 
 struct Step {
-    enum Type { TILE, GATE1, DIAG1, GATE2, GATEK, GATEK_LOW } type = TILE;
+    enum Type { TILE, GATE1, DIAG1, GATE2, GATEK, GATEK_LOW, DENSE } type = TILE;
     // tile
     TileArgs ta{};
     int grid = 1, nthr = 1, R = 1;
@@ -285,6 +285,7 @@ struct Step {
     Mat4 m4{};
     int64_t coff = 0;
     double dre = 0, dim = 0;
+    DenseArgs da{};  // DENSE
     double bytes = 0;
 };
 
@@ -522,7 +523,15 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
             q = e;
             continue;
         }
-        if (!it.xbits) {
+        const int tbit0 = n - 1 - f.tw[0];
+        if (!it.xbits && f.k == 1 && f.nc == 0 && ((pass.S >> tbit0) & 1)) {
+            // an uncontrolled one-qubit diagonal (PhaseShift, the phase factors
+            // of U3 / Rot) on a tile bit: a 2x2 matrix on a group position, so
+            // it runs in register layers instead of evaluating its global
+            // index per element
+            pr.kind = it.dot ? Proto::DOT : Proto::APPLY;
+            pr.tbits = 1u << rank[tbit0];
+        } else if (!it.xbits) {
             if (f.k > 6) fail(QSV_ERR_UNSUPPORTED, "diagonal factor wider than 6 targets");
             pr.kind = it.dot ? Proto::DOTDIAG : Proto::DIAG;
         } else {
@@ -811,6 +820,9 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
     for (auto& x : ztab) P.coef.push_back(x);
     st.nslots = nslots;
     st.lds = (size_t)tile_lds_bytes(b, two, (int)eb, nslots, a.zt_n);
+    if (st.lds > (size_t)LDS_PER_CU)  // the planner's budget keeps passes below this
+        fail(QSV_ERR_UNSUPPORTED, "tile pass needs more LDS than a CU has");
+    if (tile_prefetch(st.lds, R)) st.grid = (int)std::min<uint64_t>(a.n_tiles, TILE_PF_GRID);
     st.bytes = (double)(two ? 4 : 2) * (double)((uint64_t)1 << n) * (double)eb;
     P.max_partials = std::max(P.max_partials, (size_t)nslots * st.grid);
     P.steps.push_back(st);
@@ -861,6 +873,52 @@ bool lower_single(Program& P, const Factor& f, int n, size_t eb, int low_bits) {
             st.m4.im[j] = f.m[j].imag();
         }
         st.bytes = (st.cls == MC_MID ? 1.0 : 2.0) * N * eb * frac;
+    } else if (f.k >= 3 && f.k <= 6 && n - f.nc >= f.k + 6) {
+        // LDS-staged dense matrix: targets plus six lane bits per tile
+        st.type = Step::DENSE;
+        DenseArgs& d = st.da;
+        d.k = f.k;
+        uint64_t used = 0;
+        for (int p : pos) used |= 1ull << p;
+        std::vector<int> lane;
+        for (int p = 0; p < n && (int)lane.size() < 6; ++p)
+            if (!((used >> p) & 1)) lane.push_back(p);
+        std::vector<int> tbits;  // tile bits ascending
+        for (int i = 0; i < f.k; ++i) tbits.push_back(n - 1 - f.tw[i]);
+        for (int p : lane) tbits.push_back(p);
+        std::sort(tbits.begin(), tbits.end());
+        for (int i = 0; i < f.k + 6; ++i) {
+            d.sb[i] = tbits[i];
+            const auto li = std::find(lane.begin(), lane.end(), tbits[i]);
+            if (li != lane.end()) {
+                d.cb[i] = (int)(li - lane.begin());
+            } else {
+                int t = 0;
+                while (n - 1 - f.tw[t] != tbits[i]) ++t;
+                d.cb[i] = 6 + (f.k - 1 - t);  // target 0 is the matrix index's msb
+            }
+        }
+        const int rl = (64 << f.k) / 256;
+        for (int r = 0; r < rl; ++r) {
+            uint64_t g = 0;
+            uint32_t cc = 0;
+            for (int i = 8; i < f.k + 6; ++i)
+                if (((r << 8) >> i) & 1) {
+                    g |= 1ull << d.sb[i];
+                    cc |= 1u << d.cb[i];
+                }
+            d.goff_hi[r] = g;
+            d.coff_hi[r] = cc;
+        }
+        std::vector<int> outer_pos = tbits;
+        for (int j = 0; j < f.nc; ++j) outer_pos.push_back(n - 1 - f.cw[j]);
+        std::sort(outer_pos.begin(), outer_pos.end());
+        d.outer = make_expand(outer_pos);
+        d.setmask = setmask;
+        d.n_tiles = (uint64_t)1 << (n - (int)outer_pos.size());
+        st.coff = (int64_t)P.coef.size();
+        for (int j = 0; j < dim * dim; ++j) P.coef.push_back(f.m[j]);
+        st.bytes = 2.0 * N * eb * frac;
     } else if (f.k == 3 && n >= 6 && [&] {
                    for (int i = 0; i < f.k; ++i)
                        if (n - 1 - f.tw[i] >= 6) return false;
@@ -911,12 +969,21 @@ PlanOptions plan_opts(int64_t tile_bits, int64_t low_bits, int64_t fusion, qsv_d
                       int64_t layers = 1) {
     PlanOptions o;
     const bool c128 = dt == QSV_C128;
+    const int eb = c128 ? 16 : 8;
     int b = (int)tile_bits;
     if (b <= 0) b = two ? (c128 ? 11 : 12) : (c128 ? 12 : 13);
-    o.b = std::min(b, 8 + TILE_MAX_R_LOG2);
+    b = std::min(b, 8 + TILE_MAX_R_LOG2);
+    // the tile itself must leave room in the CU's LDS for the pass's slot
+    // accumulators and phase tables
+    while (b > 1 && tile_lds_bytes(b, two, eb, 0, 0) > LDS_PER_CU - 8192) --b;
+    o.b = b;
     o.low = low_bits > 0 ? (int)low_bits : (c128 ? 4 : 5);
     o.fusion = fusion != 0;
     o.layers = layers != 0;
+    const int nthr = 1 << std::min(b, 8);
+    o.slot_bytes = 8 * (nthr >= 64 ? nthr / 16 : 1);
+    o.ztab_bytes = 2 * eb;
+    o.lds_budget = LDS_PER_CU - tile_lds_bytes(b, two, eb, 0, 0) - 16;
     return o;
 }
 
@@ -957,10 +1024,12 @@ void run_program(qsv_ctx* c, const Program& P, qsv_dtype dt, int n, void* phi, v
         if (st.type == Step::TILE) {
             const void* src = (phi_src && &st == &P.steps[0]) ? phi_src : phi;
             Timed t(c, lam ? KK_TILE2 : KK_TILE1, st.bytes);
-            hipError_t e = c128 ? launch_tile<double>(c->stream, lam != nullptr, st.generic, src, phi, lam, st.ta,
+            TileArgs ta = st.ta;
+            if (c->opt_nontemporal) ta.flags |= TILE_NT;
+            hipError_t e = c128 ? launch_tile<double>(c->stream, lam != nullptr, st.generic, src, phi, lam, ta,
                                                       (const TOp*)c->ops.p, c->coef.p, (const uint64_t*)c->words.p,
                                                       (double*)c->partials.p, st.grid, st.nthr, st.R, st.lds)
-                                : launch_tile<float>(c->stream, lam != nullptr, st.generic, src, phi, lam, st.ta,
+                                : launch_tile<float>(c->stream, lam != nullptr, st.generic, src, phi, lam, ta,
                                                      (const TOp*)c->ops.p, c->coef.p, (const uint64_t*)c->words.p,
                                                      (double*)c->partials.p, st.grid, st.nthr, st.R, st.lds);
             t.done(e);
@@ -973,33 +1042,41 @@ void run_program(qsv_ctx* c, const Program& P, qsv_dtype dt, int n, void* phi, v
         }
         const int kind = st.type == Step::GATE1 ? KK_GATE1
                          : st.type == Step::DIAG1 ? KK_DIAG1
-                         : st.type == Step::GATE2 ? KK_GATE2 : KK_GATEK;  // GATEK and GATEK_LOW
+                         : st.type == Step::GATE2 ? KK_GATE2
+                         : st.type == Step::DENSE ? KK_DENSE : KK_GATEK;  // GATEK and GATEK_LOW
         Timed t(c, kind, st.bytes);
         hipError_t e = hipSuccess;
+        const bool nt = c->opt_nontemporal != 0;
         switch (st.type) {
         case Step::GATE1:
-            e = c128 ? launch_gate1<double>(c->stream, phi, st.n_items, st.ex, st.setmask, st.tbit, st.cls, st.m2)
-                     : launch_gate1<float>(c->stream, phi, st.n_items, st.ex, st.setmask, st.tbit, st.cls, st.m2);
+            e = c128 ? launch_gate1<double>(c->stream, phi, st.n_items, st.ex, st.setmask, st.tbit, st.cls, st.m2, nt)
+                     : launch_gate1<float>(c->stream, phi, st.n_items, st.ex, st.setmask, st.tbit, st.cls, st.m2, nt);
             break;
         case Step::DIAG1:
-            e = c128 ? launch_diag1<double>(c->stream, phi, st.n_items, st.ex, st.setmask, st.dre, st.dim)
-                     : launch_diag1<float>(c->stream, phi, st.n_items, st.ex, st.setmask, st.dre, st.dim);
+            e = c128 ? launch_diag1<double>(c->stream, phi, st.n_items, st.ex, st.setmask, st.dre, st.dim, nt)
+                     : launch_diag1<float>(c->stream, phi, st.n_items, st.ex, st.setmask, st.dre, st.dim, nt);
             break;
         case Step::GATE2:
-            e = c128 ? launch_gate2<double>(c->stream, phi, st.n_items, st.ex, st.setmask, st.b0, st.b1, st.cls, st.m4)
-                     : launch_gate2<float>(c->stream, phi, st.n_items, st.ex, st.setmask, st.b0, st.b1, st.cls, st.m4);
+            e = c128 ? launch_gate2<double>(c->stream, phi, st.n_items, st.ex, st.setmask, st.b0, st.b1, st.cls, st.m4,
+                                            nt)
+                     : launch_gate2<float>(c->stream, phi, st.n_items, st.ex, st.setmask, st.b0, st.b1, st.cls, st.m4,
+                                           nt);
             break;
         case Step::GATEK_LOW:
             e = c128 ? launch_gatek_low<double>(c->stream, phi, st.n_items, st.ex, st.setmask, st.k, st.tb, st.lcm,
-                                                st.lcv, (const char*)c->coef.p + st.coff * cb)
+                                                st.lcv, (const char*)c->coef.p + st.coff * cb, nt)
                      : launch_gatek_low<float>(c->stream, phi, st.n_items, st.ex, st.setmask, st.k, st.tb, st.lcm,
-                                               st.lcv, (const char*)c->coef.p + st.coff * cb);
+                                               st.lcv, (const char*)c->coef.p + st.coff * cb, nt);
             break;
         case Step::GATEK:
             e = c128 ? launch_gatek<double>(c->stream, phi, st.n_items, st.ex, st.setmask, st.k, st.tb,
-                                            (const char*)c->coef.p + st.coff * cb)
+                                            (const char*)c->coef.p + st.coff * cb, nt)
                      : launch_gatek<float>(c->stream, phi, st.n_items, st.ex, st.setmask, st.k, st.tb,
-                                           (const char*)c->coef.p + st.coff * cb);
+                                           (const char*)c->coef.p + st.coff * cb, nt);
+            break;
+        case Step::DENSE:
+            e = c128 ? launch_dense<double>(c->stream, phi, st.da, (const char*)c->coef.p + st.coff * cb, nt)
+                     : launch_dense<float>(c->stream, phi, st.da, (const char*)c->coef.p + st.coff * cb, nt);
             break;
         default:
             break;
@@ -1588,14 +1665,28 @@ qsv_status qsv_plan_json(int n, qsv_dtype dt, const qsv_op* ops, size_t n_ops, c
         for (size_t i = 0; i < P.steps.size(); ++i) {
             const Step& st = P.steps[i];
             if (i) js += ",";
-            static const char* names[] = {"tile", "gate1", "diag1", "gate2", "gatek", "gatek_low"};
+            static const char* names[] = {"tile", "gate1", "diag1", "gate2", "gatek", "gatek_low", "dense"};
             add("{\"type\":\"%s\",\"bytes\":%.17g", names[st.type], st.bytes);
-            if (st.type == Step::TILE) {
+            if (st.type == Step::DENSE) {
+                const DenseArgs& d = st.da;
+                add(",\"k\":%d,\"coff\":%lld,\"n_tiles\":%llu,\"setmask\":%llu,\"sb\":[", d.k, (long long)st.coff,
+                    (unsigned long long)d.n_tiles, (unsigned long long)d.setmask);
+                for (int j = 0; j < d.k + 6; ++j) add(j ? ",%d" : "%d", d.sb[j]);
+                js += "],\"cb\":[";
+                for (int j = 0; j < d.k + 6; ++j) add(j ? ",%d" : "%d", d.cb[j]);
+                js += "],\"goff_hi\":[";
+                for (int r = 0; r < (64 << d.k) / 256; ++r) add(r ? ",%llu" : "%llu", (unsigned long long)d.goff_hi[r]);
+                js += "],\"coff_hi\":[";
+                for (int r = 0; r < (64 << d.k) / 256; ++r) add(r ? ",%u" : "%u", d.coff_hi[r]);
+                js += "],\"outer\":[";
+                for (int j = 0; j < d.outer.nm; ++j) add(j ? ",%llu" : "%llu", (unsigned long long)d.outer.m[j]);
+                js += "]";
+            } else if (st.type == Step::TILE) {
                 const TileArgs& a = st.ta;
                 add(",\"b\":%d,\"nthr\":%d,\"R\":%d,\"grid\":%d,\"op0\":%d,\"nops\":%d,\"nslots\":%d,\"slot_base\":%d,"
-                    "\"generic\":%d,\"n_tiles\":%llu,\"n_outer\":%d,\"sb\":[",
+                    "\"generic\":%d,\"n_tiles\":%llu,\"n_outer\":%d,\"lds\":%zu,\"sb\":[",
                     a.b, st.nthr, st.R, st.grid, a.op0, a.nops, a.nslots, st.slot_base, (int)st.generic,
-                    (unsigned long long)a.n_tiles, a.n_outer);
+                    (unsigned long long)a.n_tiles, a.n_outer, st.lds);
                 for (int j = 0; j < a.b; ++j) add(j ? ",%d" : "%d", a.sb[j]);
                 js += "],\"offhi\":[";
                 for (int r = 0; r < st.R; ++r) add(r ? ",%llu" : "%llu", (unsigned long long)a.offhi[r]);

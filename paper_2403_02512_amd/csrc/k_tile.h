@@ -749,6 +749,29 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
     }
 }
 
+// Global loads of one tile's amplitudes (this thread's elements) into
+// registers; with synth the basis state is generated instead.
+template <typename T, bool TWO, int RP>
+__device__ __forceinline__ void tile_fetch(cx<T> (&vp)[RP], cx<T> (&vl)[RP], const cx<T>* phi_src,
+                                           const cx<T>* lam, const TileArgs& a, uint64_t offlo, uint64_t tile,
+                                           bool synth) {
+    const uint64_t base = expand_idx(tile, a.outer) | offlo;
+    if (synth) {
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+            vp[r].re = (base | a.offhi[r]) == a.basis ? T(1) : T(0);
+            vp[r].im = T(0);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < RP; ++r) vp[r] = phi_src[base | a.offhi[r]];
+    }
+    if (TWO) {
+#pragma unroll
+        for (int r = 0; r < RP; ++r) vl[r] = lam[base | a.offhi[r]];
+    }
+}
+
 // GEN: the pass also holds standalone ops (k-qubit matrices, or a tile too
 // small for groups); group-only passes compile without those code paths,
 // which keeps their register footprint (and so their occupancy) lower.
@@ -756,7 +779,15 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
 // described by a.  phi_src is where phi is read from (phi itself, or the
 // post-circuit state for an out-of-place first adjoint pass); with
 // TILE_SYNTH the tile is synthesised as the basis state a.basis instead.
-template <typename T, bool TWO, int LR, bool GEN>
+//
+// PF (prefetch): for tiles so large that one block fills the CU's LDS.  The
+// block holds the next tile's amplitudes in registers: their global loads are
+// issued right after the current tile is in LDS and stay in flight while the
+// tile's groups run (a workgroup barrier waits for LDS traffic only, not for
+// outstanding global loads), so HBM reads overlap the compute instead of
+// alternating with it.  One wave per SIMD leaves the whole register file
+// (VGPRs and AGPRs) to the wave, room for the 2R in-flight amplitudes.
+template <typename T, bool TWO, int LR, bool GEN, bool PF = false>
 __device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
                                           cx<T>* __restrict__ lam, const TileArgs& a, const TOp* __restrict__ ops,
                                           const cx<T>* __restrict__ coef, const uint64_t* __restrict__ words,
@@ -796,6 +827,9 @@ __device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
     c.offlo = offlo;
     for (int s = tid; s < a.nslots * c.nacc; s += nthr) c.sacc[s] = 0.0;
     const bool synth = (a.flags & TILE_SYNTH) != 0;
+    constexpr int RP = PF ? R : 1;
+    cx<T> pf_p[RP], pf_l[RP];
+    if (PF && blk < a.n_tiles) tile_fetch<T, TWO, RP>(pf_p, pf_l, phi_src, lam, a, offlo, blk, synth);
 
     for (uint64_t tile = blk; tile < a.n_tiles; tile += nblk) {
         const uint64_t base = expand_idx(tile, a.outer);
@@ -804,6 +838,13 @@ __device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
         // global -> LDS in chunks of LCH elements per thread: LCH loads in
         // flight per thread without keeping all R values live in registers
         constexpr int LCH = R < 8 ? R : 8;
+        if constexpr (PF) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                c.tp[stid + r * nthr] = pf_p[r];
+                if (TWO) c.tl[stid + r * nthr] = pf_l[r];
+            }
+        } else
         for (int r0 = 0; r0 < R; r0 += LCH) {
             cx<T> vp[LCH], vl[LCH];
 #pragma unroll
@@ -824,6 +865,8 @@ __device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
             }
         }
         __syncthreads();
+        if (PF && tile + nblk < a.n_tiles)  // in flight during the groups
+            tile_fetch<T, TWO, RP>(pf_p, pf_l, phi_src, lam, a, offlo, tile + nblk, synth);
         for (int oi = 0; oi < a.nops; ++oi) {
             const TOp& op = ops[a.op0 + oi];
             if ((op.kind <= OP_APPLYK || (op.kind >= OP_DOT1 && op.kind <= OP_DOTK)) &&
@@ -847,12 +890,13 @@ __device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
             }
             __syncthreads();
         }
+        const bool nt = (a.flags & TILE_NT) != 0;
         for (int r0 = 0; r0 < R; r0 += LCH) {
 #pragma unroll
             for (int r = 0; r < LCH; ++r) {
                 const uint64_t g = base | offlo | a.offhi[r0 + r];
-                phi[g] = c.tp[stid + (r0 + r) * nthr];
-                if (TWO) lam[g] = c.tl[stid + (r0 + r) * nthr];
+                st_amp(phi + g, c.tp[stid + (r0 + r) * nthr], nt);
+                if (TWO) st_amp(lam + g, c.tl[stid + (r0 + r) * nthr], nt);
             }
         }
         __syncthreads();
@@ -873,6 +917,16 @@ __global__ __launch_bounds__(256, 2) void k_tile(const cx<T>* phi_src, cx<T>* ph
     tile_body<T, TWO, LR, GEN>(phi_src, phi, lam, a, ops, coef, words, partials, blockIdx.x, gridDim.x);
 }
 
+// One block per CU (the tile fills the LDS), next tile prefetched into registers.
+template <typename T, bool TWO, int LR, bool GEN>
+__global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_tile_pf(const cx<T>* phi_src, cx<T>* phi, cx<T>* __restrict__ lam,
+                                                    const TileArgs a, const TOp* __restrict__ ops,
+                                                    const cx<T>* __restrict__ coef,
+                                                    const uint64_t* __restrict__ words,
+                                                    double* __restrict__ partials) {
+    tile_body<T, TWO, LR, GEN, true>(phi_src, phi, lam, a, ops, coef, words, partials, blockIdx.x, gridDim.x);
+}
+
 // Batched passes: block b serves entry blk_entry[b] (one circuit's pass).
 template <typename T, bool TWO, int LR, bool GEN>
 __global__ __launch_bounds__(256, 2) void k_tile_batch(const TileEntry* __restrict__ entries,
@@ -891,6 +945,18 @@ template <typename T, bool TWO, int LR, bool GEN>
 static hipError_t launch_tile_lr(hipStream_t s, const void* phi_src, void* phi, void* lam, const TileArgs& a,
                                  const TOp* ops, const void* coef, const uint64_t* words, double* partials, int grid,
                                  int nthr, size_t lds) {
+    if constexpr (LR >= 3) {
+        if (tile_prefetch(lds, 1 << LR)) {
+            // one block fits per CU: the prefetching form (the host sized the
+            // grid to one persistent block per CU)
+            static std::atomic<uint64_t> pf_raised{0};
+            hipError_t e = allow_big_lds((const void*)k_tile_pf<T, TWO, LR, GEN>, pf_raised);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_tile_pf<T, TWO, LR, GEN>), dim3(grid), dim3(nthr), lds, s, (const cx<T>*)phi_src,
+                               (cx<T>*)phi, (cx<T>*)lam, a, ops, (const cx<T>*)coef, words, partials);
+            return hipGetLastError();
+        }
+    }
     static std::atomic<uint64_t> lds_raised{0};
     if (lds > 65536) {
         hipError_t e = allow_big_lds((const void*)k_tile<T, TWO, LR, GEN>, lds_raised);

@@ -43,6 +43,23 @@ __device__ __forceinline__ double im_conj_mul(cx<T> l, cx<T> v) {
     return (double)l.re * (double)v.im - (double)l.im * (double)v.re;
 }
 
+// Store of one amplitude.  nt: a non-temporal (streaming) store, which asks
+// the caches not to keep the line: the state is written once per pass and
+// not read again before it is evicted (the paper's streaming stores, Sec.
+// 3.1).  nt is uniform across the launch, so the branch is a scalar one.
+template <typename T>
+__device__ __forceinline__ void st_amp(cx<T>* p, cx<T> v, bool nt) {
+    if (nt) {
+        typedef T V2 __attribute__((ext_vector_type(2)));
+        V2 x;
+        x.x = v.re;
+        x.y = v.im;
+        __builtin_nontemporal_store(x, reinterpret_cast<V2*>(p));
+    } else {
+        *p = v;
+    }
+}
+
 __device__ __forceinline__ uint64_t expand_idx(uint64_t k, const Expand& e) {
     uint64_t r = k & e.m[0];
     for (int i = 1; i < e.nm; ++i) r |= (k << i) & e.m[i];

@@ -27,7 +27,7 @@ namespace qsv {
 
 const char* const kKernelNames[KK_COUNT] = {"init",  "gate1", "diag1",        "gate2",        "gatek", "tile1",
                                             "tile2", "pauli_expval", "pauli_lambda", "reduce", "copy",  "probs", "sparse_expval",
-                                            "sample"};
+                                            "sample", "dense"};
 
 // ------------------------------------------------------------------ init
 
@@ -57,7 +57,7 @@ constexpr int G1_ITEMS = 2;
 
 template <typename T, int CLS>
 __global__ __launch_bounds__(256) void k_gate1(cx<T>* __restrict__ psi, uint64_t n_items, Expand ex,
-                                               uint64_t setmask, uint64_t tbit, Mat2 mat) {
+                                               uint64_t setmask, uint64_t tbit, Mat2 mat, int nt) {
     const M2T<T> m = to_t<T>(mat);
     const uint64_t k0 = (uint64_t)blockIdx.x * (256 * G1_ITEMS) + threadIdx.x;
     uint64_t i0[G1_ITEMS];
@@ -85,28 +85,28 @@ __global__ __launch_bounds__(256) void k_gate1(cx<T>* __restrict__ psi, uint64_t
             b0 = cmul(m.b, a1[r]);
             b1 = cmul(m.c, a0[r]);
         }
-        psi[i0[r]] = b0;
-        psi[i0[r] | tbit] = b1;
+        st_amp(psi + i0[r], b0, nt);
+        st_amp(psi + (i0[r] | tbit), b1, nt);
     }
 }
 
 template <typename T>
 hipError_t launch_gate1(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex, uint64_t setmask,
-                        uint64_t tbit, int cls, const Mat2& m) {
+                        uint64_t tbit, int cls, const Mat2& m, bool nt) {
     const uint64_t blocks = (n_items + 256 * G1_ITEMS - 1) / (256 * G1_ITEMS);
     dim3 g((unsigned)blocks), b(256);
     if (cls == MC_DIAG)
-        hipLaunchKernelGGL((k_gate1<T, MC_DIAG>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, tbit, m);
+        hipLaunchKernelGGL((k_gate1<T, MC_DIAG>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, tbit, m, (int)nt);
     else if (cls == MC_ANTI)
-        hipLaunchKernelGGL((k_gate1<T, MC_ANTI>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, tbit, m);
+        hipLaunchKernelGGL((k_gate1<T, MC_ANTI>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, tbit, m, (int)nt);
     else
-        hipLaunchKernelGGL((k_gate1<T, MC_DENSE>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, tbit, m);
+        hipLaunchKernelGGL((k_gate1<T, MC_DENSE>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, tbit, m, (int)nt);
     return hipGetLastError();
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_diag1(cx<T>* __restrict__ psi, uint64_t n_items, Expand ex,
-                                               uint64_t setmask, double dre, double dim) {
+                                               uint64_t setmask, double dre, double dim, int nt) {
     const cx<T> d = {(T)dre, (T)dim};
     const uint64_t k0 = (uint64_t)blockIdx.x * (256 * 4) + threadIdx.x;
     uint64_t idx[4];
@@ -119,15 +119,15 @@ __global__ __launch_bounds__(256) void k_diag1(cx<T>* __restrict__ psi, uint64_t
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-        if (idx[r] != ~0ull) psi[idx[r]] = cmul(d, a[r]);
+        if (idx[r] != ~0ull) st_amp(psi + idx[r], cmul(d, a[r]), nt);
 }
 
 template <typename T>
 hipError_t launch_diag1(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex, uint64_t setmask,
-                        double dre, double dim) {
+                        double dre, double dim, bool nt) {
     const uint64_t blocks = (n_items + 1023) / 1024;
     hipLaunchKernelGGL(k_diag1<T>, dim3((unsigned)blocks), dim3(256), 0, s, (cx<T>*)psi, n_items, ex, setmask,
-                       dre, dim);
+                       dre, dim, (int)nt);
     return hipGetLastError();
 }
 
@@ -135,7 +135,7 @@ hipError_t launch_diag1(hipStream_t s, void* psi, uint64_t n_items, const Expand
 
 template <typename T, int CLS>
 __global__ __launch_bounds__(256) void k_gate2(cx<T>* __restrict__ psi, uint64_t n_items, Expand ex,
-                                               uint64_t setmask, uint64_t b0, uint64_t b1, Mat4 mat) {
+                                               uint64_t setmask, uint64_t b0, uint64_t b1, Mat4 mat, int nt) {
     const uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= n_items) return;
     const uint64_t i = expand_idx(k, ex) | setmask;
@@ -144,8 +144,8 @@ __global__ __launch_bounds__(256) void k_gate2(cx<T>* __restrict__ psi, uint64_t
         const cx<T> x1 = psi[idx[1]], x2 = psi[idx[2]];
         const cx<T> m11 = {(T)mat.re[5], (T)mat.im[5]}, m12 = {(T)mat.re[6], (T)mat.im[6]};
         const cx<T> m21 = {(T)mat.re[9], (T)mat.im[9]}, m22 = {(T)mat.re[10], (T)mat.im[10]};
-        psi[idx[1]] = cmad(m11, x1, cmul(m12, x2));
-        psi[idx[2]] = cmad(m21, x1, cmul(m22, x2));
+        st_amp(psi + idx[1], cmad(m11, x1, cmul(m12, x2)), nt);
+        st_amp(psi + idx[2], cmad(m21, x1, cmul(m22, x2)), nt);
         return;
     }
     cx<T> a[4];
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(256) void k_gate2(cx<T>* __restrict__ psi, uint64_t
     for (int j = 0; j < 4; ++j) a[j] = psi[idx[j]];
     if (CLS == MC_DIAG) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) psi[idx[j]] = cmul(cx<T>{(T)mat.re[j * 5], (T)mat.im[j * 5]}, a[j]);
+        for (int j = 0; j < 4; ++j) st_amp(psi + idx[j], cmul(cx<T>{(T)mat.re[j * 5], (T)mat.im[j * 5]}, a[j]), nt);
         return;
     }
 #pragma unroll
@@ -161,21 +161,22 @@ __global__ __launch_bounds__(256) void k_gate2(cx<T>* __restrict__ psi, uint64_t
         cx<T> acc = {T(0), T(0)};
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc = cmad(cx<T>{(T)mat.re[r * 4 + j], (T)mat.im[r * 4 + j]}, a[j], acc);
-        psi[idx[r]] = acc;
+        st_amp(psi + idx[r], acc, nt);
     }
 }
 
 template <typename T>
 hipError_t launch_gate2(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex, uint64_t setmask, uint64_t b0,
-                        uint64_t b1, int cls, const Mat4& m) {
+                        uint64_t b1, int cls, const Mat4& m, bool nt) {
     const uint64_t blocks = (n_items + 255) / 256;
     dim3 g((unsigned)blocks), b(256);
     if (cls == MC_MID)
-        hipLaunchKernelGGL((k_gate2<T, MC_MID>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, b0, b1, m);
+        hipLaunchKernelGGL((k_gate2<T, MC_MID>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, b0, b1, m, (int)nt);
     else if (cls == MC_DIAG)
-        hipLaunchKernelGGL((k_gate2<T, MC_DIAG>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, b0, b1, m);
+        hipLaunchKernelGGL((k_gate2<T, MC_DIAG>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, b0, b1, m, (int)nt);
     else
-        hipLaunchKernelGGL((k_gate2<T, MC_DENSE>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, b0, b1, m);
+        hipLaunchKernelGGL((k_gate2<T, MC_DENSE>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, b0, b1, m,
+                           (int)nt);
     return hipGetLastError();
 }
 
@@ -187,7 +188,7 @@ struct TBits {
 
 template <typename T, int K>
 __global__ __launch_bounds__(256) void k_gatek(cx<T>* __restrict__ psi, uint64_t n_items, Expand ex,
-                                               uint64_t setmask, TBits tb, const cx<T>* __restrict__ mat) {
+                                               uint64_t setmask, TBits tb, const cx<T>* __restrict__ mat, int nt) {
     constexpr int D = 1 << K;
     const uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= n_items) return;
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(256) void k_gatek(cx<T>* __restrict__ psi, uint64_t
         cx<T> acc = {T(0), T(0)};
 #pragma unroll
         for (int j = 0; j < D; ++j) acc = cmad(mat[r * D + j], a[j], acc);
-        psi[base | off[r]] = acc;
+        st_amp(psi + (base | off[r]), acc, nt);
     }
 }
 
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(256) void k_gatek(cx<T>* __restrict__ psi, uint64_t
 template <typename T>
 __global__ __launch_bounds__(256) void k_gatek_low(cx<T>* __restrict__ psi, uint64_t n_chunks, Expand ex,
                                                    uint64_t setmask, TBits tb, int k, uint32_t lcm, uint32_t lcv,
-                                                   const cx<T>* __restrict__ mat) {
+                                                   const cx<T>* __restrict__ mat, int nt) {
     extern __shared__ __align__(16) unsigned char gk_smem[];
     const int dim = 1 << k, stride = dim + 1;
     cx<T>* m = reinterpret_cast<cx<T>*>(gk_smem);
@@ -257,7 +258,7 @@ __global__ __launch_bounds__(256) void k_gatek_low(cx<T>* __restrict__ psi, uint
                     if ((j >> (k - 1 - i)) & 1) o |= 1u << tb.tb[i];
                 acc = cmad(mr[j], wb[o], acc);
             }
-            if (on) psi[base + lane] = acc;
+            if (on) st_amp(psi + base + lane, acc, nt);
         }
         __syncthreads();
     }
@@ -265,7 +266,7 @@ __global__ __launch_bounds__(256) void k_gatek_low(cx<T>* __restrict__ psi, uint
 
 template <typename T>
 hipError_t launch_gatek_low(hipStream_t s, void* psi, uint64_t n_chunks, const Expand& ex, uint64_t setmask, int k,
-                            const int32_t* tbits, uint32_t lcm, uint32_t lcv, const void* mat) {
+                            const int32_t* tbits, uint32_t lcm, uint32_t lcv, const void* mat, bool nt) {
     if (k < 1 || k > 6) return hipErrorInvalidValue;
     TBits tb;
     for (int i = 0; i < 6; ++i) tb.tb[i] = i < k ? tbits[i] : 0;
@@ -279,24 +280,133 @@ hipError_t launch_gatek_low(hipStream_t s, void* psi, uint64_t n_chunks, const E
     uint64_t blocks = (n_chunks + 3) / 4;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_gatek_low<T>, dim3((unsigned)(blocks ? blocks : 1)), dim3(256), lds, s, (cx<T>*)psi,
-                       n_chunks, ex, setmask, tb, k, lcm, lcv, (const cx<T>*)mat);
+                       n_chunks, ex, setmask, tb, k, lcm, lcv, (const cx<T>*)mat, (int)nt);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_gatek(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex, uint64_t setmask, int k,
-                        const int32_t* tbits, const void* mat) {
+                        const int32_t* tbits, const void* mat, bool nt) {
     TBits tb;
     for (int i = 0; i < 6; ++i) tb.tb[i] = i < k ? tbits[i] : 0;
     const uint64_t blocks = (n_items + 255) / 256;
     dim3 g((unsigned)blocks), b(256);
     const cx<T>* m = (const cx<T>*)mat;
     switch (k) {
-    case 3: hipLaunchKernelGGL((k_gatek<T, 3>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, tb, m); break;
-    case 4: hipLaunchKernelGGL((k_gatek<T, 4>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, tb, m); break;
-    case 5: hipLaunchKernelGGL((k_gatek<T, 5>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, tb, m); break;
+    case 3: hipLaunchKernelGGL((k_gatek<T, 3>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, tb, m, (int)nt); break;
+    case 4: hipLaunchKernelGGL((k_gatek<T, 4>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, tb, m, (int)nt); break;
+    case 5: hipLaunchKernelGGL((k_gatek<T, 5>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, tb, m, (int)nt); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ dense k-qubit matrices, LDS-staged
+
+// A dense 2^K x 2^K matrix (K = 3..6) on any K target bits.  A tile is the
+// 2^(K+6) amplitudes that agree outside the targets and the six lowest index
+// bits that are neither targets nor controls (the lane bits): 64 tuples of
+// 2^K amplitudes.  Controls always lie outside the tile and are enumerated by
+// ex / setmask, so no lane tests a control.
+//
+//  load:    the tile in ascending tile-bit order (global order, so loads are
+//           coalesced runs) into LDS at c = (j << 6) | l for element j of
+//           tuple l, with one pad slot per 64 (address c + (c >> 6)), which
+//           keeps both the load's and the compute's LDS accesses conflict-free
+//           whichever bits are targets;
+//  compute: wave w takes rows [w R, (w+1) R), R = 2^(K-2), of every tuple,
+//           lane = tuple: each input read from LDS feeds R complex MACs, and
+//           the matrix entries are wave-uniform (scalar loads);
+//  store:   outputs back to LDS, then coalesced stores.
+// FLOPs per amplitude 8 * 2^K: memory-bound up to K = 5 in complex128 and
+// FP64-ALU-bound at K = 6.
+template <typename T, int K>
+__global__ __launch_bounds__(256, 2) void k_dense(cx<T>* __restrict__ psi, const DenseArgs a,
+                                                  const cx<T>* __restrict__ mat, int nt) {
+    constexpr int D = 1 << K;          // tuple size
+    constexpr int RW = D / 4;          // rows per wave
+    constexpr int NE = D * 64;         // tile elements
+    constexpr int RL = NE / 256;       // elements per thread in load / store
+    extern __shared__ __align__(16) unsigned char dn_smem[];
+    cx<T>* lds = reinterpret_cast<cx<T>*>(dn_smem);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    // the thread's load/store slots: tile-local index tid + r * 256; both maps
+    // (to the global offset and to the compact LDS index) are bit deposits,
+    // linear over GF(2), so the tid part and the r part combine by OR
+    uint64_t goff = 0;
+    uint32_t coff = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        if ((tid >> i) & 1) {
+            goff |= 1ull << a.sb[i];
+            coff |= 1u << a.cb[i];
+        }
+    const cx<T>* mrow = mat + (size_t)wave * RW * D;
+    for (uint64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+        const uint64_t base = expand_idx(tile, a.outer) | a.setmask;
+        cx<T> v[RL];
+#pragma unroll
+        for (int r = 0; r < RL; ++r) v[r] = psi[base | goff | a.goff_hi[r]];
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+            const uint32_t c = coff | a.coff_hi[r];
+            lds[c + (c >> 6)] = v[r];
+        }
+        __syncthreads();
+        cx<T> acc[RW];
+#pragma unroll
+        for (int q = 0; q < RW; ++q) acc[q] = {T(0), T(0)};
+#pragma unroll 4
+        for (int j = 0; j < D; ++j) {
+            const cx<T> x = lds[(j << 6) + lane + j];
+#pragma unroll
+            for (int q = 0; q < RW; ++q) acc[q] = cmad(mrow[q * D + j], x, acc[q]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+            const int row = wave * RW + q;
+            lds[(row << 6) + lane + row] = acc[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+            const uint32_t c = coff | a.coff_hi[r];
+            st_amp(psi + (base | goff | a.goff_hi[r]), lds[c + (c >> 6)], nt);
+        }
+        __syncthreads();
+    }
+}
+
+size_t dense_lds_bytes(int k, int elem_bytes) { return (size_t)(64 << k) * 65 / 64 * elem_bytes; }
+
+template <typename T>
+hipError_t launch_dense(hipStream_t s, void* psi, const DenseArgs& a, const void* mat, bool nt) {
+    const size_t lds = dense_lds_bytes(a.k, (int)sizeof(cx<T>));
+    uint64_t blocks = a.n_tiles < 4096 ? a.n_tiles : 4096;
+    if (blocks == 0) return hipSuccess;
+    const cx<T>* m = (const cx<T>*)mat;
+    static std::atomic<uint64_t> lds_raised{0};
+#define QSV_DN(KV)                                                                                        \
+    {                                                                                                     \
+        if (lds > 65536) {                                                                                \
+            hipError_t e = allow_big_lds((const void*)k_dense<T, KV>, lds_raised);                       \
+            if (e != hipSuccess) return e;                                                                \
+        }                                                                                                 \
+        hipLaunchKernelGGL((k_dense<T, KV>), dim3((unsigned)blocks), dim3(256), lds, s, (cx<T>*)psi, a, m, \
+                           (int)nt);                                                                      \
+    }                                                                                                     \
+    break;
+    switch (a.k) {
+    case 3: QSV_DN(3)
+    case 4: QSV_DN(4)
+    case 5: QSV_DN(5)
+    case 6: QSV_DN(6)
+    default: return hipErrorInvalidValue;
+    }
+#undef QSV_DN
     return hipGetLastError();
 }
 
@@ -715,14 +825,16 @@ hipError_t launch_reduce(hipStream_t s, const double* partials, int n_blocks, in
 #define QSV_INST(T)                                                                                              \
     template hipError_t launch_init<T>(hipStream_t, void*, uint64_t, uint64_t);                                 \
     template hipError_t launch_gate1<T>(hipStream_t, void*, uint64_t, const Expand&, uint64_t, uint64_t, int,   \
-                                        const Mat2&);                                                           \
-    template hipError_t launch_diag1<T>(hipStream_t, void*, uint64_t, const Expand&, uint64_t, double, double); \
+                                        const Mat2&, bool);                                                     \
+    template hipError_t launch_diag1<T>(hipStream_t, void*, uint64_t, const Expand&, uint64_t, double, double,  \
+                                        bool);                                                                  \
     template hipError_t launch_gate2<T>(hipStream_t, void*, uint64_t, const Expand&, uint64_t, uint64_t,        \
-                                        uint64_t, int, const Mat4&);                                            \
+                                        uint64_t, int, const Mat4&, bool);                                      \
     template hipError_t launch_gatek<T>(hipStream_t, void*, uint64_t, const Expand&, uint64_t, int,             \
-                                        const int32_t*, const void*);                                           \
+                                        const int32_t*, const void*, bool);                                     \
     template hipError_t launch_gatek_low<T>(hipStream_t, void*, uint64_t, const Expand&, uint64_t, int,         \
-                                            const int32_t*, uint32_t, uint32_t, const void*);                   \
+                                            const int32_t*, uint32_t, uint32_t, const void*, bool);             \
+    template hipError_t launch_dense<T>(hipStream_t, void*, const DenseArgs&, const void*, bool);              \
     template hipError_t launch_tile<T>(hipStream_t, bool, bool, const void*, void*, void*, const TileArgs&, const TOp*,      \
                                        const void*, const uint64_t*, double*, int, int, int, size_t);           \
     template hipError_t launch_pauli<T>(hipStream_t, bool, bool, const void*, void*, uint64_t,                  \

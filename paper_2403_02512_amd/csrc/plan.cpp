@@ -34,6 +34,7 @@ Item make_item(const Factor& f, bool dot, int fidx, int n) {
     const bool diag = is_diag(dot ? f.g : f.m, 1 << f.k);
     it.xbits = diag ? 0 : tb;
     it.zbits = cb | (diag ? tb : 0);
+    it.zrot = f.zrot && !dot;
     return it;
 }
 
@@ -64,11 +65,13 @@ std::vector<Pass> plan_passes(const std::vector<Item>& items, int n, const PlanO
         } else {
             uint64_t bx = 0, bz = 0;
             int scanned = 0;
+            int64_t lds = 0;  // slot accumulators and phase tables of the pass
             for (size_t j = first; j < items.size() && scanned < opt.max_scan; ++j) {
                 if (done[j]) continue;
                 ++scanned;
                 const Item& it = items[j];
-                bool ok = !(it.xbits & (bx | bz)) && !(it.zbits & bx);
+                const int64_t cost = (it.dot ? opt.slot_bytes : 0) + (it.zrot ? opt.ztab_bytes : 0);
+                bool ok = !(it.xbits & (bx | bz)) && !(it.zbits & bx) && lds + cost <= opt.lds_budget;
                 if (ok && it.xbits) {
                     const uint64_t ns = p.S | it.xbits;
                     if (__builtin_popcountll(ns) <= b)
@@ -82,6 +85,7 @@ std::vector<Pass> plan_passes(const std::vector<Item>& items, int n, const PlanO
                     p.items.push_back((int)j);
                     done[j] = 1;
                     --left;
+                    lds += cost;
                 } else {
                     bx |= it.xbits;
                     bz |= it.zbits;

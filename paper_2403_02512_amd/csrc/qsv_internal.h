@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <complex>
 #include <cstdint>
 #include <string>
@@ -90,6 +91,21 @@ struct TileArgs {
     uint64_t basis;
 };
 constexpr int32_t TILE_SYNTH = 1;
+constexpr int32_t TILE_NT = 2;  // write back with non-temporal stores
+
+// A dense k-qubit matrix on a tile of 2^(k+6) amplitudes: the k targets and
+// six lane bits (the lowest index bits that are neither targets nor
+// controls).  Tile-local bit i (ascending global bit order) is global bit
+// sb[i] and bit cb[i] of the compact LDS index (j << 6) | lane.
+struct DenseArgs {
+    Expand outer;        // tile number -> base index (zeros at tile bits and controls)
+    uint64_t setmask;    // control values
+    uint64_t n_tiles;
+    uint64_t goff_hi[16];  // global offset of tile-local index r * 256
+    uint32_t coff_hi[16];  // compact index of tile-local index r * 256
+    int32_t sb[12], cb[12];
+    int32_t k, pad;
+};
 
 // One circuit's pass inside a batched launch (blocks blk0 .. blk0+nblk-1).
 struct TileEntry {
@@ -136,7 +152,7 @@ struct PauliTermDev {
 
 enum KernelKind : int {
     KK_INIT = 0, KK_GATE1, KK_DIAG1, KK_GATE2, KK_GATEK, KK_TILE1, KK_TILE2,
-    KK_PAULI, KK_PAULI_LAMBDA, KK_REDUCE, KK_COPY, KK_PROBS, KK_SPARSE, KK_SAMPLE, KK_COUNT
+    KK_PAULI, KK_PAULI_LAMBDA, KK_REDUCE, KK_COPY, KK_PROBS, KK_SPARSE, KK_SAMPLE, KK_DENSE, KK_COUNT
 };
 extern const char* const kKernelNames[KK_COUNT];
 
@@ -147,17 +163,22 @@ struct Mat2 { double re[4], im[4]; };
 struct Mat4 { double re[16], im[16]; };
 
 template <typename T> hipError_t launch_init(hipStream_t s, void* psi, uint64_t N, uint64_t basis);
+// nt: non-temporal (streaming) stores
 template <typename T> hipError_t launch_gate1(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex,
-                                              uint64_t setmask, uint64_t tbit, int cls, const Mat2& m);
+                                              uint64_t setmask, uint64_t tbit, int cls, const Mat2& m, bool nt);
 template <typename T> hipError_t launch_diag1(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex,
-                                              uint64_t setmask, double dre, double dim);
+                                              uint64_t setmask, double dre, double dim, bool nt);
 template <typename T> hipError_t launch_gate2(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex,
-                                              uint64_t setmask, uint64_t b0, uint64_t b1, int cls, const Mat4& m);
+                                              uint64_t setmask, uint64_t b0, uint64_t b1, int cls, const Mat4& m,
+                                              bool nt);
 template <typename T> hipError_t launch_gatek_low(hipStream_t s, void* psi, uint64_t n_chunks, const Expand& ex,
                                                   uint64_t setmask, int k, const int32_t* tbits, uint32_t lcm,
-                                                  uint32_t lcv, const void* mat);
+                                                  uint32_t lcv, const void* mat, bool nt);
 template <typename T> hipError_t launch_gatek(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex,
-                                              uint64_t setmask, int k, const int32_t* tbits, const void* mat);
+                                              uint64_t setmask, int k, const int32_t* tbits, const void* mat,
+                                              bool nt);
+template <typename T> hipError_t launch_dense(hipStream_t s, void* psi, const DenseArgs& a, const void* mat, bool nt);
+size_t dense_lds_bytes(int k, int elem_bytes);
 template <typename T> hipError_t launch_tile(hipStream_t s, bool two, bool generic, const void* phi_src, void* phi,
                                              void* lam, const TileArgs& a,
                                              const TOp* ops, const void* coef, const uint64_t* words,
@@ -235,6 +256,7 @@ int gate_n_angles(int gate);
 
 struct Item {
     bool dot;        // generator inner product (else apply factor matrix)
+    bool zrot = false;  // Z-parity rotation (a phase table in the tile pass's LDS)
     int f;           // factor index
     uint64_t xbits;  // index bits the item mixes (targets of a non-diagonal matrix)
     uint64_t zbits;  // index bits it acts on diagonally (controls, diagonal targets)
@@ -251,7 +273,18 @@ struct PlanOptions {
     bool fusion = true;
     bool layers = true;  // one-qubit runs inside register groups as LAYER1 sub-ops
     int max_scan = 2048; // look-ahead window of the greedy planner
+    // LDS a tile pass may spend beyond its tile: each inner product holds a
+    // slot accumulator (slot_bytes), each Z-parity rotation at most two
+    // phase-table entries (ztab_bytes); a pass closes before exceeding it
+    int64_t slot_bytes = 0, ztab_bytes = 0, lds_budget = INT64_MAX;
 };
+
+constexpr int LDS_PER_CU = 160 * 1024;
+// A tile pass whose LDS admits one block per CU runs the prefetching kernel
+// form (next tile held in registers) as one persistent block per CU of the
+// MI355X (256 CUs).
+constexpr int TILE_PF_GRID = 256;
+inline bool tile_prefetch(size_t lds, int R) { return lds > (size_t)LDS_PER_CU / 2 && R >= 8; }
 
 std::vector<Pass> plan_passes(const std::vector<Item>& items, int n, const PlanOptions& opt);
 Item make_item(const Factor& f, bool dot, int fidx, int n);

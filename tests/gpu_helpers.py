@@ -1,13 +1,25 @@
 """Shared helpers of the GPU parity tests (HIP path vs the CPU oracle)."""
+import os
+
 import numpy as np
 
 import oracle
 from paper_2403_02512_amd import qsv
+from tests.parity_log import record
 
 # Tolerances: state vectors by ||psi - psi_ref||_2 (||psi|| = 1); scalars
 # relative to s = sum_t |c_t| of the observable (s bounds |<H>|, and with the
 # per-slot factor below every derivative).
 TOL = {qsv.C128: 1e-12, qsv.C64: 1e-5}
+
+
+def dname(dt):
+    return "c128" if dt == qsv.C128 else "c64"
+
+
+def _case():
+    # the running test's id (pytest sets it for the duration of each test)
+    return os.environ.get("PYTEST_CURRENT_TEST", "?").split(" ")[0]
 
 
 def np_dtype(dt):
@@ -48,9 +60,22 @@ def jac_bound(ops, n_params, observables):
     return np.outer(obs_scale(observables), np.maximum(per_p, 1.0))
 
 
-def assert_state_close(got, ref, tol, what=""):
-    err = np.linalg.norm(got.astype(np.complex128) - ref)
+def assert_state_close(got, ref, tol, what="", dtype=None):
+    """||got - ref||_2 <= tol (states of norm 1); the error is recorded."""
+    err = float(np.linalg.norm(got.astype(np.complex128) - ref))
+    dt = dtype if dtype is not None else ("c64" if got.dtype == np.complex64 else "c128")
+    record(_case(), "state " + what, dt if isinstance(dt, str) else dname(dt), err, tol)
     assert err <= tol, f"{what}: ||psi - psi_ref|| = {err:.3e} > {tol:.1e}"
+    return err
+
+
+def assert_rel_close(got, ref, scale, dt, what=""):
+    """max |got - ref| / scale <= TOL[dt] (scale: the bounds of reading 10,
+    sum |c_t| for expectation values, jac_bound for Jacobian entries); the
+    achieved error is recorded."""
+    err = float(np.max(np.abs(np.asarray(got) - np.asarray(ref)) / np.asarray(scale)))
+    record(_case(), what, dname(dt), err, TOL[dt])
+    assert err <= TOL[dt], f"{what}: relative error {err:.3e} > {TOL[dt]:.1e}"
     return err
 
 

@@ -49,7 +49,47 @@ def run_program(prog, phi, lam=None, slots=None):
             _stream(prog, st, phi)
 
 
+def _dense(prog, st, psi):
+    """The LDS-staged dense kernel, index by index: 256 threads load the tile
+    (tile-local index tid + r * 256 -> global offset and compact LDS index by
+    bit deposits), wave w computes rows [w R, (w+1) R) of the 64 tuples (lane
+    = tuple) from the padded LDS layout, and the outputs go back the same way."""
+    k = st["k"]
+    D = 1 << k
+    RW = D // 4
+    RL = (64 << k) // 256
+    M = _coef(prog, st["coff"], D * D).reshape(D, D)
+    sb, cb = st["sb"], st["cb"]
+    lds_size = (64 << k) * 65 // 64
+    for tile in range(st["n_tiles"]):
+        base = expand(tile, st["outer"]) | st["setmask"]
+        lds = np.full(lds_size, np.nan + 0j)
+        slots = []
+        for tid in range(256):
+            goff = sum(1 << sb[i] for i in range(8) if (tid >> i) & 1)
+            coff = sum(1 << cb[i] for i in range(8) if (tid >> i) & 1)
+            for r in range(RL):
+                g = base | goff | st["goff_hi"][r]
+                c = coff | st["coff_hi"][r]
+                assert c + (c >> 6) < lds_size
+                lds[c + (c >> 6)] = psi[g]
+                slots.append((g, c))
+        assert len({g for g, _ in slots}) == 64 << k and len({c for _, c in slots}) == 64 << k
+        out = lds.copy()
+        for wave in range(4):
+            for lane in range(64):
+                x = np.array([lds[(j << 6) + lane + j] for j in range(D)])
+                for q in range(RW):
+                    row = wave * RW + q
+                    out[(row << 6) + lane + row] = M[row] @ x
+        for g, c in slots:
+            psi[g] = out[c + (c >> 6)]
+
+
 def _stream(prog, st, psi):
+    if st["type"] == "dense":
+        _dense(prog, st, psi)
+        return
     ex = st["ex"]
     idx = np.array([expand(k, ex) | st["setmask"] for k in range(st["n_items"])], dtype=np.int64)
     m2 = np.array(st["m2"], dtype=float).view(np.complex128)

@@ -7,7 +7,7 @@ import pytest
 import oracle
 from paper_2403_02512_amd import qsv
 from paper_2403_02512_amd import workloads as W
-from tests.gpu_helpers import TOL, jac_bound
+from tests.gpu_helpers import assert_rel_close, jac_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -42,15 +42,13 @@ def _oracle(c, params):
 
 
 def _check(cs, params, ev, grads, dt):
-    tol = TOL[dt]
     for i, c in enumerate(cs):
         want_ev, want_j = _oracle(c, params[i])
         s = float(np.sum(np.abs(c.observables[0].coeffs)))
-        assert abs(ev[i] - want_ev) <= tol * s, (i, c.name, ev[i], want_ev)
+        assert_rel_close(ev[i], want_ev, s, dt, f"expval circuit {i} ({c.name})")
         if grads is not None and c.n_params:
             bound = jac_bound(c.ops, c.n_params, c.observables[:1])[0]
-            err = np.max(np.abs(grads[i] - want_j) / bound)
-            assert err <= tol, (i, c.name, err)
+            assert_rel_close(grads[i], want_j, bound, dt, f"gradient circuit {i} ({c.name})")
 
 
 @pytest.mark.parametrize("dt", [qsv.C128, qsv.C64])
@@ -80,9 +78,9 @@ def test_batch_matches_single_circuit_path(ctx):
         jac, e1 = qsv.adjoint_jacobian(st, c.ops, c.params, c.observables)
         st.close()
         s = float(np.sum(np.abs(c.observables[0].coeffs)))
-        assert abs(ev[i] - e1[0]) <= 1e-12 * s
+        assert_rel_close(ev[i], e1[0], s, qsv.C128, "batched vs single expval")
         bound = jac_bound(c.ops, c.n_params, c.observables)[0]
-        assert np.max(np.abs(grads[i] - jac[0]) / bound) <= 1e-12
+        assert_rel_close(grads[i], jac[0], bound, qsv.C128, "batched vs single gradient")
     b.close()
 
 

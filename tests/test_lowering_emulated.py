@@ -57,3 +57,43 @@ def test_layers_with_mixed_generators(opt):
     for o in range(2):
         g, _ = emulate_adjoint(n, c.ops, c.params, psi, oracle.apply_pauli_sum(psi, obs[o]), **opt)
         np.testing.assert_allclose(g, want[o], atol=1e-11)
+
+
+@pytest.mark.parametrize("k", [3, 4, 5, 6])
+@pytest.mark.parametrize("where", ["low", "high", "mixed", "controlled"])
+def test_dense_kernel_lowering(k, where):
+    """Dense k-qubit unitaries through the LDS-staged kernel's index
+    arithmetic (targets on the lowest bits, the highest, scattered, and with
+    controls on low and high bits, which must stay outside the tile)."""
+    n = k + 7 if where != "controlled" else k + 9
+    rng = np.random.default_rng(10 * k + len(where))
+    if where == "low":
+        wires, nc = [n - 1 - b for b in range(k)], 0
+    elif where == "high":
+        wires, nc = list(range(k))[::-1], 0
+    elif where == "mixed":
+        wires, nc = [int(w) for w in rng.choice(n, size=k, replace=False)], 0
+    else:
+        wires, nc = [n - 1, 0] + [int(w) for w in rng.choice(range(1, n - 1), size=k, replace=False)], 2
+    o = W.op("QubitUnitary", wires, n_ctrls=nc, ctrl_values=2 if nc else -1, matrix=W.random_unitary(k, rng))
+    psi0 = W.random_state(n, k)
+    from paper_2403_02512_amd import qsv
+    prog = qsv.plan_json(n, [o], [])
+    assert [st["type"] for st in prog["steps"]] == ["dense"]
+    got = emulate_apply(n, [o], [], psi0)
+    np.testing.assert_allclose(got, oracle.apply(n, [o], [], psi=psi0), atol=1e-12)
+
+
+@pytest.mark.parametrize("opts", [{}, {"tile_bits": 6, "low_bits": 2}, {"tile_bits": 5, "low_bits": 1}])
+def test_u3_brickwall_adjoint_program(opts):
+    """U3 layers and CNOT bricks (the 32-qubit benchmark circuit's shape): in
+    the reverse sweep the phase factors of each U3 run as one-qubit matrices
+    inside register layers when their wire is a tile bit, and through the
+    global-index diagonal path otherwise."""
+    n = 9
+    c = W.config5(n=n, layers=3)
+    psi = oracle.apply(n, c.ops, c.params)
+    lam = oracle.apply_pauli_sum(psi, c.observables[0])
+    g, phi = emulate_adjoint(n, c.ops, c.params, psi, lam, **opts)
+    np.testing.assert_allclose(g, oracle.adjoint_jacobian(psi, c.ops, c.params, c.observables)[0], atol=1e-11)
+    np.testing.assert_allclose(phi, oracle.zero_state(n), atol=1e-12)

@@ -35,10 +35,10 @@ def test_small_register_is_one_tile():
 @pytest.mark.parametrize("name,k,low", [("RX", 1, True), ("IsingXX", 2, True), ("QubitUnitary", 3, True),
                                         ("QubitUnitary", 4, False), ("QubitUnitary", 5, False),
                                         ("QubitUnitary", 4, True), ("QubitUnitary", 5, True),
-                                        ("QubitUnitary", 6, False)])
+                                        ("QubitUnitary", 6, False), ("QubitUnitary", 6, True)])
 def test_single_gate_kernel_choice(name, k, low):
-    """One pass per single gate: streaming kernels up to k = 5 (on low or high
-    bits), the LDS-tiled pass for 6-qubit matrices."""
+    """One pass per single gate: the pair and quad kernels for k = 1, 2, the
+    LDS-staged dense kernel for k = 3..6 (on low or high bits)."""
     n = 20
     rng = np.random.default_rng(0)
     mat = W.random_unitary(k, rng) if name == "QubitUnitary" else None
@@ -46,8 +46,9 @@ def test_single_gate_kernel_choice(name, k, low):
     wires = list(range(n - k, n))[::-1] if low else list(range(k))
     o = W.op(name, wires, *slots, matrix=mat)
     st = qsv.plan_stats(n, [o], [0.3])
-    assert st["passes"] == 1
-    assert st["tile_passes"] == (1 if k == 6 else 0)
+    assert st["passes"] == 1 and st["tile_passes"] == 0
+    kind = qsv.plan_json(n, [o], [0.3])["steps"][0]["type"]
+    assert kind == {1: "gate1", 2: "gate2"}.get(k, "dense")
 
 
 def test_non_commuting_gates_keep_order():
@@ -87,3 +88,37 @@ def test_wide_gate_beside_coalescing_bits_terminates():
     for adj in (False, True):
         st = qsv.plan_stats(n, ops, [0.2], adjoint=adj, tile_bits=5, low_bits=2)
         assert 1 <= st["passes"] <= 2
+
+
+def _deep_narrow(n=10, layers=40):
+    ops, p = [], 0
+    for _ in range(layers):
+        for q in range(n):
+            for g in ("RX", "RY", "RZ"):
+                ops.append(W.op(g, [q], (p, 1.0)))
+                p += 1
+    return ops, np.linspace(0.1, 3.0, p)
+
+
+@pytest.mark.parametrize("dt", [qsv.C128, qsv.C64])
+@pytest.mark.parametrize("tile_bits", [0, 8, 12, 13])
+def test_tile_passes_fit_the_cu_lds(dt, tile_bits):
+    """A deep narrow circuit (10 qubits, 1200 trainable slots) puts many
+    inner products next to each other; every adjoint and forward tile pass
+    must stay within the CU's 160 KiB of LDS (slot accumulators and phase
+    tables included), at every tile width the options allow."""
+    ops, params = _deep_narrow()
+    for adj in (False, True):
+        prog = qsv.plan_json(10, ops, params, dtype=dt, adjoint=adj, tile_bits=tile_bits)
+        tiles = [st for st in prog["steps"] if st["type"] == "tile"]
+        assert tiles and all(st["lds"] <= 160 * 1024 for st in tiles), max(st["lds"] for st in tiles)
+        if adj:
+            assert sum(st["nslots"] for st in tiles) == len(params)
+
+
+def test_qaoa_lds_below_two_blocks_per_cu():
+    # the benchmark's passes keep two blocks per CU (<= 80 KiB each)
+    c = W.config3(n=28)
+    for adj in (False, True):
+        prog = qsv.plan_json(28, c.ops, c.params, adjoint=adj)
+        assert max(st["lds"] for st in prog["steps"] if st["type"] == "tile") <= 80 * 1024
