@@ -319,6 +319,7 @@ def main():
     ap.add_argument("--tile-bits", type=int, default=0, help="qubits per LDS tile, one-vector passes (0: default)")
     ap.add_argument("--tile-bits-adj", type=int, default=0, help="qubits per LDS tile, adjoint passes (0: default)")
     ap.add_argument("--low-bits", type=int, default=0, help="coalescing low bits per tile (0: default)")
+    ap.add_argument("--tile-ws", type=int, default=0, help="warp-specialised tile passes (QSV_OPT_TILE_WS)")
     ap.add_argument("--micro", action="store_true", help="per-kernel-class gate-apply bandwidth sweep")
     ap.add_argument("--micro-dtype", default="c128", choices=["c128", "c64"])
     ap.add_argument("--nt", action="store_true", help="micro: non-temporal stores (QSV_OPT_NONTEMPORAL)")
@@ -369,6 +370,7 @@ def main():
     ctx.set_option(qsv.OPT_TILE_BITS, args.tile_bits)
     ctx.set_option(qsv.OPT_TILE_BITS_ADJ, args.tile_bits_adj)
     ctx.set_option(qsv.OPT_LOW_BITS, args.low_bits)
+    ctx.set_option(qsv.OPT_TILE_WS, args.tile_ws)
     print(f"bench: {circ.name}, complex128, {args.warmup} warm-up + {args.steps} timed steps", file=sys.stderr,
           flush=True)
     h = qaoa_eval(ctx, circ, qsv.C128, args.steps, args.warmup)
@@ -378,7 +380,7 @@ def main():
     # the counters were taken on
     from paper_2403_02512_amd.rocprof_summary import read_traffic
     tr = None
-    if n == 28 and not (args.tile_bits or args.tile_bits_adj or args.low_bits) and args.fusion:
+    if n == 28 and not (args.tile_bits or args.tile_bits_adj or args.low_bits) and args.fusion and not args.tile_ws:
         tr = (read_traffic(os.path.join(ROOT, "profiles", "hbm_traffic_qaoa28_c128.txt")) or {}).get(d["kind"])
     roofline = {"bound": "hbm", "kernel": d["kind"], "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": tr,
@@ -409,7 +411,8 @@ def main():
                                f"adjoint Jacobian", "n_qubits": n, "n_gates": len(circ.ops),
                    "n_params": circ.n_params, "n_terms": len(circ.observables[0].words), "precision": "c128",
                    "fusion": bool(args.fusion), "tile_bits": args.tile_bits or "default",
-                   "tile_bits_adj": args.tile_bits_adj or "default", "low_bits": args.low_bits or "default"},
+                   "tile_bits_adj": args.tile_bits_adj or "default", "low_bits": args.low_bits or "default",
+                   "tile_ws": bool(args.tile_ws)},
         "roofline": roofline, "cpu_baseline": cpu,
         "ms_per_step_no_events": round(1e3 * h["s_per_eval_no_events"], 3),
         "forward_ms": round(1e3 * h["forward_s"], 3), "gates_per_s": h["gates_per_s"],

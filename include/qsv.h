@@ -124,8 +124,18 @@ enum {
     QSV_OPT_TILE_BITS_ADJ = 3,  /* qubits per LDS tile for two-vector adjoint passes      */
     QSV_OPT_LOW_BITS = 4,       /* low index bits every tile keeps for coalescing         */
     QSV_OPT_PROFILE = 5,        /* 1: time every launch with HIP events                   */
-    QSV_OPT_NONTEMPORAL = 6,    /* 1: streaming kernels use non-temporal stores           */
-    QSV_OPT_LAYERS = 7          /* 1: one-qubit runs in register groups run as layers (default) */
+    QSV_OPT_NONTEMPORAL = 6,    /* 1: every kernel that writes the state back uses
+                                   non-temporal (streaming) stores (paper Sec. 3.1); 0 default */
+    QSV_OPT_LAYERS = 7,         /* 1: one-qubit runs in register groups run as layers (default) */
+    QSV_OPT_TILE_WS = 10,       /* 1: group-only tile passes of >= 2^11 amplitudes run
+                                   warp-specialised where two tile buffers fit the LDS (load
+                                   waves fetch the next tile while compute waves run this
+                                   one); 0 (default): one buffer per block, two blocks per CU */
+    /* Fault injection, for tests of the error paths only:                                     */
+    QSV_OPT_TEST_ALLOC_LIMIT = 8, /* >0: a device allocation above this many bytes fails with
+                                     QSV_ERR_OOM, as if the device were full; 0: no limit    */
+    QSV_OPT_TEST_FAIL_LAUNCH = 9  /* k>0: the k-th kernel launch from now fails with
+                                     QSV_ERR_HIP before it is issued (then the count is spent) */
 };
 qsv_status qsv_ctx_set_option(qsv_ctx *ctx, int option, int64_t value);
 qsv_status qsv_ctx_get_option(qsv_ctx *ctx, int option, int64_t *value);
@@ -198,6 +208,17 @@ qsv_status qsv_apply(qsv_state *s, const qsv_op *ops, size_t n_ops, const double
 /* out[o] = <psi|H_o|psi> for n_obs Pauli sums (paper Sec. 2.2).  Host output;
  * synchronises the context stream. */
 qsv_status qsv_expval(qsv_state *s, const qsv_pauli_sum *obs, size_t n_obs, double *out);
+
+/* qsv_expval without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same results as qsv_expval, with the Pauli tables,
+ * per-block partials and results kept in a static device scratch of 8 MiB
+ * that every device holds for the life of the process.  Observables whose
+ * tables, partials and results exceed it are rejected with QSV_ERR_ARG
+ * before any device work (a few hundred thousand terms fit).  Calls that
+ * overlap on one device share the scratch and race: issue them in order.
+ * Host output; synchronises the context stream. */
+qsv_status qsv_expval_noalloc(qsv_state *s, const qsv_pauli_sum *obs, size_t n_obs, double *out);
 
 /* Variance out[o] = <H_o^2> - <H_o>^2 = ||H_o psi||^2 - <H_o>^2 for n_obs Pauli
  * sums (paper Sec. 2.2 lists variances among the measurements).  Host output;

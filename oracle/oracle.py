@@ -20,7 +20,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB_PATH: load another build of the oracle (the CPU suite's
+# sanitizer build); the default is the in-tree liboracle.so
+_LIB_PATH = os.environ.get("ORACLE_LIB_PATH") or os.path.join(_HERE, "liboracle.so")
 
 # Gate numbering of oracle.h (enum orc_gate), keyed by PennyLane gate names.
 GATES = {
@@ -53,13 +55,26 @@ def build(force: bool = False) -> str:
     return _LIB_PATH
 
 
+def build_sanitized(out_dir: str) -> str:
+    """Compile the oracle with AddressSanitizer and UndefinedBehaviorSanitizer
+    (any report aborts) into out_dir; used by the CPU suite's sanitizer run."""
+    os.makedirs(out_dir, exist_ok=True)
+    out = os.path.join(out_dir, "liboracle.so")
+    subprocess.check_call([
+        "gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+        "-fno-sanitize-recover=undefined", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+        "-std=gnu11", "-Wall", _SRC, "-o", out, "-lm"])
+    return out
+
+
 _lib = None
 
 
 def lib():
     global _lib
     if _lib is None:
-        build()
+        if not os.environ.get("ORACLE_LIB_PATH"):
+            build()
         L = ctypes.CDLL(_LIB_PATH)
         dp = ctypes.POINTER(ctypes.c_double)
         i32p = ctypes.POINTER(ctypes.c_int32)

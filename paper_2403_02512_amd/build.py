@@ -65,5 +65,50 @@ def build(verbose: bool = True) -> str:
     return LIB
 
 
+HOST_SOURCES = ["gates.cpp", "plan.cpp", "api.cpp"]
+# host-only instrumentation: the kernels (.hip) keep their normal objects
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
+
+
+def build_sanitized(out_dir: str) -> str:
+    """A CPU-test build of the library whose host runtime (validation,
+    planning, lowering, the C entry points) carries AddressSanitizer and
+    UndefinedBehaviorSanitizer, linked with the normal kernel objects.
+    Returns the path of its libqsv.so (run it with the ASan runtime
+    preloaded)."""
+    os.makedirs(out_dir, exist_ok=True)
+    kobjs = []
+    for src in SOURCES:
+        if src.endswith(".hip"):
+            obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+            kobjs.append(obj if os.path.exists(obj) else _compile(src))
+    hobjs = []
+    for src in HOST_SOURCES:
+        obj = os.path.join(out_dir, src + ".o")
+        cmd = [hipcc(), f"--offload-arch={ARCH}", "-O1", "-std=c++17", "-fPIC", "-Wall", *SANITIZE,
+               f"-I{INCLUDE}", f"-I{CSRC}", "-c", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+        hobjs.append(obj)
+    lib = os.path.join(out_dir, "libqsv.so")
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-shared-libsan",
+           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", *hobjs, *kobjs, "-o", lib]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return lib
+
+
+def asan_runtime() -> str:
+    """The clang AddressSanitizer runtime the sanitized build links against."""
+    clang = os.path.join(os.path.dirname(os.path.realpath(hipcc())), "..", "llvm", "bin", "clang")
+    if not os.path.exists(clang):
+        clang = "/opt/rocm/llvm/bin/clang"
+    r = subprocess.run([clang, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    return r.stdout.strip()
+
+
 if __name__ == "__main__":
     build()

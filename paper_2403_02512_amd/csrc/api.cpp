@@ -12,6 +12,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 
 #include "qsv_internal.h"
@@ -47,7 +48,10 @@ struct qsv_ctx {
     bool own_stream = false;
     std::string err;
     int64_t opt_fusion = 1, opt_tile_bits = 0, opt_tile_bits_adj = 0, opt_low_bits = 0, opt_profile = 0,
-            opt_nontemporal = 0, opt_layers = 1;
+            opt_nontemporal = 0, opt_layers = 1, opt_tile_ws = 0;
+    void* scratch = nullptr;  // this device's allocation-free scratch (qsv_expval_noalloc)
+    // fault injection for tests of the error paths (QSV_OPT_TEST_*)
+    int64_t test_alloc_limit = 0, test_fail_launch = 0;
     DevBuf ops, coef, words, partials, slots, pgroups, pterms, paux, ws0, ws1, binbits, csr_ptr, csr_col, csr_val,
         smp_chunk, smp_resid, smp_out;
     void* pin = nullptr;
@@ -97,6 +101,13 @@ qsv_status guard(qsv_ctx* ctx, F&& f) {
 
 void set_device(qsv_ctx* c) { HIPCHK(hipSetDevice(c->device)); }
 
+// hipMalloc, except that with QSV_OPT_TEST_ALLOC_LIMIT set an allocation
+// above the limit fails as if the device were out of memory.
+hipError_t dev_malloc(qsv_ctx* c, void** p, size_t bytes) {
+    if (c->test_alloc_limit > 0 && bytes > (size_t)c->test_alloc_limit) return hipErrorOutOfMemory;
+    return hipMalloc(p, bytes);
+}
+
 void ensure(qsv_ctx* c, DevBuf& b, size_t bytes) {
     if (bytes == 0) bytes = 8;
     if (b.bytes >= bytes) return;
@@ -107,7 +118,7 @@ void ensure(qsv_ctx* c, DevBuf& b, size_t bytes) {
         b.bytes = 0;
     }
     const size_t want = std::max(bytes, (size_t)4096);
-    hipError_t e = hipMalloc(&b.p, want);
+    hipError_t e = dev_malloc(c, &b.p, want);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         fail(QSV_ERR_OOM, "device allocation of " + std::to_string(want) + " bytes failed");
@@ -178,6 +189,9 @@ struct Timed {
     double bytes;
     hipEvent_t a = nullptr;
     Timed(qsv_ctx* c_, int k, double by) : c(c_), kind(k), bytes(by) {
+        if (c->test_fail_launch > 0 && --c->test_fail_launch == 0)
+            fail(QSV_ERR_HIP, std::string("injected failure of a ") + qsv::kKernelNames[kind] +
+                                  " launch (QSV_OPT_TEST_FAIL_LAUNCH)");
         if (c->opt_profile) {
             a = get_event(c);
             HIPCHK(hipEventRecord(a, c->stream));
@@ -419,7 +433,7 @@ std::vector<Proto> schedule_groups(const std::vector<Proto>& pr, int GB) {
 
 // Lower one planned pass into a k_tile step.
 void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item>& items, const Pass& pass, int n,
-                bool two, bool dagger, size_t eb, bool layers = true) {
+                bool two, bool dagger, size_t eb, bool layers = true, bool ws = false) {
     Step st;
     st.type = Step::TILE;
     int sb[16], b = 0;
@@ -822,7 +836,15 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
     st.lds = (size_t)tile_lds_bytes(b, two, (int)eb, nslots, a.zt_n);
     if (st.lds > (size_t)LDS_PER_CU)  // the planner's budget keeps passes below this
         fail(QSV_ERR_UNSUPPORTED, "tile pass needs more LDS than a CU has");
-    if (tile_prefetch(st.lds, R)) st.grid = (int)std::min<uint64_t>(a.n_tiles, TILE_PF_GRID);
+    {
+        // the warp-specialised form needs a second tile buffer
+        const size_t lds_ws = st.lds + (size_t)(two ? 2 : 1) * ((size_t)1 << b) * eb;
+        if (ws && !st.generic && nthr == 256 && R >= 8 && lds_ws <= (size_t)LDS_PER_CU) {
+            a.flags |= TILE_WS;
+            st.lds = lds_ws;
+            st.grid = (int)std::min<uint64_t>(a.n_tiles, TILE_WS_GRID);
+        }
+    }
     st.bytes = (double)(two ? 4 : 2) * (double)((uint64_t)1 << n) * (double)eb;
     P.max_partials = std::max(P.max_partials, (size_t)nslots * st.grid);
     P.steps.push_back(st);
@@ -863,17 +885,10 @@ bool lower_single(Program& P, const Factor& f, int n, size_t eb, int low_bits) {
             }
             st.bytes = 2.0 * N * eb * frac;
         }
-    } else if (f.k == 2) {
-        st.type = Step::GATE2;
-        st.cls = classify2(f.m);
-        st.b0 = wire_bit(n, f.tw[0]);
-        st.b1 = wire_bit(n, f.tw[1]);
-        for (int j = 0; j < 16; ++j) {
-            st.m4.re[j] = f.m[j].real();
-            st.m4.im[j] = f.m[j].imag();
-        }
-        st.bytes = (st.cls == MC_MID ? 1.0 : 2.0) * N * eb * frac;
-    } else if (f.k >= 3 && f.k <= 6 && n - f.nc >= f.k + 6) {
+    } else if (f.k >= 2 && f.k <= 6 && n - f.nc >= f.k + 6 &&
+               (f.k >= 3 || n - 1 - f.tw[0] < 2 || n - 1 - f.tw[1] < 2)) {
+        // (two-qubit gates only when a target is one of the two lowest bits:
+        // the quad kernel's per-lane 64-byte strides there coalesce poorly)
         // LDS-staged dense matrix: targets plus six lane bits per tile
         st.type = Step::DENSE;
         DenseArgs& d = st.da;
@@ -916,9 +931,24 @@ bool lower_single(Program& P, const Factor& f, int n, size_t eb, int low_bits) {
         d.outer = make_expand(outer_pos);
         d.setmask = setmask;
         d.n_tiles = (uint64_t)1 << (n - (int)outer_pos.size());
+        // the kernel's matrix layout: (wave w, column j, row q of the wave's
+        // dim / 4 rows), so one input's entries are contiguous per wave
         st.coff = (int64_t)P.coef.size();
-        for (int j = 0; j < dim * dim; ++j) P.coef.push_back(f.m[j]);
+        const int rw = dim / 4;
+        for (int w = 0; w < 4; ++w)
+            for (int j = 0; j < dim; ++j)
+                for (int q = 0; q < rw; ++q) P.coef.push_back(f.m[(size_t)(w * rw + q) * dim + j]);
         st.bytes = 2.0 * N * eb * frac;
+    } else if (f.k == 2) {
+        st.type = Step::GATE2;
+        st.cls = classify2(f.m);
+        st.b0 = wire_bit(n, f.tw[0]);
+        st.b1 = wire_bit(n, f.tw[1]);
+        for (int j = 0; j < 16; ++j) {
+            st.m4.re[j] = f.m[j].real();
+            st.m4.im[j] = f.m[j].imag();
+        }
+        st.bytes = (st.cls == MC_MID ? 1.0 : 2.0) * N * eb * frac;
     } else if (f.k == 3 && n >= 6 && [&] {
                    for (int i = 0; i < f.k; ++i)
                        if (n - 1 - f.tw[i] >= 6) return false;
@@ -988,8 +1018,10 @@ PlanOptions plan_opts(int64_t tile_bits, int64_t low_bits, int64_t fusion, qsv_d
 }
 
 PlanOptions plan_opts(qsv_ctx* c, qsv_dtype dt, bool two) {
-    return plan_opts(two ? c->opt_tile_bits_adj : c->opt_tile_bits, c->opt_low_bits, c->opt_fusion, dt, two,
-                     c->opt_layers);
+    PlanOptions o = plan_opts(two ? c->opt_tile_bits_adj : c->opt_tile_bits, c->opt_low_bits, c->opt_fusion, dt,
+                              two, c->opt_layers);
+    o.ws = c->opt_tile_ws != 0;
+    return o;
 }
 
 Program build_program(const PlanOptions& po, const std::vector<Factor>& F, const std::vector<Item>& items, int n,
@@ -1001,7 +1033,7 @@ Program build_program(const PlanOptions& po, const std::vector<Factor>& F, const
         if (allow_streaming && !two && p.items.size() == 1 && !items[p.items[0]].dot) {
             if (lower_single(P, F[items[p.items[0]].f], n, eb, po.low)) continue;
         }
-        lower_tile(P, F, items, p, n, two, dagger, eb, po.layers);
+        lower_tile(P, F, items, p, n, two, dagger, eb, po.layers, po.ws);
     }
     return P;
 }
@@ -1382,6 +1414,28 @@ int qsv_device_count(void) {
 int qsv_kernel_kinds(void) { return KK_COUNT; }
 const char* qsv_kernel_name(int kind) { return kind >= 0 && kind < KK_COUNT ? kKernelNames[kind] : ""; }
 
+namespace {
+// Device address of the allocation-free scratch, taken once per device (with
+// that device current) at the first context created on it.
+std::mutex g_scratch_mu;
+void* g_scratch[64] = {nullptr};
+
+void* scratch_for_device(int device) {
+    if (device < 0 || device >= 64) fail(QSV_ERR_UNSUPPORTED, "device id beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void* p = nullptr;
+        hipError_t e = noalloc_scratch_address(&p);
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            fail(QSV_ERR_HIP, std::string("hipGetSymbolAddress of the scratch failed: ") + hipGetErrorString(e));
+        }
+        g_scratch[device] = p;
+    }
+    return g_scratch[device];
+}
+}  // namespace
+
 qsv_status qsv_ctx_create(int device, void* hip_stream, qsv_ctx** out) {
     return guard(nullptr, [&] {
         if (!out) fail(QSV_ERR_ARG, "out is NULL");
@@ -1398,6 +1452,7 @@ qsv_status qsv_ctx_create(int device, void* hip_stream, qsv_ctx** out) {
             c->own_stream = true;
         }
         HIPCHK(hipEventCreateWithFlags(&c->pin_ev, hipEventDisableTiming));
+        c->scratch = scratch_for_device(device);
         *out = c.release();
     });
 }
@@ -1466,6 +1521,15 @@ qsv_status qsv_ctx_set_option(qsv_ctx* c, int option, int64_t v) {
         case QSV_OPT_PROFILE: c->opt_profile = v != 0; break;
         case QSV_OPT_NONTEMPORAL: c->opt_nontemporal = v != 0; break;
         case QSV_OPT_LAYERS: c->opt_layers = v != 0; break;
+        case QSV_OPT_TILE_WS: c->opt_tile_ws = v != 0; break;
+        case QSV_OPT_TEST_ALLOC_LIMIT:
+            if (v < 0) fail(QSV_ERR_ARG, "allocation limit must be >= 0");
+            c->test_alloc_limit = v;
+            break;
+        case QSV_OPT_TEST_FAIL_LAUNCH:
+            if (v < 0) fail(QSV_ERR_ARG, "launch count must be >= 0");
+            c->test_fail_launch = v;
+            break;
         default: fail(QSV_ERR_ARG, "unknown option");
         }
     });
@@ -1482,6 +1546,9 @@ qsv_status qsv_ctx_get_option(qsv_ctx* c, int option, int64_t* v) {
         case QSV_OPT_PROFILE: *v = c->opt_profile; break;
         case QSV_OPT_NONTEMPORAL: *v = c->opt_nontemporal; break;
         case QSV_OPT_LAYERS: *v = c->opt_layers; break;
+        case QSV_OPT_TILE_WS: *v = c->opt_tile_ws; break;
+        case QSV_OPT_TEST_ALLOC_LIMIT: *v = c->test_alloc_limit; break;
+        case QSV_OPT_TEST_FAIL_LAUNCH: *v = c->test_fail_launch; break;
         default: fail(QSV_ERR_ARG, "unknown option");
         }
     });
@@ -1543,7 +1610,7 @@ qsv_status qsv_state_create(qsv_ctx* c, int n, qsv_dtype dt, qsv_state** out) {
         set_device(c);
         const size_t bytes = ((size_t)1 << n) * elem_bytes(dt);
         void* p = nullptr;
-        if (hipMalloc(&p, bytes) != hipSuccess) {
+        if (dev_malloc(c, &p, bytes) != hipSuccess) {
             (void)hipGetLastError();
             fail(QSV_ERR_OOM, "state allocation of " + std::to_string(bytes) + " bytes failed");
         }
@@ -1684,9 +1751,9 @@ qsv_status qsv_plan_json(int n, qsv_dtype dt, const qsv_op* ops, size_t n_ops, c
             } else if (st.type == Step::TILE) {
                 const TileArgs& a = st.ta;
                 add(",\"b\":%d,\"nthr\":%d,\"R\":%d,\"grid\":%d,\"op0\":%d,\"nops\":%d,\"nslots\":%d,\"slot_base\":%d,"
-                    "\"generic\":%d,\"n_tiles\":%llu,\"n_outer\":%d,\"lds\":%zu,\"sb\":[",
+                    "\"generic\":%d,\"n_tiles\":%llu,\"n_outer\":%d,\"lds\":%zu,\"flags\":%d,\"sb\":[",
                     a.b, st.nthr, st.R, st.grid, a.op0, a.nops, a.nslots, st.slot_base, (int)st.generic,
-                    (unsigned long long)a.n_tiles, a.n_outer, st.lds);
+                    (unsigned long long)a.n_tiles, a.n_outer, st.lds, a.flags);
                 for (int j = 0; j < a.b; ++j) add(j ? ",%d" : "%d", a.sb[j]);
                 js += "],\"offhi\":[";
                 for (int r = 0; r < st.R; ++r) add(r ? ",%llu" : "%llu", (unsigned long long)a.offhi[r]);
@@ -1794,6 +1861,53 @@ qsv_status qsv_expval(qsv_state* s, const qsv_pauli_sum* obs, size_t n_obs, doub
         ensure(c, c->slots, n_obs * 8);
         for (size_t o = 0; o < n_obs; ++o) run_pauli(c, s->dt, s->n, T, (int)o, s->ptr, nullptr, (double*)c->slots.p + o);
         HIPCHK(hipMemcpyAsync(out, c->slots.p, n_obs * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    });
+}
+
+
+qsv_status qsv_expval_noalloc(qsv_state* s, const qsv_pauli_sum* obs, size_t n_obs, double* out) {
+    qsv_ctx* c = s ? s->ctx : nullptr;
+    return guard(c, [&] {
+        state_ctx(s);
+        validate_obs_impl(s->n, obs, n_obs);
+        if (n_obs && !out) fail(QSV_ERR_ARG, "out is NULL");
+        if (!n_obs) return;
+        set_device(c);
+        char* base = (char*)c->scratch;
+        if (!base) fail(QSV_ERR_HIP, "no scratch address for this context's device");
+        PauliTables T;
+        for (size_t o = 0; o < n_obs; ++o) add_pauli(T, obs[o], 1.0);
+        const uint64_t N = 1ull << s->n;
+        const int grid = pauli_grid(N);
+        auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+        const size_t gb = T.groups.size() * sizeof(PauliGroupDev), tb = T.terms.size() * sizeof(PauliTermDev),
+                     ab = T.aux.size() * 8;
+        const size_t off_g = 0, off_t = al(off_g + gb), off_a = al(off_t + tb), off_p = al(off_a + ab),
+                     off_s = al(off_p + (size_t)grid * 8), total = off_s + n_obs * 8;
+        if (total > NOALLOC_SCRATCH_BYTES)
+            fail(QSV_ERR_ARG, "observables need " + std::to_string(total) + " bytes of scratch; the allocation-free "
+                              "entry point has " + std::to_string(NOALLOC_SCRATCH_BYTES));
+        if (gb) HIPCHK(hipMemcpyAsync(base + off_g, T.groups.data(), gb, hipMemcpyHostToDevice, c->stream));
+        if (tb) HIPCHK(hipMemcpyAsync(base + off_t, T.terms.data(), tb, hipMemcpyHostToDevice, c->stream));
+        if (ab) HIPCHK(hipMemcpyAsync(base + off_a, T.aux.data(), ab, hipMemcpyHostToDevice, c->stream));
+        const PauliGroupDev* groups = (const PauliGroupDev*)(base + off_g);
+        const PauliTermDev* terms = (const PauliTermDev*)(base + off_t);
+        const uint64_t* aux = (const uint64_t*)(base + off_a);
+        double* partials = (double*)(base + off_p);
+        double* slots = (double*)(base + off_s);
+        for (size_t o = 0; o < n_obs; ++o) {
+            // every block writes its partial and the reduction writes the
+            // slot, so nothing in the scratch needs clearing between calls
+            const PauliGroupDev* g = groups + T.obs_groups[o].first;
+            HIPCHK(s->dt == QSV_C128
+                       ? launch_pauli<double>(c->stream, false, false, s->ptr, nullptr, N, g, T.obs_groups[o].second,
+                                              terms, aux, T.lut_tables[o], partials, grid)
+                       : launch_pauli<float>(c->stream, false, false, s->ptr, nullptr, N, g, T.obs_groups[o].second,
+                                             terms, aux, T.lut_tables[o], partials, grid));
+            HIPCHK(launch_reduce(c->stream, partials, grid, 1, slots + o));
+        }
+        HIPCHK(hipMemcpyAsync(out, slots, n_obs * 8, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
     });
 }
@@ -2055,6 +2169,7 @@ struct BatchLaunch {
     bool two = false, generic = false;
     int R = 1, nthr = 256, blocks = 0;
     size_t lds = 0;
+    int lut_tables = 0;                   // PAULI: most byte tables of one circuit (LDS)
     size_t entries_off = 0, blk_off = 0;  // byte offsets in the table buffer
     int n_entries = 0;
     double bytes = 0;
@@ -2063,6 +2178,7 @@ struct BatchLaunch {
 struct BatchPlan {
     std::vector<char> tab;           // the device table image
     size_t off_tops = 0, off_coef = 0, off_words = 0, off_args = 0, off_pg = 0, off_pt = 0, off_re = 0;
+    size_t off_aux = 0;
     int n_reduce = 0;
     std::vector<BatchLaunch> launches;
     size_t n_partials = 0, n_results = 0;
@@ -2160,6 +2276,7 @@ BatchPlan plan_batch(qsv_batch* B, const double* params, bool grad) {
         std::vector<Factor> F = forward_factors(ops.data(), ops.size(), pp, B->matrices.data(), false);
         std::vector<Item> it = forward_items(F, n);
         PlanOptions po = plan_opts(c, B->dt, false);
+        po.ws = false;  // the batched kernel runs the classic form
         Pf[ci] = build_program(po, F, it, n, B->dt, false, false, false);
         if (Pf[ci].steps.empty()) {  // no gates: one empty pass that writes |0..0>
             Pass p;
@@ -2170,7 +2287,9 @@ BatchPlan plan_batch(qsv_batch* B, const double* params, bool grad) {
         if (grad && B->n_params[ci]) {
             std::vector<Factor> Fa = forward_factors(ops.data(), ops.size(), pp, B->matrices.data(), true);
             std::vector<Item> ia = adjoint_items(Fa, n);
-            Pb[ci] = build_program(plan_opts(c, B->dt, true), Fa, ia, n, B->dt, true, true, false);
+            PlanOptions pa = plan_opts(c, B->dt, true);
+            pa.ws = false;  // the batched kernel runs the classic form
+            Pb[ci] = build_program(pa, Fa, ia, n, B->dt, true, true, false);
         }
     });
     for (size_t ci = 0; ci < nc; ++ci) {
@@ -2186,7 +2305,7 @@ BatchPlan plan_batch(qsv_batch* B, const double* params, bool grad) {
     PauliTables T;
     for (size_t ci = 0; ci < nc; ++ci) {
         qsv_pauli_sum h{(int64_t)B->ocoef[ci].size(), B->ocoef[ci].data(), B->ox[ci].data(), B->oz[ci].data()};
-        add_pauli(T, h, 1.0, false);  // the batched kernel runs the term loop
+        add_pauli(T, h, 1.0);
     }
     std::vector<char>& tab = bp.tab;
     std::vector<char> coef_b = coef_bytes(coef, B->dt);
@@ -2196,6 +2315,7 @@ BatchPlan plan_batch(qsv_batch* B, const double* params, bool grad) {
     bp.off_args = append_bytes(tab, args);
     bp.off_pg = append_bytes(tab, T.groups);
     bp.off_pt = append_bytes(tab, T.terms);
+    bp.off_aux = append_bytes(tab, T.aux);
     const uintptr_t pool = (uintptr_t)B->pool.p;
     std::vector<ReduceEntry> reds;
     auto tile_launches = [&](std::vector<std::vector<StepRef>>& steps, bool two) {
@@ -2274,6 +2394,7 @@ BatchPlan plan_batch(qsv_batch* B, const double* params, bool grad) {
             e.blk0 = (int32_t)blk.size();
             e.part_off = (int64_t)n_part;
             reds.push_back({(int64_t)n_part, e.nblk, (int32_t)ci});
+            L.lut_tables = std::max(L.lut_tables, T.lut_tables[ci]);
             n_part += (size_t)e.nblk;
             for (int b = 0; b < e.nblk; ++b) blk.push_back((int32_t)ents.size());
             ents.push_back(e);
@@ -2339,11 +2460,13 @@ void enqueue_batch(qsv_batch* B, const BatchPlan& bp) {
             e = c128 ? launch_pauli_batch<double>(st, L.two, (const PauliEntry*)(T + L.entries_off),
                                                   (const int32_t*)(T + L.blk_off),
                                                   (const PauliGroupDev*)(T + bp.off_pg),
-                                                  (const PauliTermDev*)(T + bp.off_pt), part, L.blocks)
+                                                  (const PauliTermDev*)(T + bp.off_pt),
+                                                  (const uint64_t*)(T + bp.off_aux), L.lut_tables, part, L.blocks)
                      : launch_pauli_batch<float>(st, L.two, (const PauliEntry*)(T + L.entries_off),
                                                  (const int32_t*)(T + L.blk_off),
                                                  (const PauliGroupDev*)(T + bp.off_pg),
-                                                 (const PauliTermDev*)(T + bp.off_pt), part, L.blocks);
+                                                 (const PauliTermDev*)(T + bp.off_pt),
+                                                 (const uint64_t*)(T + bp.off_aux), L.lut_tables, part, L.blocks);
             t.done(e);
         }
     }

@@ -749,26 +749,24 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
     }
 }
 
-// Global loads of one tile's amplitudes (this thread's elements) into
-// registers; with synth the basis state is generated instead.
-template <typename T, bool TWO, int RP>
-__device__ __forceinline__ void tile_fetch(cx<T> (&vp)[RP], cx<T> (&vl)[RP], const cx<T>* phi_src,
-                                           const cx<T>* lam, const TileArgs& a, uint64_t offlo, uint64_t tile,
-                                           bool synth) {
+// The first tile of a warp-specialised block, loaded into LDS buffer buf.
+template <typename T, bool TWO, int R>
+__device__ __forceinline__ void tile_to_lds(cx<T>* buf, uint32_t stid, const cx<T>* phi_src, const cx<T>* lam,
+                                            const TileArgs& a, uint64_t offlo, uint64_t tile, bool synth) {
+    constexpr int NT = 256;
     const uint64_t base = expand_idx(tile, a.outer) | offlo;
-    if (synth) {
 #pragma unroll
-        for (int r = 0; r < RP; ++r) {
-            vp[r].re = (base | a.offhi[r]) == a.basis ? T(1) : T(0);
-            vp[r].im = T(0);
+    for (int r = 0; r < R; ++r) {
+        const uint64_t g = base | a.offhi[r];
+        cx<T> v;
+        if (synth) {
+            v.re = g == a.basis ? T(1) : T(0);
+            v.im = T(0);
+        } else {
+            v = phi_src[g];
         }
-    } else {
-#pragma unroll
-        for (int r = 0; r < RP; ++r) vp[r] = phi_src[base | a.offhi[r]];
-    }
-    if (TWO) {
-#pragma unroll
-        for (int r = 0; r < RP; ++r) vl[r] = lam[base | a.offhi[r]];
+        buf[stid + r * NT] = v;
+        if (TWO) buf[NT * R + stid + r * NT] = lam[g];
     }
 }
 
@@ -779,15 +777,7 @@ __device__ __forceinline__ void tile_fetch(cx<T> (&vp)[RP], cx<T> (&vl)[RP], con
 // described by a.  phi_src is where phi is read from (phi itself, or the
 // post-circuit state for an out-of-place first adjoint pass); with
 // TILE_SYNTH the tile is synthesised as the basis state a.basis instead.
-//
-// PF (prefetch): for tiles so large that one block fills the CU's LDS.  The
-// block holds the next tile's amplitudes in registers: their global loads are
-// issued right after the current tile is in LDS and stay in flight while the
-// tile's groups run (a workgroup barrier waits for LDS traffic only, not for
-// outstanding global loads), so HBM reads overlap the compute instead of
-// alternating with it.  One wave per SIMD leaves the whole register file
-// (VGPRs and AGPRs) to the wave, room for the 2R in-flight amplitudes.
-template <typename T, bool TWO, int LR, bool GEN, bool PF = false>
+template <typename T, bool TWO, int LR, bool GEN>
 __device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
                                           cx<T>* __restrict__ lam, const TileArgs& a, const TOp* __restrict__ ops,
                                           const cx<T>* __restrict__ coef, const uint64_t* __restrict__ words,
@@ -827,9 +817,6 @@ __device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
     c.offlo = offlo;
     for (int s = tid; s < a.nslots * c.nacc; s += nthr) c.sacc[s] = 0.0;
     const bool synth = (a.flags & TILE_SYNTH) != 0;
-    constexpr int RP = PF ? R : 1;
-    cx<T> pf_p[RP], pf_l[RP];
-    if (PF && blk < a.n_tiles) tile_fetch<T, TWO, RP>(pf_p, pf_l, phi_src, lam, a, offlo, blk, synth);
 
     for (uint64_t tile = blk; tile < a.n_tiles; tile += nblk) {
         const uint64_t base = expand_idx(tile, a.outer);
@@ -838,13 +825,6 @@ __device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
         // global -> LDS in chunks of LCH elements per thread: LCH loads in
         // flight per thread without keeping all R values live in registers
         constexpr int LCH = R < 8 ? R : 8;
-        if constexpr (PF) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                c.tp[stid + r * nthr] = pf_p[r];
-                if (TWO) c.tl[stid + r * nthr] = pf_l[r];
-            }
-        } else
         for (int r0 = 0; r0 < R; r0 += LCH) {
             cx<T> vp[LCH], vl[LCH];
 #pragma unroll
@@ -865,8 +845,6 @@ __device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
             }
         }
         __syncthreads();
-        if (PF && tile + nblk < a.n_tiles)  // in flight during the groups
-            tile_fetch<T, TWO, RP>(pf_p, pf_l, phi_src, lam, a, offlo, tile + nblk, synth);
         for (int oi = 0; oi < a.nops; ++oi) {
             const TOp& op = ops[a.op0 + oi];
             if ((op.kind <= OP_APPLYK || (op.kind >= OP_DOT1 && op.kind <= OP_DOTK)) &&
@@ -917,14 +895,135 @@ __global__ __launch_bounds__(256, 2) void k_tile(const cx<T>* phi_src, cx<T>* ph
     tile_body<T, TWO, LR, GEN>(phi_src, phi, lam, a, ops, coef, words, partials, blockIdx.x, gridDim.x);
 }
 
-// One block per CU (the tile fills the LDS), next tile prefetched into registers.
-template <typename T, bool TWO, int LR, bool GEN>
-__global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_tile_pf(const cx<T>* phi_src, cx<T>* phi, cx<T>* __restrict__ lam,
+// Warp-specialised form of a group-only pass (every top-level op is a
+// register group, so each op costs exactly one barrier): 512 threads, waves
+// 0-3 compute, waves 4-7 load, with two tile buffers in LDS.  While the
+// compute waves run tile i from one buffer, the load waves fetch tile i+1
+// (global -> registers -> LDS) into the other; both sides execute the same
+// barriers (one per group, one per tile), so HBM reads overlap the groups
+// and neither side waits for the other except at the tile boundary.  The
+// compute waves write tile i back at its end (stores do not block).
+// LDS: buffer 0, buffer 1 (phi, then lambda when TWO), then the reduction
+// area, slot accumulators and phase tables as in tile_body.
+template <typename T, bool TWO, int LR>
+__device__ __forceinline__ void tile_body_ws(const cx<T>* phi_src, cx<T>* phi, cx<T>* __restrict__ lam,
+                                             const TileArgs& a, const TOp* __restrict__ ops,
+                                             const cx<T>* __restrict__ coef, const uint64_t* __restrict__ words,
+                                             double* __restrict__ partials, uint64_t blk, uint64_t nblk) {
+    constexpr int R = 1 << LR;
+    constexpr int NT = 256;  // compute threads (and load threads)
+    constexpr int TSZ = NT * R;
+    constexpr size_t VB = (size_t)(TWO ? 2 : 1) * TSZ * sizeof(cx<T>);  // one buffer
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x;
+    const bool loader = tid >= NT;
+    const int lt = tid & (NT - 1);
+    const uint32_t stid = sw((uint32_t)lt);
+    cx<T>* buf0 = reinterpret_cast<cx<T>*>(smem);
+    cx<T>* buf1 = reinterpret_cast<cx<T>*>(smem + VB);
+    TileCtx<T, TWO, R> c;
+    c.red = reinterpret_cast<double*>(smem + 2 * VB);
+    c.sacc = c.red + 64;
+    c.coef = coef;
+    c.words = words;
+    c.offhi = a.offhi;
+    c.n_outer = a.n_outer;
+    c.tid = lt;
+    c.nthr = NT;
+    c.nwaves = NT >> 6;
+    c.nacc = NT >> 4;
+    {
+        const size_t off = (64 + (size_t)a.nslots * c.nacc) * sizeof(double);
+        cx<T>* zt = reinterpret_cast<cx<T>*>(reinterpret_cast<unsigned char*>(c.red) + ((off + 15) & ~(size_t)15));
+        for (int i = tid; i < a.zt_n; i += 2 * NT) zt[i] = coef[a.zt_off + i];
+        c.ztab = zt;
+    }
+    uint64_t offlo = 0;
+    for (int j = 0; j < 8; ++j) offlo |= (uint64_t)((lt >> j) & 1) << a.sb[j];
+    c.offlo = offlo;
+    for (int s = tid; s < a.nslots * c.nacc; s += 2 * NT) c.sacc[s] = 0.0;
+    const bool synth = (a.flags & TILE_SYNTH) != 0;
+
+    if (loader) {
+        if (blk < a.n_tiles) tile_to_lds<T, TWO, R>(buf0, stid, phi_src, lam, a, offlo, blk, synth);
+        __syncthreads();
+        int cur = 0;
+        for (uint64_t tile = blk; tile < a.n_tiles; tile += nblk) {
+            const bool more = tile + nblk < a.n_tiles;
+            // phi then (TWO) lambda values of the next tile, one array so that
+            // all of them stay in registers
+            constexpr int NV = (TWO ? 2 : 1) * R;
+            cx<T> v[NV];
+            const uint64_t nbase = expand_idx(more ? tile + nblk : tile, a.outer) | offlo;
+            if (more) {
+#pragma unroll
+                for (int q = 0; q < NV; ++q) {
+                    const uint64_t g = nbase | a.offhi[q % R];
+                    if (q >= R) {
+                        v[q] = lam[g];
+                    } else if (synth) {
+                        v[q].re = g == a.basis ? T(1) : T(0);
+                        v[q].im = T(0);
+                    } else {
+                        v[q] = phi_src[g];
+                    }
+                }
+            }
+            // the compute side's barriers: one per group
+            for (int oi = 0; oi < a.nops; ++oi) {
+                oi += ops[a.op0 + oi].m;
+                __syncthreads();
+            }
+            if (more) {
+                cx<T>* nb = cur ? buf0 : buf1;
+#pragma unroll
+                for (int q = 0; q < NV; ++q) nb[(q >= R ? TSZ : 0) + stid + (q % R) * NT] = v[q];
+            }
+            __syncthreads();
+            cur ^= 1;
+        }
+    } else {
+        __syncthreads();
+        int cur = 0;
+        const bool nt = (a.flags & TILE_NT) != 0;
+        for (uint64_t tile = blk; tile < a.n_tiles; tile += nblk) {
+            const uint64_t base = expand_idx(tile, a.outer);
+            c.base = base;
+            c.tile = tile;
+            c.tp = cur ? buf1 : buf0;
+            c.tl = c.tp + (TWO ? TSZ : 0);
+            for (int oi = 0; oi < a.nops; ++oi) {
+                const TOp& op = ops[a.op0 + oi];
+                tile_group<T, TWO, R, TWO ? GROUP_BITS_TWO : GROUP_BITS_ONE>(c, op, ops + a.op0 + oi + 1, a.b);
+                oi += op.m;
+                __syncthreads();
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint64_t g = base | offlo | a.offhi[r];
+                st_amp(phi + g, c.tp[stid + r * NT], nt);
+                if (TWO) st_amp(lam + g, c.tl[stid + r * NT], nt);
+            }
+            __syncthreads();
+            cur ^= 1;
+        }
+    }
+    __syncthreads();
+    if (!loader)
+        for (int s = lt; s < a.nslots; s += NT) {
+            double v = 0.0;
+            for (int w = 0; w < c.nacc; ++w) v += c.sacc[s * c.nacc + w];
+            partials[(uint64_t)s * nblk + blk] = v;
+        }
+}
+
+template <typename T, bool TWO, int LR>
+__global__ __launch_bounds__(512, 1) void k_tile_ws(const cx<T>* phi_src, cx<T>* phi, cx<T>* __restrict__ lam,
                                                     const TileArgs a, const TOp* __restrict__ ops,
                                                     const cx<T>* __restrict__ coef,
                                                     const uint64_t* __restrict__ words,
                                                     double* __restrict__ partials) {
-    tile_body<T, TWO, LR, GEN, true>(phi_src, phi, lam, a, ops, coef, words, partials, blockIdx.x, gridDim.x);
+    tile_body_ws<T, TWO, LR>(phi_src, phi, lam, a, ops, coef, words, partials, blockIdx.x, gridDim.x);
 }
 
 // Batched passes: block b serves entry blk_entry[b] (one circuit's pass).
@@ -945,14 +1044,13 @@ template <typename T, bool TWO, int LR, bool GEN>
 static hipError_t launch_tile_lr(hipStream_t s, const void* phi_src, void* phi, void* lam, const TileArgs& a,
                                  const TOp* ops, const void* coef, const uint64_t* words, double* partials, int grid,
                                  int nthr, size_t lds) {
-    if constexpr (LR >= 3) {
-        if (tile_prefetch(lds, 1 << LR)) {
-            // one block fits per CU: the prefetching form (the host sized the
-            // grid to one persistent block per CU)
-            static std::atomic<uint64_t> pf_raised{0};
-            hipError_t e = allow_big_lds((const void*)k_tile_pf<T, TWO, LR, GEN>, pf_raised);
+    if constexpr (LR >= 3 && !GEN) {
+        if (a.flags & TILE_WS) {
+            // warp-specialised form (the host sized the grid and the LDS for it)
+            static std::atomic<uint64_t> ws_raised{0};
+            hipError_t e = allow_big_lds((const void*)k_tile_ws<T, TWO, LR>, ws_raised);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL((k_tile_pf<T, TWO, LR, GEN>), dim3(grid), dim3(nthr), lds, s, (const cx<T>*)phi_src,
+            hipLaunchKernelGGL((k_tile_ws<T, TWO, LR>), dim3(grid), dim3(512), lds, s, (const cx<T>*)phi_src,
                                (cx<T>*)phi, (cx<T>*)lam, a, ops, (const cx<T>*)coef, words, partials);
             return hipGetLastError();
         }

@@ -303,7 +303,7 @@ hipError_t launch_gatek(hipStream_t s, void* psi, uint64_t n_items, const Expand
 
 // ------------------------------------------------------------------ dense k-qubit matrices, LDS-staged
 
-// A dense 2^K x 2^K matrix (K = 3..6) on any K target bits.  A tile is the
+// A dense 2^K x 2^K matrix (K = 2..6) on any K target bits.  A tile is the
 // 2^(K+6) amplitudes that agree outside the targets and the six lowest index
 // bits that are neither targets nor controls (the lane bits): 64 tuples of
 // 2^K amplitudes.  Controls always lie outside the tile and are enumerated by
@@ -316,7 +316,10 @@ hipError_t launch_gatek(hipStream_t s, void* psi, uint64_t n_items, const Expand
 //           whichever bits are targets;
 //  compute: wave w takes rows [w R, (w+1) R), R = 2^(K-2), of every tuple,
 //           lane = tuple: each input read from LDS feeds R complex MACs, and
-//           the matrix entries are wave-uniform (scalar loads);
+//           the matrix entries are wave-uniform (scalar loads).  The host
+//           stores the matrix as (wave, column j, row) so that the entries a
+//           wave needs for one input are contiguous; rows are taken in steps
+//           of at most 8, which bounds the scalar registers one step holds;
 //  store:   outputs back to LDS, then coalesced stores.
 // FLOPs per amplitude 8 * 2^K: memory-bound up to K = 5 in complex128 and
 // FP64-ALU-bound at K = 6.
@@ -343,7 +346,8 @@ __global__ __launch_bounds__(256, 2) void k_dense(cx<T>* __restrict__ psi, const
             goff |= 1ull << a.sb[i];
             coff |= 1u << a.cb[i];
         }
-    const cx<T>* mrow = mat + (size_t)wave * RW * D;
+    constexpr int HS = RW < 8 ? RW : 8;  // rows per step
+    const cx<T>* mw = mat + (size_t)wave * D * RW;
     for (uint64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
         const uint64_t base = expand_idx(tile, a.outer) | a.setmask;
         cx<T> v[RL];
@@ -358,11 +362,15 @@ __global__ __launch_bounds__(256, 2) void k_dense(cx<T>* __restrict__ psi, const
         cx<T> acc[RW];
 #pragma unroll
         for (int q = 0; q < RW; ++q) acc[q] = {T(0), T(0)};
-#pragma unroll 4
-        for (int j = 0; j < D; ++j) {
-            const cx<T> x = lds[(j << 6) + lane + j];
 #pragma unroll
-            for (int q = 0; q < RW; ++q) acc[q] = cmad(mrow[q * D + j], x, acc[q]);
+        for (int h = 0; h < RW; h += HS) {
+#pragma unroll 2
+            for (int j = 0; j < D; ++j) {
+                const cx<T> x = lds[(j << 6) + lane + j];
+                const cx<T>* mj = mw + (size_t)j * RW + h;
+#pragma unroll
+                for (int q = 0; q < HS; ++q) acc[h + q] = cmad(mj[q], x, acc[h + q]);
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -400,6 +408,7 @@ hipError_t launch_dense(hipStream_t s, void* psi, const DenseArgs& a, const void
     }                                                                                                     \
     break;
     switch (a.k) {
+    case 2: QSV_DN(2)
     case 3: QSV_DN(3)
     case 4: QSV_DN(4)
     case 5: QSV_DN(5)
@@ -446,12 +455,129 @@ hipError_t launch_tile_batch(hipStream_t s, bool two, bool generic, const TileEn
 // (P psi)_i = i^{nY} (-1)^{popcount((i ^ x) & z)} psi_{i ^ x}; terms sharing
 // an x mask share the load of psi_{i ^ x}.  Accumulation in FP64.
 //
-// Groups flagged with a table slot (at most two per launch, chosen by the
+// Groups flagged with a table slot (at most two per observable, chosen by the
 // host for many-term groups) skip the term loop: the parity vector of the
 // source index s = i ^ x is linear over GF(2) in s, so for the grid-stride
 // index i = base0 + it * stride it is (the thread's constant part) XOR (the
 // iteration's uniform part), each an XOR of per-bit columns; the group's
 // weight is then the sum of one 256-entry table lookup per byte of it.
+
+// Table state of one block: LDS offsets, parity columns and the thread's
+// constant parity part of (up to) two table groups.
+struct LutState {
+    int nslot;
+    int toff[2];
+    const uint64_t* cols[2];
+    uint64_t pthr[2];
+};
+
+// Copy the observable's byte tables into LDS and set up the parity parts for
+// the block's first index base0 (every thread must call it; ends with a
+// barrier).
+__device__ __forceinline__ void lut_setup(LutState& L, const PauliGroupDev* __restrict__ groups, int n_groups,
+                                          const uint64_t* __restrict__ aux, cx<double>* tabs, uint64_t base0) {
+    L.nslot = 0;
+    L.toff[0] = L.toff[1] = 0;
+    L.cols[0] = L.cols[1] = nullptr;
+    L.pthr[0] = L.pthr[1] = 0;
+    int tot = 0;
+    for (int g = 0; g < n_groups; ++g) {
+        const PauliGroupDev gr = groups[g];
+        if (gr.lut < 0) continue;
+        const cx<double>* src = reinterpret_cast<const cx<double>*>(aux + gr.lut_off);
+        for (int e = threadIdx.x; e < gr.nb * 256; e += blockDim.x) tabs[tot * 256 + e] = src[e];
+        const uint64_t* cl = aux + gr.col_off;
+        uint64_t p = 0;
+        const uint64_t s0 = base0 ^ gr.x;  // the source index without the iteration's bits
+        for (int k = 0; k < 64; ++k)
+            if ((s0 >> k) & 1) p ^= cl[k];
+        const int sl = gr.lut & 1;
+        L.toff[sl] = tot * 256;
+        L.cols[sl] = cl;
+        L.pthr[sl] = p;
+        tot += gr.nb;
+        ++L.nslot;
+    }
+    __syncthreads();
+}
+
+// Weight sum_t w_t (-1)^{parity(src & z_t)} of one group at source index src
+// (it_par: the iteration's parity parts of the table groups).
+template <typename T>
+__device__ __forceinline__ void group_weight(const PauliGroupDev& gr, uint64_t src,
+                                             const PauliTermDev* __restrict__ terms, const LutState& L,
+                                             const cx<double>* tabs, const uint64_t* it_par, double& sr,
+                                             double& si) {
+    sr = 0.0;
+    si = 0.0;
+    if (gr.lut >= 0) {
+        const int sl = gr.lut & 1;
+        const uint64_t p = L.pthr[sl] ^ it_par[sl];
+        const cx<double>* tb = tabs + L.toff[sl];
+        for (int b = 0; b < gr.nb; ++b) {
+            const cx<double> e = tb[b * 256 + (int)((p >> (8 * b)) & 255)];
+            sr += e.re;
+            si += e.im;
+        }
+    } else {
+        for (int t = gr.t0; t < gr.t0 + gr.nt; ++t) {
+            const PauliTermDev tm = terms[t];
+            const bool neg = __popcll(src & tm.z) & 1;
+            sr += neg ? -tm.wre : tm.wre;
+            si += neg ? -tm.wim : tm.wim;
+        }
+    }
+}
+
+// (H psi)_i accumulated over the observable's groups.  The gathers psi[i ^ x]
+// of four groups are issued before any of them is used, so their latencies
+// overlap (observables of many single-term groups are gather-latency bound).
+template <typename T>
+__device__ __forceinline__ void pauli_row(const cx<T>* __restrict__ psi, uint64_t i, cx<T> pi,
+                                          const PauliGroupDev* __restrict__ groups, int n_groups,
+                                          const PauliTermDev* __restrict__ terms, const LutState& L,
+                                          const cx<double>* tabs, const uint64_t* it_par, double& ar, double& ai) {
+    ar = 0.0;
+    ai = 0.0;
+    constexpr int U = 4;
+    int g = 0;
+    for (; g + U <= n_groups; g += U) {
+        cx<T> ps[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t x = groups[g + u].x;
+            ps[u] = x ? psi[i ^ x] : pi;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const PauliGroupDev gr = groups[g + u];
+            double sr, si;
+            group_weight<T>(gr, i ^ gr.x, terms, L, tabs, it_par, sr, si);
+            ar += sr * (double)ps[u].re - si * (double)ps[u].im;
+            ai += sr * (double)ps[u].im + si * (double)ps[u].re;
+        }
+    }
+    for (; g < n_groups; ++g) {
+        const PauliGroupDev gr = groups[g];
+        const cx<T> ps = gr.x ? psi[i ^ gr.x] : pi;
+        double sr, si;
+        group_weight<T>(gr, i ^ gr.x, terms, L, tabs, it_par, sr, si);
+        ar += sr * (double)ps.re - si * (double)ps.im;
+        ai += sr * (double)ps.im + si * (double)ps.re;
+    }
+}
+
+// the iteration's uniform parity parts: columns of the iteration's bits
+__device__ __forceinline__ void lut_iter(const LutState& L, uint64_t it, int lstride, uint64_t* it_par) {
+    it_par[0] = it_par[1] = 0;
+    for (int sl = 0; sl < 2; ++sl) {
+        if (!L.cols[sl]) continue;
+        uint64_t p = 0;
+        for (uint64_t r = it; r; r &= r - 1) p ^= L.cols[sl][lstride + __ffsll((unsigned long long)r) - 1];
+        it_par[sl] = p;
+    }
+}
+
 template <typename T, bool WRITE, bool NORM2>
 __global__ __launch_bounds__(256) void k_pauli(const cx<T>* __restrict__ psi, cx<T>* __restrict__ lam, uint64_t N,
                                                const PauliGroupDev* __restrict__ groups, int n_groups,
@@ -463,64 +589,16 @@ __global__ __launch_bounds__(256) void k_pauli(const cx<T>* __restrict__ psi, cx
     const uint64_t base0 = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * 256;  // a power of two
     const int lstride = __ffsll((unsigned long long)stride) - 1;
-    // table slots: LDS offset, columns, thread-constant parity part
-    int toff[2] = {0, 0};
-    const uint64_t* cols[2] = {nullptr, nullptr};
-    uint64_t pthr[2] = {0, 0};
-    int nslot = 0, tot_tabs = 0;
-    for (int g = 0; g < n_groups; ++g) {
-        const PauliGroupDev gr = groups[g];
-        if (gr.lut < 0) continue;
-        const cx<double>* src = reinterpret_cast<const cx<double>*>(aux + gr.lut_off);
-        for (int e = threadIdx.x; e < gr.nb * 256; e += 256) tabs[tot_tabs * 256 + e] = src[e];
-        const uint64_t* cl = aux + gr.col_off;
-        uint64_t p = 0;
-        const uint64_t s0 = base0 ^ gr.x;  // the source index without the iteration's bits
-        for (int k = 0; k < 64; ++k)
-            if ((s0 >> k) & 1) p ^= cl[k];
-        if (gr.lut == 0) { toff[0] = tot_tabs * 256; cols[0] = cl; pthr[0] = p; }
-        else { toff[1] = tot_tabs * 256; cols[1] = cl; pthr[1] = p; }
-        tot_tabs += gr.nb;
-        ++nslot;
-    }
-    __syncthreads();
+    LutState L;
+    lut_setup(L, groups, n_groups, aux, tabs, base0);
     double dot = 0.0, nrm = 0.0;
     uint64_t it = 0;
     for (uint64_t i = base0; i < N; i += stride, ++it) {
-        // uniform part of the parity vectors: columns of the iteration's bits
-        uint64_t pit[2] = {0, 0};
-        for (int sl = 0; sl < nslot; ++sl) {
-            uint64_t p = 0;
-            for (uint64_t r = it; r; r &= r - 1) p ^= cols[sl][lstride + __ffsll((unsigned long long)r) - 1];
-            pit[sl] = p;
-        }
+        uint64_t it_par[2];
+        lut_iter(L, it, lstride, it_par);
         const cx<T> pi = psi[i];
-        double ar = 0.0, ai = 0.0;
-        for (int g = 0; g < n_groups; ++g) {
-            const PauliGroupDev gr = groups[g];
-            const uint64_t src = i ^ gr.x;
-            const cx<T> ps = gr.x ? psi[src] : pi;
-            double sr = 0.0, si = 0.0;
-            if (gr.lut >= 0) {
-                const int sl = gr.lut;
-                const uint64_t p = (sl ? pthr[1] ^ pit[1] : pthr[0] ^ pit[0]);
-                const cx<double>* tb = tabs + (sl ? toff[1] : toff[0]);
-                for (int b = 0; b < gr.nb; ++b) {
-                    const cx<double> e = tb[b * 256 + (int)((p >> (8 * b)) & 255)];
-                    sr += e.re;
-                    si += e.im;
-                }
-            } else {
-                for (int t = gr.t0; t < gr.t0 + gr.nt; ++t) {
-                    const PauliTermDev tm = terms[t];
-                    const bool neg = __popcll(src & tm.z) & 1;
-                    sr += neg ? -tm.wre : tm.wre;
-                    si += neg ? -tm.wim : tm.wim;
-                }
-            }
-            ar += sr * (double)ps.re - si * (double)ps.im;
-            ai += sr * (double)ps.im + si * (double)ps.re;
-        }
+        double ar, ai;
+        pauli_row<T>(psi, i, pi, groups, n_groups, terms, L, tabs, it_par, ar, ai);
         if (WRITE) lam[i] = cx<T>{(T)ar, (T)ai};
         dot += (double)pi.re * ar + (double)pi.im * ai;
         if (NORM2) nrm += ar * ar + ai * ai;
@@ -558,37 +636,36 @@ hipError_t launch_pauli(hipStream_t s, bool write_lambda, bool norm2, const void
     return hipGetLastError();
 }
 
-// Batched Pauli sums: block b serves entry blk_entry[b] (one circuit).
+// Batched Pauli sums: block b serves entry blk_entry[b] (one circuit), with
+// that circuit's byte tables (if any) in LDS.
 template <typename T, bool WRITE>
 __global__ __launch_bounds__(256) void k_pauli_batch(const PauliEntry* __restrict__ entries,
                                                      const int32_t* __restrict__ blk_entry,
                                                      const PauliGroupDev* __restrict__ groups,
                                                      const PauliTermDev* __restrict__ terms,
+                                                     const uint64_t* __restrict__ aux,
                                                      double* __restrict__ partials) {
     __shared__ double red[64];
+    extern __shared__ __align__(16) unsigned char pauli_smem[];
+    cx<double>* tabs = reinterpret_cast<cx<double>*>(pauli_smem);
     const PauliEntry& en = entries[blk_entry[blockIdx.x]];
     const cx<T>* __restrict__ psi = (const cx<T>*)en.psi;
     cx<T>* __restrict__ lam = (cx<T>*)en.lam;
     const uint64_t blk = blockIdx.x - en.blk0;
+    const PauliGroupDev* gp = groups + en.g0;
+    const uint64_t base0 = blk * 256 + threadIdx.x;
+    const uint64_t stride = (uint64_t)en.nblk * 256;  // a power of two
+    const int lstride = __ffsll((unsigned long long)stride) - 1;
+    LutState L;
+    lut_setup(L, gp, en.ng, aux, tabs, base0);
     double dot = 0.0;
-    const uint64_t stride = (uint64_t)en.nblk * 256;
-    for (uint64_t i = blk * 256 + threadIdx.x; i < en.N; i += stride) {
+    uint64_t it = 0;
+    for (uint64_t i = base0; i < en.N; i += stride, ++it) {
+        uint64_t it_par[2];
+        lut_iter(L, it, lstride, it_par);
         const cx<T> pi = psi[i];
-        double ar = 0.0, ai = 0.0;
-        for (int g = en.g0; g < en.g0 + en.ng; ++g) {
-            const PauliGroupDev gr = groups[g];
-            const uint64_t src = i ^ gr.x;
-            const cx<T> ps = gr.x ? psi[src] : pi;
-            double sr = 0.0, si = 0.0;
-            for (int t = gr.t0; t < gr.t0 + gr.nt; ++t) {
-                const PauliTermDev tm = terms[t];
-                const bool neg = __popcll(src & tm.z) & 1;
-                sr += neg ? -tm.wre : tm.wre;
-                si += neg ? -tm.wim : tm.wim;
-            }
-            ar += sr * (double)ps.re - si * (double)ps.im;
-            ai += sr * (double)ps.im + si * (double)ps.re;
-        }
+        double ar, ai;
+        pauli_row<T>(psi, i, pi, gp, en.ng, terms, L, tabs, it_par, ar, ai);
         if (WRITE) lam[i] = cx<T>{(T)ar, (T)ai};
         dot += (double)pi.re * ar + (double)pi.im * ai;
     }
@@ -599,13 +676,15 @@ __global__ __launch_bounds__(256) void k_pauli_batch(const PauliEntry* __restric
 
 template <typename T>
 hipError_t launch_pauli_batch(hipStream_t s, bool write_lambda, const PauliEntry* entries, const int32_t* blk_entry,
-                              const PauliGroupDev* groups, const PauliTermDev* terms, double* partials, int blocks) {
+                              const PauliGroupDev* groups, const PauliTermDev* terms, const uint64_t* aux,
+                              int lut_tables, double* partials, int blocks) {
+    const size_t lds = (size_t)lut_tables * 256 * sizeof(cx<double>);
     if (write_lambda)
-        hipLaunchKernelGGL((k_pauli_batch<T, true>), dim3(blocks), dim3(256), 0, s, entries, blk_entry, groups, terms,
-                           partials);
+        hipLaunchKernelGGL((k_pauli_batch<T, true>), dim3(blocks), dim3(256), lds, s, entries, blk_entry, groups,
+                           terms, aux, partials);
     else
-        hipLaunchKernelGGL((k_pauli_batch<T, false>), dim3(blocks), dim3(256), 0, s, entries, blk_entry, groups,
-                           terms, partials);
+        hipLaunchKernelGGL((k_pauli_batch<T, false>), dim3(blocks), dim3(256), lds, s, entries, blk_entry, groups,
+                           terms, aux, partials);
     return hipGetLastError();
 }
 
@@ -783,6 +862,19 @@ hipError_t launch_sparse(hipStream_t s, const void* psi, uint64_t N, const int64
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ allocation-free scratch
+
+// Device scratch of the allocation-free entry point (qsv_expval_noalloc): its
+// Pauli tables, per-block partials and results live here instead of in
+// buffers the library allocates.  Every device that loads the library holds
+// its own copy until the process ends; calls that overlap on one device share
+// it (and race).  Host code never names the array: it uses the address
+// returned below, taken once per device.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+// The scratch's address on the current device (the caller keeps it per device).
+hipError_t noalloc_scratch_address(void** ptr) { return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch)); }
+
 // ------------------------------------------------------------------ deterministic reduction
 
 __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ partials, int n_blocks,
@@ -846,7 +938,8 @@ hipError_t launch_reduce(hipStream_t s, const double* partials, int n_blocks, in
                                              const TileArgs*, const TOp*, const void*, const uint64_t*, double*, \
                                              int, int, int, size_t);                                            \
     template hipError_t launch_pauli_batch<T>(hipStream_t, bool, const PauliEntry*, const int32_t*,             \
-                                              const PauliGroupDev*, const PauliTermDev*, double*, int);         \
+                                              const PauliGroupDev*, const PauliTermDev*, const uint64_t*, int,  \
+                                              double*, int);                                                    \
     template hipError_t launch_sparse<T>(hipStream_t, const void*, uint64_t, const int64_t*, const int64_t*,    \
                                          const double*, double*, int);                                          \
     template hipError_t launch_chunk_norms<T>(hipStream_t, const void*, int, uint64_t, double*);              \

@@ -92,6 +92,7 @@ struct TileArgs {
 };
 constexpr int32_t TILE_SYNTH = 1;
 constexpr int32_t TILE_NT = 2;  // write back with non-temporal stores
+constexpr int32_t TILE_WS = 4;  // warp-specialised kernel form (two tile buffers, 512 threads)
 
 // A dense k-qubit matrix on a tile of 2^(k+6) amplitudes: the k targets and
 // six lane bits (the lowest index bits that are neither targets nor
@@ -199,7 +200,8 @@ template <typename T> hipError_t launch_tile_batch(hipStream_t s, bool two, bool
                                                    int blocks, int nthr, int R, size_t lds_bytes);
 template <typename T> hipError_t launch_pauli_batch(hipStream_t s, bool write_lambda, const PauliEntry* entries,
                                                     const int32_t* blk_entry, const PauliGroupDev* groups,
-                                                    const PauliTermDev* terms, double* partials, int blocks);
+                                                    const PauliTermDev* terms, const uint64_t* aux, int lut_tables,
+                                                    double* partials, int blocks);
 hipError_t launch_reduce_batch(hipStream_t s, const ReduceEntry* re, int n, const double* partials, double* out);
 template <typename T> hipError_t launch_pauli(hipStream_t s, bool write_lambda, bool norm2, const void* psi,
                                               void* lam, uint64_t N, const PauliGroupDev* groups, int n_groups,
@@ -214,6 +216,11 @@ template <typename T> hipError_t launch_sample(hipStream_t s, const void* psi, i
 template <typename T> hipError_t launch_probs(hipStream_t s, const void* psi, uint64_t n_rest, const Expand& ex,
                                               const uint64_t* binbits, int n_bins, int gx, double* partials);
 hipError_t launch_reduce(hipStream_t s, const double* partials, int n_blocks, int n_slots, double* out);
+
+// Scratch of the allocation-free entry point: a static device array of this
+// size in kernels.hip; its device address is taken once per device.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)8 << 20;
+hipError_t noalloc_scratch_address(void** ptr);
 
 int tile_lds_bytes(int b, bool two, int elem_bytes, int nslots, int zt_n);
 int pauli_grid(uint64_t N);
@@ -273,6 +280,7 @@ struct PlanOptions {
     bool fusion = true;
     bool layers = true;  // one-qubit runs inside register groups as LAYER1 sub-ops
     int max_scan = 2048; // look-ahead window of the greedy planner
+    bool ws = false;     // warp-specialised tile passes where they fit (TILE_WS)
     // LDS a tile pass may spend beyond its tile: each inner product holds a
     // slot accumulator (slot_bytes), each Z-parity rotation at most two
     // phase-table entries (ztab_bytes); a pass closes before exceeding it
@@ -280,11 +288,10 @@ struct PlanOptions {
 };
 
 constexpr int LDS_PER_CU = 160 * 1024;
-// A tile pass whose LDS admits one block per CU runs the prefetching kernel
-// form (next tile held in registers) as one persistent block per CU of the
-// MI355X (256 CUs).
-constexpr int TILE_PF_GRID = 256;
-inline bool tile_prefetch(size_t lds, int R) { return lds > (size_t)LDS_PER_CU / 2 && R >= 8; }
+// Group-only tile passes of >= 2048 amplitudes run warp-specialised (load
+// waves fill a second tile buffer while compute waves run the first) when
+// both buffers fit the CU's LDS: one persistent block per CU of the MI355X.
+constexpr int TILE_WS_GRID = 256;
 
 std::vector<Pass> plan_passes(const std::vector<Item>& items, int n, const PlanOptions& opt);
 Item make_item(const Factor& f, bool dot, int fidx, int n);

@@ -18,12 +18,16 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libqsv.so")
+# QSV_LIB_PATH: load another build of the library (the CPU suite's
+# sanitizer build); the default is the in-tree libqsv.so
+LIB_PATH = os.environ.get("QSV_LIB_PATH") or os.path.join(_HERE, "libqsv.so")
 
 C64, C128 = 1, 2
 MAX_QUBITS = 34
 ADJ_INPLACE = 1
 OPT_FUSION, OPT_TILE_BITS, OPT_TILE_BITS_ADJ, OPT_LOW_BITS, OPT_PROFILE, OPT_NONTEMPORAL, OPT_LAYERS = 1, 2, 3, 4, 5, 6, 7
+OPT_TEST_ALLOC_LIMIT, OPT_TEST_FAIL_LAUNCH = 8, 9   # fault injection (tests of the error paths)
+OPT_TILE_WS = 10
 
 GATE_IDS = {
     "PauliX": 1, "PauliY": 2, "PauliZ": 3, "Hadamard": 4, "S": 5, "T": 6, "SX": 7, "Identity": 8,
@@ -78,7 +82,7 @@ EXPORTS = [
     "qsv_kernel_name", "qsv_ctx_kernel_stats", "qsv_ctx_reset_stats", "qsv_state_create", "qsv_state_wrap",
     "qsv_state_destroy", "qsv_state_n_qubits", "qsv_state_device_ptr", "qsv_state_reset", "qsv_state_copy",
     "qsv_state_to_host", "qsv_state_from_host", "qsv_validate_ops", "qsv_validate_obs", "qsv_apply",
-    "qsv_expval", "qsv_adjoint_jacobian", "qsv_adjoint_vjp", "qsv_plan_stats", "qsv_plan_json", "qsv_var",
+    "qsv_expval", "qsv_expval_noalloc", "qsv_adjoint_jacobian", "qsv_adjoint_vjp", "qsv_plan_stats", "qsv_plan_json", "qsv_var",
     "qsv_probs", "qsv_expval_sparse", "qsv_batch_create", "qsv_batch_destroy", "qsv_batch_run", "qsv_sample",
     "qsv_autotune",
 ]
@@ -94,10 +98,11 @@ def lib():
     # PyTorch ships its own HIP runtime library; loading it first lets this
     # library bind to the same one, so that one runtime serves the process
     # (with two, whichever initialises second can find no devices)
-    try:
-        import torch  # noqa: F401
-    except ImportError:
-        pass
+    if not os.environ.get("QSV_LIB_PATH"):
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, u32, u64, dp = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64,
                                  ctypes.POINTER(ctypes.c_double))
@@ -122,6 +127,7 @@ def lib():
         "qsv_validate_ops": ([i32, opp, sz, sz, sz], i32), "qsv_validate_obs": ([i32, obp, sz], i32),
         "qsv_apply": ([vp, opp, sz, dp, sz, dp, sz], i32),
         "qsv_expval": ([vp, obp, sz, dp], i32),
+        "qsv_expval_noalloc": ([vp, obp, sz, dp], i32),
         "qsv_var": ([vp, obp, sz, dp], i32),
         "qsv_probs": ([vp, ctypes.POINTER(ctypes.c_int32), i32, dp], i32),
         "qsv_expval_sparse": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64), dp, i64, dp], i32),
@@ -416,6 +422,14 @@ def expval(state: State, observables, marshalled: Optional[MarshalledObs] = None
     mo = marshalled or MarshalledObs(observables)
     out = np.zeros(max(1, mo.n))
     _check(lib().qsv_expval(state.h, mo.arr, mo.n, _dptr(out)), state.ctx.h)
+    return out[: mo.n]
+
+
+def expval_noalloc(state: State, observables, marshalled: Optional[MarshalledObs] = None) -> np.ndarray:
+    """qsv_expval_noalloc: expval with no device allocation (static scratch)."""
+    mo = marshalled or MarshalledObs(observables)
+    out = np.zeros(max(1, mo.n))
+    _check(lib().qsv_expval_noalloc(state.h, mo.arr, mo.n, _dptr(out)), state.ctx.h)
     return out[: mo.n]
 
 

@@ -44,6 +44,7 @@ def reset_options(ctx):
     ctx.set_option(qsv.OPT_TILE_BITS, 0)
     ctx.set_option(qsv.OPT_TILE_BITS_ADJ, 0)
     ctx.set_option(qsv.OPT_LOW_BITS, 0)
+    ctx.set_option(qsv.OPT_TILE_WS, 0)
 
 
 def obs_scale(observables):

@@ -58,7 +58,9 @@ def _dense(prog, st, psi):
     D = 1 << k
     RW = D // 4
     RL = (64 << k) // 256
-    M = _coef(prog, st["coff"], D * D).reshape(D, D)
+    # the kernel's layout: (wave, column j, row q of the wave's RW rows)
+    Mt = _coef(prog, st["coff"], D * D).reshape(4, D, RW)
+    M = np.concatenate([Mt[w].T for w in range(4)], axis=0)
     sb, cb = st["sb"], st["cb"]
     lds_size = (64 << k) * 65 // 64
     for tile in range(st["n_tiles"]):

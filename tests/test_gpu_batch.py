@@ -93,3 +93,21 @@ def test_batch_rejects_bad_input(ctx):
     with pytest.raises(ValueError):
         b.run([np.zeros(c.n_params + 1)])
     b.close()
+
+
+@pytest.mark.parametrize("dt", [qsv.C128, qsv.C64])
+def test_batch_many_term_groups(ctx, dt):
+    """Batched circuits whose Hamiltonians have x-groups of many terms: the
+    batched Pauli kernel evaluates them through the per-circuit byte tables
+    (one circuit with two table groups, one with one, one with none)."""
+    from tests.test_gpu_pauli import _grouped_hamiltonian
+    cs = []
+    for n, sizes in ((10, (42, 30, 3)), (12, (16, 5)), (8, (7, 9, 2))):
+        c = W.random_circuit(n, 40, seed=n)
+        c.observables = [_grouped_hamiltonian(n, sizes, seed=n)]
+        cs.append(c)
+    b = qsv.Batch(ctx, cs, dt)
+    for graph in (False, True):
+        ev, grads = b.run([c.params for c in cs], grad=True, graph=graph)
+        _check(cs, [c.params for c in cs], ev, grads, dt)
+    b.close()

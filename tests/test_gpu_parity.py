@@ -70,6 +70,7 @@ TILE_OPTS = [
     {qsv.OPT_TILE_BITS: 5, qsv.OPT_LOW_BITS: 2},               # many small tiles, outer controls
     {qsv.OPT_TILE_BITS: 8, qsv.OPT_LOW_BITS: 3},               # R = 1
     {qsv.OPT_FUSION: 0},                                       # one kernel per gate
+    {qsv.OPT_TILE_WS: 1},                                      # warp-specialised tile passes
 ]
 
 
@@ -145,12 +146,12 @@ def test_expval_random_pauli_sums(ctx, n, dt):
 # ------------------------------------------------------------------ adjoint Jacobian
 
 @pytest.mark.parametrize("dt", DTYPES)
-@pytest.mark.parametrize("opt", range(3))
+@pytest.mark.parametrize("opt", range(4))
 @pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (4, 2), (7, 3), (10, 4), (13, 5)])
 def test_adjoint_random_circuits(ctx, n, seed, opt, dt):
     c = W.random_circuit(n, 50, seed=2000 + seed, n_params=11, p_ctrl=0.2, max_k=min(n, 4))
     obs = W.random_observables(n, np.random.default_rng(seed), n_obs=2, n_terms=4)
-    opts = [{}, {qsv.OPT_TILE_BITS_ADJ: 4, qsv.OPT_LOW_BITS: 2}, {qsv.OPT_FUSION: 0}][opt]
+    opts = [{}, {qsv.OPT_TILE_BITS_ADJ: 4, qsv.OPT_LOW_BITS: 2}, {qsv.OPT_FUSION: 0}, {qsv.OPT_TILE_WS: 1}][opt]
     for k, v in opts.items():
         ctx.set_option(k, v)
     st = qsv.State(ctx, n, dt)

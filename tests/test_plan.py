@@ -32,13 +32,15 @@ def test_small_register_is_one_tile():
         assert st["passes"] == 1
 
 
-@pytest.mark.parametrize("name,k,low", [("RX", 1, True), ("IsingXX", 2, True), ("QubitUnitary", 3, True),
+@pytest.mark.parametrize("name,k,low", [("RX", 1, True), ("IsingXX", 2, True), ("IsingXX", 2, False),
+                                        ("QubitUnitary", 3, True),
                                         ("QubitUnitary", 4, False), ("QubitUnitary", 5, False),
                                         ("QubitUnitary", 4, True), ("QubitUnitary", 5, True),
                                         ("QubitUnitary", 6, False), ("QubitUnitary", 6, True)])
 def test_single_gate_kernel_choice(name, k, low):
-    """One pass per single gate: the pair and quad kernels for k = 1, 2, the
-    LDS-staged dense kernel for k = 3..6 (on low or high bits)."""
+    """One pass per single gate: the pair kernel for k = 1, the quad kernel
+    for two-qubit gates away from the lowest two bits, the LDS-staged dense
+    kernel for two-qubit gates on them and for k = 3..6 (low or high bits)."""
     n = 20
     rng = np.random.default_rng(0)
     mat = W.random_unitary(k, rng) if name == "QubitUnitary" else None
@@ -48,7 +50,7 @@ def test_single_gate_kernel_choice(name, k, low):
     st = qsv.plan_stats(n, [o], [0.3])
     assert st["passes"] == 1 and st["tile_passes"] == 0
     kind = qsv.plan_json(n, [o], [0.3])["steps"][0]["type"]
-    assert kind == {1: "gate1", 2: "gate2"}.get(k, "dense")
+    assert kind == ("gate1" if k == 1 else "gate2" if k == 2 and not low else "dense")
 
 
 def test_non_commuting_gates_keep_order():
@@ -116,9 +118,15 @@ def test_tile_passes_fit_the_cu_lds(dt, tile_bits):
             assert sum(st["nslots"] for st in tiles) == len(params)
 
 
-def test_qaoa_lds_below_two_blocks_per_cu():
-    # the benchmark's passes keep two blocks per CU (<= 80 KiB each)
+TILE_WS = 4
+
+
+def test_qaoa_passes_fit_two_blocks_per_cu():
+    """The benchmark's tile passes are group-only, and their LDS keeps two
+    blocks per CU (<= 80 KiB each)."""
     c = W.config3(n=28)
     for adj in (False, True):
         prog = qsv.plan_json(28, c.ops, c.params, adjoint=adj)
-        assert max(st["lds"] for st in prog["steps"] if st["type"] == "tile") <= 80 * 1024
+        tiles = [st for st in prog["steps"] if st["type"] == "tile"]
+        assert all(not st["generic"] and not st["flags"] & TILE_WS for st in tiles)
+        assert max(st["lds"] for st in tiles) <= 80 * 1024
