@@ -85,7 +85,7 @@ def cpu_baseline(circ) -> dict:
             "fixed_s": round(fixed, 3), "block_s": round(block, 3), "per_term_s": round(per_term, 3)}
 
 
-def micro(n: int, reps: int = 5, dtype_name: str = "c128", nontemporal: bool = False):
+def micro(n: int, reps: int = 5, dtype_name: str = "c128", nontemporal: bool = False, dense_mfma: bool = False):
     """Per-kernel-class gate-apply bandwidth at n qubits: one JSON line per
     (gate, wires) case with the algorithmic GB/s of its kernel (HIP events on
     the launch stream) and the fraction of the 8 TB/s HBM peak."""
@@ -97,6 +97,7 @@ def micro(n: int, reps: int = 5, dtype_name: str = "c128", nontemporal: bool = F
     dev = torch.device("cuda", 0)
     ctx = qsv.Context(0, torch.cuda.current_stream(dev).cuda_stream)
     ctx.set_option(qsv.OPT_NONTEMPORAL, int(nontemporal))
+    ctx.set_option(qsv.OPT_DENSE_MFMA, int(dense_mfma))
     psi = torch.empty(1 << n, dtype=torch.complex128 if dt == qsv.C128 else torch.complex64, device=dev)
     st = qsv.State(ctx, n, dt, tensor=psi)
     st.reset(0)
@@ -144,6 +145,7 @@ def micro(n: int, reps: int = 5, dtype_name: str = "c128", nontemporal: bool = F
         kinds = {k: s["launches"] // reps for k, s in stats.items()}
         gbs = tot_b / 1e9 / (tot_ms / 1e3)
         print(json.dumps({"case": name, "n_qubits": n, "dtype": dtype_name, "nontemporal": nontemporal,
+                          "dense_mfma": dense_mfma,
                           "kernels": kinds,
                           "ms": round(tot_ms, 4), "alg_GB": round(tot_b / 1e9, 3), "GB_s": round(gbs, 1),
                           "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4)}), flush=True)
@@ -162,6 +164,111 @@ def micro(n: int, reps: int = 5, dtype_name: str = "c128", nontemporal: bool = F
     print(json.dumps({"case": "torch copy_ (reference)", "ms": round(ms, 4), "alg_GB": by / 1e9,
                       "GB_s": round(by / 1e9 / (ms / 1e3), 1), "frac_of_8TBs": round(by / 1e9 / (ms / 1e3) / 8000, 4)}),
           flush=True)
+
+
+def sweep_cases(n: int, rng, only_half_touch: bool = False):
+    """Gate cases of the per-wire sweep at n qubits: every target wire for the
+    one-qubit gates; for the two-qubit gates the pair (0, n-1), adjacent pairs
+    on low, middle and high wires and 16 random pairs; dense 3- to 5-qubit
+    unitaries on the lowest and highest wires.  only_half_touch: the gates that
+    touch half the amplitudes (PhaseShift, CZ, CNOT, SingleExcitation) with an
+    untouched or control bit among the three lowest index bits, whose cache
+    lines hold both touched and untouched amplitudes."""
+    from paper_2403_02512_amd import workloads as W
+    w = lambda bit: n - 1 - bit          # wire of an index bit
+    out = []
+    if only_half_touch:
+        for b in (0, 1, 2, 3, 8, n - 1):
+            out.append((f"PhaseShift bit{b}", "half", [W.op("PhaseShift", [w(b)], (-1, 0.3))]))
+        for c, t in ((0, 1), (0, n - 1), (n - 1, 0), (13, 14)):
+            out.append((f"CNOT ctrl{c} tgt{t}", "half", [W.op("CNOT", [w(c), w(t)])]))
+        for a, b in ((0, 1), (1, 2), (13, 14)):
+            out.append((f"CZ bits{a},{b}", "half", [W.op("CZ", [w(a), w(b)])]))
+            out.append((f"SingleExcitation bits{a},{b}", "half",
+                        [W.op("SingleExcitation", [w(a), w(b)], (-1, 0.3))]))
+        return out
+    for g in ("RX", "Hadamard", "RZ", "PhaseShift"):
+        for b in range(n):
+            par = () if g == "Hadamard" else ((-1, 0.3),)
+            out.append((f"{g} bit{b}", "1q", [W.op(g, [w(b)], *par)]))
+    pairs = [(0, n - 1), (0, 1), (1, 2), (n // 2 - 1, n // 2), (n - 2, n - 1)]
+    while len(pairs) < 21:
+        a, b = (int(x) for x in rng.choice(n, size=2, replace=False))
+        if (a, b) not in pairs:
+            pairs.append((a, b))
+    for g in ("CNOT", "CZ", "IsingZZ", "IsingXX", "SingleExcitation"):
+        par = () if g in ("CNOT", "CZ") else ((-1, 0.3),)
+        for a, b in pairs:
+            out.append((f"{g} bits{a},{b}", "2q", [W.op(g, [w(a), w(b)], *par)]))
+    for k in (3, 4, 5):
+        for lo in (True, False):
+            bits = list(range(k)) if lo else list(range(n - k, n))
+            out.append((f"QubitUnitary k={k} {'low' if lo else 'high'} bits", "dense",
+                        [W.op("QubitUnitary", [w(b) for b in bits], matrix=W.random_unitary(k, rng))]))
+    return out
+
+
+def sweep(n: int, dtype_name: str = "c128", reps: int = 3, only_half_touch: bool = False, markers: bool = False):
+    """Per-wire gate sweep at n qubits on a random normalised state (seed 0):
+    one JSON line per case with its kernel class, the algorithmic bytes and
+    GB/s of its launch (HIP events on the launch stream, mean of reps after
+    one warm-up) and the fraction of the 8 TB/s HBM peak; then one summary
+    line per gate class.  markers: a small torch fill kernel runs before each
+    case's timed launches, so that a counter profile's dispatches can be split
+    per case."""
+    import torch
+    from paper_2403_02512_amd import qsv
+
+    dt = qsv.C128 if dtype_name == "c128" else qsv.C64
+    dev = torch.device("cuda", 0)
+    ctx = qsv.Context(0, torch.cuda.current_stream(dev).cuda_stream)
+    cdt = torch.complex128 if dt == qsv.C128 else torch.complex64
+    psi = torch.empty(1 << n, dtype=cdt, device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(0)
+    torch.view_as_real(psi).normal_(generator=g)
+    psi.div_(torch.linalg.vector_norm(psi))
+    st = qsv.State(ctx, n, dt, tensor=psi)
+    marker = torch.zeros(64, device=dev)
+    if markers:
+        # a plain copy of the state: its counter readings calibrate the
+        # counters against known bytes
+        cal = torch.empty_like(psi)
+        cal.copy_(psi)
+        torch.cuda.synchronize()
+        del cal
+    rng = np.random.default_rng(0)
+    rows = []
+    for ci, (name, cls, ops) in enumerate(sweep_cases(n, rng, only_half_touch)):
+        m = qsv.MarshalledOps(ops, np.zeros(0))
+        qsv.apply(st, ops, None, marshalled=m)   # warm-up (planning, first launch)
+        torch.cuda.synchronize()
+        if markers:
+            marker.fill_(float(ci))
+        ctx.set_option(qsv.OPT_PROFILE, 1)
+        ctx.reset_stats()
+        for _ in range(reps):
+            qsv.apply(st, ops, None, marshalled=m)
+        stats = ctx.kernel_stats()
+        ctx.set_option(qsv.OPT_PROFILE, 0)
+        tot_ms = sum(s["ms"] for s in stats.values()) / reps
+        tot_b = sum(s["bytes"] for s in stats.values()) / reps
+        gbs = tot_b / 1e9 / (tot_ms / 1e3)
+        row = {"case": name, "class": cls, "n_qubits": n, "dtype": dtype_name,
+               "kernels": {k: s["launches"] // reps for k, s in stats.items()},
+               "ms": round(tot_ms, 4), "alg_GB": round(tot_b / 1e9, 3), "GB_s": round(gbs, 1),
+               "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4)}
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+    torch.cuda.synchronize()
+    gates = {}
+    for r in rows:
+        gates.setdefault(r["case"].split(" ")[0], []).append(r["frac_of_8TBs"])
+    for gname, fr in gates.items():
+        fr = sorted(fr)
+        print(json.dumps({"summary": gname, "n_qubits": n, "dtype": dtype_name, "cases": len(fr),
+                          "frac_min": fr[0], "frac_median": fr[len(fr) // 2], "frac_max": fr[-1]}), flush=True)
+    st.close()
 
 
 def micro_tile(n: int, reps: int = 5, only: str = "", layer_modes=(1, 0)):
@@ -323,11 +430,19 @@ def main():
     ap.add_argument("--micro", action="store_true", help="per-kernel-class gate-apply bandwidth sweep")
     ap.add_argument("--micro-dtype", default="c128", choices=["c128", "c64"])
     ap.add_argument("--nt", action="store_true", help="micro: non-temporal stores (QSV_OPT_NONTEMPORAL)")
+    ap.add_argument("--dense-mfma", action="store_true", help="micro: 6-qubit unitaries on FP64 MFMA")
     ap.add_argument("--batch", action="store_true",
                     help="batched VQE sweep (512 circuits, 12-22 qubits): per-circuit loop vs batched launches "
                          "vs captured graph, circuits/s and gradients/s")
     ap.add_argument("--batch-circuits", type=int, default=512)
     ap.add_argument("--micro-tile", action="store_true", help="tile-pass cost structure sweep")
+    ap.add_argument("--sweep", action="store_true",
+                    help="per-wire gate sweep at --n qubits, --micro-dtype precision (one line per case)")
+    ap.add_argument("--sweep-half-touch", action="store_true",
+                    help="sweep: only the half-touch gates with low untouched/control bits")
+    ap.add_argument("--sweep-markers", action="store_true",
+                    help="sweep: a marker kernel before each case (splits counter profiles per case)")
+    ap.add_argument("--sweep-reps", type=int, default=3)
     ap.add_argument("--micro-case", default="", help="run only this micro-tile case (layers on)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy one state-sized buffer device to device (the reference kernel that "
@@ -345,7 +460,11 @@ def main():
         micro_tile(args.n, only=args.micro_case, layer_modes=(1,) if args.micro_case else (1, 0))
         return
     if args.micro:
-        micro(args.n, dtype_name=args.micro_dtype, nontemporal=args.nt)
+        micro(args.n, dtype_name=args.micro_dtype, nontemporal=args.nt, dense_mfma=args.dense_mfma)
+        return
+    if args.sweep:
+        sweep(args.n, dtype_name=args.micro_dtype, reps=args.sweep_reps, only_half_touch=args.sweep_half_touch,
+              markers=args.sweep_markers)
         return
 
     import torch

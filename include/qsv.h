@@ -131,6 +131,8 @@ enum {
                                    warp-specialised where two tile buffers fit the LDS (load
                                    waves fetch the next tile while compute waves run this
                                    one); 0 (default): one buffer per block, two blocks per CU */
+    QSV_OPT_DENSE_MFMA = 11,    /* 1: 6-qubit dense matrices on complex128 states run on the
+                                   FP64 matrix cores (16x16x4 MFMA); 0 (default): FP64 FMA   */
     /* Fault injection, for tests of the error paths only:                                     */
     QSV_OPT_TEST_ALLOC_LIMIT = 8, /* >0: a device allocation above this many bytes fails with
                                      QSV_ERR_OOM, as if the device were full; 0: no limit    */

@@ -3,6 +3,7 @@
 // Jacobian (paper Sec. 2.1-2.2; the adjoint method of Jones & Gacon cited in
 // Sec. 2.1 and Sec. 3.1.1).
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <atomic>
 #include <exception>
@@ -48,7 +49,7 @@ struct qsv_ctx {
     bool own_stream = false;
     std::string err;
     int64_t opt_fusion = 1, opt_tile_bits = 0, opt_tile_bits_adj = 0, opt_low_bits = 0, opt_profile = 0,
-            opt_nontemporal = 0, opt_layers = 1, opt_tile_ws = 0;
+            opt_nontemporal = 0, opt_layers = 1, opt_tile_ws = 0, opt_dense_mfma = 0;
     void* scratch = nullptr;  // this device's allocation-free scratch (qsv_expval_noalloc)
     // fault injection for tests of the error paths (QSV_OPT_TEST_*)
     int64_t test_alloc_limit = 0, test_fail_launch = 0;
@@ -885,10 +886,7 @@ bool lower_single(Program& P, const Factor& f, int n, size_t eb, int low_bits) {
             }
             st.bytes = 2.0 * N * eb * frac;
         }
-    } else if (f.k >= 2 && f.k <= 6 && n - f.nc >= f.k + 6 &&
-               (f.k >= 3 || n - 1 - f.tw[0] < 2 || n - 1 - f.tw[1] < 2)) {
-        // (two-qubit gates only when a target is one of the two lowest bits:
-        // the quad kernel's per-lane 64-byte strides there coalesce poorly)
+    } else if (f.k >= 3 && f.k <= 6 && n - f.nc >= f.k + 6) {
         // LDS-staged dense matrix: targets plus six lane bits per tile
         st.type = Step::DENSE;
         DenseArgs& d = st.da;
@@ -913,12 +911,13 @@ bool lower_single(Program& P, const Factor& f, int n, size_t eb, int low_bits) {
                 d.cb[i] = 6 + (f.k - 1 - t);  // target 0 is the matrix index's msb
             }
         }
-        const int rl = (64 << f.k) / 256;
+        const int nt = dense_threads(f.k), lb = nt == 512 ? 9 : 8;
+        const int rl = (64 << f.k) / nt;
         for (int r = 0; r < rl; ++r) {
             uint64_t g = 0;
             uint32_t cc = 0;
-            for (int i = 8; i < f.k + 6; ++i)
-                if (((r << 8) >> i) & 1) {
+            for (int i = lb; i < f.k + 6; ++i)
+                if (((r << lb) >> i) & 1) {
                     g |= 1ull << d.sb[i];
                     cc |= 1u << d.cb[i];
                 }
@@ -932,10 +931,10 @@ bool lower_single(Program& P, const Factor& f, int n, size_t eb, int low_bits) {
         d.setmask = setmask;
         d.n_tiles = (uint64_t)1 << (n - (int)outer_pos.size());
         // the kernel's matrix layout: (wave w, column j, row q of the wave's
-        // dim / 4 rows), so one input's entries are contiguous per wave
+        // dim / waves rows), so one input's entries are contiguous per wave
         st.coff = (int64_t)P.coef.size();
-        const int rw = dim / 4;
-        for (int w = 0; w < 4; ++w)
+        const int nw = nt / 64, rw = dim / nw;
+        for (int w = 0; w < nw; ++w)
             for (int j = 0; j < dim; ++j)
                 for (int q = 0; q < rw; ++q) P.coef.push_back(f.m[(size_t)(w * rw + q) * dim + j]);
         st.bytes = 2.0 * N * eb * frac;
@@ -1107,8 +1106,9 @@ void run_program(qsv_ctx* c, const Program& P, qsv_dtype dt, int n, void* phi, v
                                            (const char*)c->coef.p + st.coff * cb, nt);
             break;
         case Step::DENSE:
-            e = c128 ? launch_dense<double>(c->stream, phi, st.da, (const char*)c->coef.p + st.coff * cb, nt)
-                     : launch_dense<float>(c->stream, phi, st.da, (const char*)c->coef.p + st.coff * cb, nt);
+            e = c128 ? launch_dense<double>(c->stream, phi, st.da, (const char*)c->coef.p + st.coff * cb, nt,
+                                            c->opt_dense_mfma != 0)
+                     : launch_dense<float>(c->stream, phi, st.da, (const char*)c->coef.p + st.coff * cb, nt, false);
             break;
         default:
             break;
@@ -1522,6 +1522,7 @@ qsv_status qsv_ctx_set_option(qsv_ctx* c, int option, int64_t v) {
         case QSV_OPT_NONTEMPORAL: c->opt_nontemporal = v != 0; break;
         case QSV_OPT_LAYERS: c->opt_layers = v != 0; break;
         case QSV_OPT_TILE_WS: c->opt_tile_ws = v != 0; break;
+        case QSV_OPT_DENSE_MFMA: c->opt_dense_mfma = v != 0; break;
         case QSV_OPT_TEST_ALLOC_LIMIT:
             if (v < 0) fail(QSV_ERR_ARG, "allocation limit must be >= 0");
             c->test_alloc_limit = v;
@@ -1547,6 +1548,7 @@ qsv_status qsv_ctx_get_option(qsv_ctx* c, int option, int64_t* v) {
         case QSV_OPT_NONTEMPORAL: *v = c->opt_nontemporal; break;
         case QSV_OPT_LAYERS: *v = c->opt_layers; break;
         case QSV_OPT_TILE_WS: *v = c->opt_tile_ws; break;
+        case QSV_OPT_DENSE_MFMA: *v = c->opt_dense_mfma; break;
         case QSV_OPT_TEST_ALLOC_LIMIT: *v = c->test_alloc_limit; break;
         case QSV_OPT_TEST_FAIL_LAUNCH: *v = c->test_fail_launch; break;
         default: fail(QSV_ERR_ARG, "unknown option");
@@ -1736,15 +1738,17 @@ qsv_status qsv_plan_json(int n, qsv_dtype dt, const qsv_op* ops, size_t n_ops, c
             add("{\"type\":\"%s\",\"bytes\":%.17g", names[st.type], st.bytes);
             if (st.type == Step::DENSE) {
                 const DenseArgs& d = st.da;
-                add(",\"k\":%d,\"coff\":%lld,\"n_tiles\":%llu,\"setmask\":%llu,\"sb\":[", d.k, (long long)st.coff,
-                    (unsigned long long)d.n_tiles, (unsigned long long)d.setmask);
+                add(",\"k\":%d,\"nthr\":%d,\"coff\":%lld,\"n_tiles\":%llu,\"setmask\":%llu,\"sb\":[", d.k,
+                    dense_threads(d.k), (long long)st.coff, (unsigned long long)d.n_tiles,
+                    (unsigned long long)d.setmask);
                 for (int j = 0; j < d.k + 6; ++j) add(j ? ",%d" : "%d", d.sb[j]);
                 js += "],\"cb\":[";
                 for (int j = 0; j < d.k + 6; ++j) add(j ? ",%d" : "%d", d.cb[j]);
                 js += "],\"goff_hi\":[";
-                for (int r = 0; r < (64 << d.k) / 256; ++r) add(r ? ",%llu" : "%llu", (unsigned long long)d.goff_hi[r]);
+                const int rl = (64 << d.k) / dense_threads(d.k);
+                for (int r = 0; r < rl; ++r) add(r ? ",%llu" : "%llu", (unsigned long long)d.goff_hi[r]);
                 js += "],\"coff_hi\":[";
-                for (int r = 0; r < (64 << d.k) / 256; ++r) add(r ? ",%u" : "%u", d.coff_hi[r]);
+                for (int r = 0; r < rl; ++r) add(r ? ",%u" : "%u", d.coff_hi[r]);
                 js += "],\"outer\":[";
                 for (int j = 0; j < d.outer.nm; ++j) add(j ? ",%llu" : "%llu", (unsigned long long)d.outer.m[j]);
                 js += "]";
@@ -2164,6 +2168,53 @@ uint64_t fnv(uint64_t h, const void* p, size_t n) {
     return h;
 }
 
+// Block table of a batched launch, XCD-aware: the GPU hands workgroup b to
+// XCD b mod 8 and each XCD has its own L2, so every block of a circuit goes to
+// the circuit's home XCD, where its state then stays cached across the
+// launches of the batch.  ents: (entry, blocks, home XCD).  Returns (entry,
+// local block) pairs in launch order; a position whose XCD has no blocks left
+// takes one from the fullest queue.
+constexpr int N_XCD = 8;
+std::vector<int32_t> xcd_block_table(const std::vector<std::array<int32_t, 3>>& ents) {
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> q(N_XCD);
+    size_t total = 0;
+    for (const auto& e : ents) {
+        auto& qq = q[(size_t)e[2] % N_XCD];
+        for (int32_t b = e[1] - 1; b >= 0; --b) qq.push_back({e[0], b});  // popped from the back: ascending
+        total += (size_t)e[1];
+    }
+    std::vector<int32_t> out;
+    out.reserve(2 * total);
+    for (size_t b = 0; b < total; ++b) {
+        size_t x = b % N_XCD;
+        if (q[x].empty())
+            for (size_t y = 0; y < (size_t)N_XCD; ++y)
+                if (q[y].size() > q[x].size()) x = y;
+        out.push_back(q[x].back().first);
+        out.push_back(q[x].back().second);
+        q[x].pop_back();
+    }
+    return out;
+}
+
+// Home XCD of each circuit: longest-processing-time assignment by state
+// size, so the XCDs get about equal shares of the batch.
+std::vector<int32_t> xcd_homes(const std::vector<int>& n) {
+    std::vector<size_t> order(n.size());
+    for (size_t i = 0; i < n.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return n[a] > n[b]; });
+    std::vector<double> load(N_XCD, 0.0);
+    std::vector<int32_t> home(n.size(), 0);
+    for (size_t i : order) {
+        int x = 0;
+        for (int y = 1; y < N_XCD; ++y)
+            if (load[y] < load[x]) x = y;
+        home[i] = x;
+        load[x] += std::ldexp(1.0, n[i]);
+    }
+    return home;
+}
+
 struct BatchLaunch {
     enum { TILE, PAULI, REDUCE } kind;
     bool two = false, generic = false;
@@ -2318,6 +2369,7 @@ BatchPlan plan_batch(qsv_batch* B, const double* params, bool grad) {
     bp.off_aux = append_bytes(tab, T.aux);
     const uintptr_t pool = (uintptr_t)B->pool.p;
     std::vector<ReduceEntry> reds;
+    const std::vector<int32_t> home = xcd_homes(B->n);
     auto tile_launches = [&](std::vector<std::vector<StepRef>>& steps, bool two) {
         size_t max_steps = 0;
         for (auto& v : steps) max_steps = std::max(max_steps, v.size());
@@ -2337,7 +2389,7 @@ BatchPlan plan_batch(qsv_batch* B, const double* params, bool grad) {
                 L.nthr = std::get<1>(kv.first);
                 L.generic = std::get<2>(kv.first);
                 std::vector<TileEntry> ents;
-                std::vector<int32_t> blk;
+                std::vector<std::array<int32_t, 3>> eb;
                 for (size_t ci : kv.second) {
                     const StepRef& r = steps[ci][si];
                     TileEntry e;
@@ -2354,9 +2406,8 @@ BatchPlan plan_batch(qsv_batch* B, const double* params, bool grad) {
                     }
                     e.part_off = r.part_off;
                     e.args = r.args_idx;
-                    e.blk0 = (int32_t)blk.size();
                     e.nblk = r.grid;
-                    for (int b = 0; b < r.grid; ++b) blk.push_back((int32_t)ents.size());
+                    eb.push_back({(int32_t)ents.size(), r.grid, home[ci]});
                     ents.push_back(e);
                     L.lds = std::max(L.lds, r.lds);
                     L.bytes += r.bytes;
@@ -2365,7 +2416,8 @@ BatchPlan plan_batch(qsv_batch* B, const double* params, bool grad) {
                         reds.push_back({r.part_off + (int64_t)sl * r.grid, r.grid,
                                         (int32_t)(bp.slot_base[ci] + (size_t)(r.slot_base + sl))});
                 }
-                L.blocks = (int)blk.size();
+                const std::vector<int32_t> blk = xcd_block_table(eb);
+                L.blocks = (int)(blk.size() / 2);
                 L.n_entries = (int)ents.size();
                 L.entries_off = append_bytes(tab, ents);
                 L.blk_off = append_bytes(tab, blk);
@@ -2380,7 +2432,7 @@ BatchPlan plan_batch(qsv_batch* B, const double* params, bool grad) {
         L.kind = BatchLaunch::PAULI;
         L.two = grad;
         std::vector<PauliEntry> ents;
-        std::vector<int32_t> blk;
+        std::vector<std::array<int32_t, 3>> ebl;
         for (size_t ci = 0; ci < nc; ++ci) {
             const uint64_t N = 1ull << B->n[ci];
             PauliEntry e;
@@ -2391,16 +2443,16 @@ BatchPlan plan_batch(qsv_batch* B, const double* params, bool grad) {
             e.g0 = T.obs_groups[ci].first;
             e.ng = T.obs_groups[ci].second;
             e.nblk = std::max(1, std::min(pauli_grid(N), 256));
-            e.blk0 = (int32_t)blk.size();
             e.part_off = (int64_t)n_part;
             reds.push_back({(int64_t)n_part, e.nblk, (int32_t)ci});
             L.lut_tables = std::max(L.lut_tables, T.lut_tables[ci]);
             n_part += (size_t)e.nblk;
-            for (int b = 0; b < e.nblk; ++b) blk.push_back((int32_t)ents.size());
+            ebl.push_back({(int32_t)ents.size(), e.nblk, home[ci]});
             ents.push_back(e);
             L.bytes += (1.0 + T.n_x_groups[ci] + (grad ? 1.0 : 0.0)) * (double)N * eb;
         }
-        L.blocks = (int)blk.size();
+        const std::vector<int32_t> blk = xcd_block_table(ebl);
+        L.blocks = (int)(blk.size() / 2);
         L.n_entries = (int)ents.size();
         L.entries_off = append_bytes(tab, ents);
         L.blk_off = append_bytes(tab, blk);

@@ -1026,7 +1026,8 @@ __global__ __launch_bounds__(512, 1) void k_tile_ws(const cx<T>* phi_src, cx<T>*
     tile_body_ws<T, TWO, LR>(phi_src, phi, lam, a, ops, coef, words, partials, blockIdx.x, gridDim.x);
 }
 
-// Batched passes: block b serves entry blk_entry[b] (one circuit's pass).
+// Batched passes: block b serves entry blk_entry[2b] (one circuit's pass) as
+// its block blk_entry[2b + 1].
 template <typename T, bool TWO, int LR, bool GEN>
 __global__ __launch_bounds__(256, 2) void k_tile_batch(const TileEntry* __restrict__ entries,
                                                        const int32_t* __restrict__ blk_entry,
@@ -1034,9 +1035,9 @@ __global__ __launch_bounds__(256, 2) void k_tile_batch(const TileEntry* __restri
                                                        const cx<T>* __restrict__ coef,
                                                        const uint64_t* __restrict__ words,
                                                        double* __restrict__ partials) {
-    const TileEntry& e = entries[blk_entry[blockIdx.x]];
+    const TileEntry& e = entries[blk_entry[2 * blockIdx.x]];
     tile_body<T, TWO, LR, GEN>((const cx<T>*)e.phi_src, (cx<T>*)e.phi, (cx<T>*)e.lam, args[e.args], ops, coef, words,
-                               partials + e.part_off, blockIdx.x - e.blk0, e.nblk);
+                               partials + e.part_off, (uint64_t)blk_entry[2 * blockIdx.x + 1], e.nblk);
 }
 
 

@@ -303,7 +303,7 @@ hipError_t launch_gatek(hipStream_t s, void* psi, uint64_t n_items, const Expand
 
 // ------------------------------------------------------------------ dense k-qubit matrices, LDS-staged
 
-// A dense 2^K x 2^K matrix (K = 2..6) on any K target bits.  A tile is the
+// A dense 2^K x 2^K matrix (K = 3..6) on any K target bits.  A tile is the
 // 2^(K+6) amplitudes that agree outside the targets and the six lowest index
 // bits that are neither targets nor controls (the lane bits): 64 tuples of
 // 2^K amplitudes.  Controls always lie outside the tile and are enumerated by
@@ -314,63 +314,78 @@ hipError_t launch_gatek(hipStream_t s, void* psi, uint64_t n_items, const Expand
 //           tuple l, with one pad slot per 64 (address c + (c >> 6)), which
 //           keeps both the load's and the compute's LDS accesses conflict-free
 //           whichever bits are targets;
-//  compute: wave w takes rows [w R, (w+1) R), R = 2^(K-2), of every tuple,
-//           lane = tuple: each input read from LDS feeds R complex MACs, and
-//           the matrix entries are wave-uniform (scalar loads).  The host
-//           stores the matrix as (wave, column j, row) so that the entries a
-//           wave needs for one input are contiguous; rows are taken in steps
-//           of at most 8, which bounds the scalar registers one step holds;
+//  compute: wave w of the NT / 64 waves takes rows [w R, (w+1) R) of every
+//           tuple, R = 2^K / (NT / 64), lane = tuple: each input read from
+//           LDS feeds R complex MACs whose matrix entries are wave-uniform
+//           (scalar loads).  The host stores the matrix as (wave, column j,
+//           row) so a wave's entries for one input are contiguous, and the
+//           next column's input and entries are fetched before the current
+//           column's MACs, so their latency hides behind the arithmetic;
 //  store:   outputs back to LDS, then coalesced stores.
 // FLOPs per amplitude 8 * 2^K: memory-bound up to K = 5 in complex128 and
-// FP64-ALU-bound at K = 6.
-template <typename T, int K>
-__global__ __launch_bounds__(256, 2) void k_dense(cx<T>* __restrict__ psi, const DenseArgs a,
-                                                  const cx<T>* __restrict__ mat, int nt) {
+// FP64-ALU-bound at K = 6, which runs 512 threads (four waves per SIMD with
+// two blocks per CU, so at most 128 VGPRs) to keep the FMA pipes fed.
+template <typename T, int K, int NT>
+__global__ __launch_bounds__(NT, 4) void k_dense(cx<T>* __restrict__ psi, const DenseArgs a,
+                                                         const cx<T>* __restrict__ mat, int nt) {
     constexpr int D = 1 << K;          // tuple size
-    constexpr int RW = D / 4;          // rows per wave
+    constexpr int NW = NT / 64;        // waves
+    constexpr int RW = D / NW;         // rows per wave
     constexpr int NE = D * 64;         // tile elements
-    constexpr int RL = NE / 256;       // elements per thread in load / store
+    constexpr int RL = NE / NT;        // elements per thread in load / store
+    constexpr int LB = NT == 512 ? 9 : 8;
     extern __shared__ __align__(16) unsigned char dn_smem[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(dn_smem);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    // the thread's load/store slots: tile-local index tid + r * 256; both maps
+    // the thread's load/store slots: tile-local index tid + r * NT; both maps
     // (to the global offset and to the compact LDS index) are bit deposits,
     // linear over GF(2), so the tid part and the r part combine by OR
     uint64_t goff = 0;
     uint32_t coff = 0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < LB; ++i)
         if ((tid >> i) & 1) {
             goff |= 1ull << a.sb[i];
             coff |= 1u << a.cb[i];
         }
-    constexpr int HS = RW < 8 ? RW : 8;  // rows per step
     const cx<T>* mw = mat + (size_t)wave * D * RW;
     for (uint64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
         const uint64_t base = expand_idx(tile, a.outer) | a.setmask;
-        cx<T> v[RL];
+        constexpr int LC = RL < 4 ? RL : 4;  // loads in flight per thread per chunk
 #pragma unroll
-        for (int r = 0; r < RL; ++r) v[r] = psi[base | goff | a.goff_hi[r]];
+        for (int r0 = 0; r0 < RL; r0 += LC) {
+            cx<T> v[LC];
 #pragma unroll
-        for (int r = 0; r < RL; ++r) {
-            const uint32_t c = coff | a.coff_hi[r];
-            lds[c + (c >> 6)] = v[r];
+            for (int r = 0; r < LC; ++r) v[r] = psi[base | goff | a.goff_hi[r0 + r]];
+#pragma unroll
+            for (int r = 0; r < LC; ++r) {
+                const uint32_t c = coff | a.coff_hi[r0 + r];
+                lds[c + (c >> 6)] = v[r];
+            }
         }
         __syncthreads();
         cx<T> acc[RW];
 #pragma unroll
         for (int q = 0; q < RW; ++q) acc[q] = {T(0), T(0)};
+        cx<T> x = lds[lane];
+        cx<T> m[RW];
 #pragma unroll
-        for (int h = 0; h < RW; h += HS) {
-#pragma unroll 2
-            for (int j = 0; j < D; ++j) {
-                const cx<T> x = lds[(j << 6) + lane + j];
-                const cx<T>* mj = mw + (size_t)j * RW + h;
+        for (int q = 0; q < RW; ++q) m[q] = mw[q];
+        for (int j = 0; j < D; ++j) {
+            // next column's input and entries first (the last fetch re-reads
+            // column D - 1, in bounds, unused)
+            const int jn = j + 1 < D ? j + 1 : j;
+            const cx<T> xn = lds[(jn << 6) + lane + jn];
+            cx<T> mn[RW];
 #pragma unroll
-                for (int q = 0; q < HS; ++q) acc[h + q] = cmad(mj[q], x, acc[h + q]);
-            }
+            for (int q = 0; q < RW; ++q) mn[q] = mw[(size_t)jn * RW + q];
+#pragma unroll
+            for (int q = 0; q < RW; ++q) acc[q] = cmad(m[q], x, acc[q]);
+            x = xn;
+#pragma unroll
+            for (int q = 0; q < RW; ++q) m[q] = mn[q];
         }
         __syncthreads();
 #pragma unroll
@@ -388,36 +403,143 @@ __global__ __launch_bounds__(256, 2) void k_dense(cx<T>* __restrict__ psi, const
     }
 }
 
+// The 6-qubit complex128 case on the FP64 matrix cores: the tile's product
+// OUT[r][t] = sum_j M[r][j] X[j][t] (64 rows, 64 tuples, 64 columns) as real
+// 16x16x4 products, Re += Mr Xr - Mi Xi and Im += Mr Xi + Mi Xr.  Wave w of
+// 8 owns the 16-row block w / 2 and the 32 tuples of half w % 2; its A
+// operands (its 16 rows of Mr and Mi, one double per lane per 4-column step)
+// stay in registers for the whole launch, the B operands (X, one complex per
+// lane per step and tuple block) come from the same padded LDS layout as the
+// vector form, and the accumulators hold 16 x 16 blocks (four doubles per
+// lane).  Operand layout of v_mfma_f64_16x16x4f64, wave64: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] and receives D[4 (l / 16) + v][l % 16]
+// in element v of its accumulator.  Load, layout and store are those of
+// k_dense<double, 6, 512>; the matrix is read from the same per-wave layout.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(512, 2) void k_dense6_mfma(cx<double>* __restrict__ psi, const DenseArgs a,
+                                                        const cx<double>* __restrict__ mat, int nt) {
+    constexpr int D = 64, NT = 512, RW = 8, RL = 8, LB = 9;
+    extern __shared__ __align__(16) unsigned char dm_smem[];
+    cx<double>* lds = reinterpret_cast<cx<double>*>(dm_smem);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int rb = wave >> 1, th = wave & 1;
+    uint64_t goff = 0;
+    uint32_t coff = 0;
+#pragma unroll
+    for (int i = 0; i < LB; ++i)
+        if ((tid >> i) & 1) {
+            goff |= 1ull << a.sb[i];
+            coff |= 1u << a.cb[i];
+        }
+    // A operands for the whole launch: M[16 rb + lane % 16][4 s + lane / 16];
+    // row r, column j sits at ((r / RW) * D + j) * RW + r % RW
+    double ar[16], ai[16];
+    {
+        const int r = 16 * rb + (lane & 15);
+#pragma unroll
+        for (int st = 0; st < 16; ++st) {
+            const int j = 4 * st + (lane >> 4);
+            const cx<double> m = mat[((size_t)(r / RW) * D + j) * RW + (r % RW)];
+            ar[st] = m.re;
+            ai[st] = m.im;
+        }
+    }
+    for (uint64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+        const uint64_t base = expand_idx(tile, a.outer) | a.setmask;
+#pragma unroll
+        for (int r0 = 0; r0 < RL; r0 += 4) {
+            cx<double> v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = psi[base | goff | a.goff_hi[r0 + r]];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t c = coff | a.coff_hi[r0 + r];
+                lds[c + (c >> 6)] = v[r];
+            }
+        }
+        __syncthreads();
+        v4d cre[2], cim[2];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            cre[b] = v4d{0.0, 0.0, 0.0, 0.0};
+            cim[b] = v4d{0.0, 0.0, 0.0, 0.0};
+        }
+#pragma unroll
+        for (int st = 0; st < 16; ++st) {
+            const int k = 4 * st + (lane >> 4);
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int t = 32 * th + 16 * b + (lane & 15);
+                const cx<double> x = lds[k * 65 + t];
+                cre[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[st], x.re, cre[b], 0, 0, 0);
+                cre[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[st], -x.im, cre[b], 0, 0, 0);
+                cim[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[st], x.im, cim[b], 0, 0, 0);
+                cim[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[st], x.re, cim[b], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                // accumulator element v of lane l is D[4 v + l / 16][l % 16]
+                const int r = 16 * rb + 4 * v + (lane >> 4), t = 32 * th + 16 * b + (lane & 15);
+                lds[r * 65 + t] = cx<double>{cre[b][v], cim[b][v]};
+            }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+            const uint32_t c = coff | a.coff_hi[r];
+            st_amp(psi + (base | goff | a.goff_hi[r]), lds[c + (c >> 6)], nt);
+        }
+        __syncthreads();
+    }
+}
+
 size_t dense_lds_bytes(int k, int elem_bytes) { return (size_t)(64 << k) * 65 / 64 * elem_bytes; }
 
 template <typename T>
-hipError_t launch_dense(hipStream_t s, void* psi, const DenseArgs& a, const void* mat, bool nt) {
+hipError_t launch_dense(hipStream_t s, void* psi, const DenseArgs& a, const void* mat, bool nt, bool mfma) {
     const size_t lds = dense_lds_bytes(a.k, (int)sizeof(cx<T>));
     uint64_t blocks = a.n_tiles < 4096 ? a.n_tiles : 4096;
     if (blocks == 0) return hipSuccess;
+    if constexpr (sizeof(T) == 8) {
+        if (mfma && a.k == 6) {
+            static std::atomic<uint64_t> mf_raised{0};
+            hipError_t e = allow_big_lds((const void*)k_dense6_mfma, mf_raised);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_dense6_mfma, dim3((unsigned)blocks), dim3(512), lds, s, (cx<double>*)psi, a,
+                               (const cx<double>*)mat, (int)nt);
+            return hipGetLastError();
+        }
+    }
     const cx<T>* m = (const cx<T>*)mat;
     static std::atomic<uint64_t> lds_raised{0};
-#define QSV_DN(KV)                                                                                        \
-    {                                                                                                     \
-        if (lds > 65536) {                                                                                \
-            hipError_t e = allow_big_lds((const void*)k_dense<T, KV>, lds_raised);                       \
-            if (e != hipSuccess) return e;                                                                \
-        }                                                                                                 \
-        hipLaunchKernelGGL((k_dense<T, KV>), dim3((unsigned)blocks), dim3(256), lds, s, (cx<T>*)psi, a, m, \
-                           (int)nt);                                                                      \
-    }                                                                                                     \
+#define QSV_DN(KV, NTV)                                                                                          \
+    {                                                                                                            \
+        if (lds > 65536) {                                                                                       \
+            hipError_t e = allow_big_lds((const void*)k_dense<T, KV, NTV>, lds_raised);                         \
+            if (e != hipSuccess) return e;                                                                       \
+        }                                                                                                        \
+        hipLaunchKernelGGL((k_dense<T, KV, NTV>), dim3((unsigned)blocks), dim3(NTV), lds, s, (cx<T>*)psi, a, m, \
+                           (int)nt);                                                                             \
+    }                                                                                                            \
     break;
     switch (a.k) {
-    case 2: QSV_DN(2)
-    case 3: QSV_DN(3)
-    case 4: QSV_DN(4)
-    case 5: QSV_DN(5)
-    case 6: QSV_DN(6)
+    case 3: QSV_DN(3, 256)
+    case 4: QSV_DN(4, 256)
+    case 5: QSV_DN(5, 256)
+    case 6: QSV_DN(6, 512)
     default: return hipErrorInvalidValue;
     }
 #undef QSV_DN
     return hipGetLastError();
 }
+
+int dense_threads(int k) { return k == 6 ? 512 : 256; }
 
 // ------------------------------------------------------------------ tile passes (tile_*.hip)
 
@@ -578,6 +700,37 @@ __device__ __forceinline__ void lut_iter(const LutState& L, uint64_t it, int lst
     }
 }
 
+// One thread's share of an observable sweep: indices base0, base0 + stride,
+// ... below N.  The diagonal loads psi[i] of U indices are issued together
+// (one 16-byte load per index would leave the sweep latency bound), then the
+// rows are formed in index order, so the sums keep their order.
+template <typename T, bool WRITE, bool NORM2>
+__device__ __forceinline__ void pauli_sweep(const cx<T>* __restrict__ psi, cx<T>* __restrict__ lam, uint64_t N,
+                                            uint64_t base0, uint64_t stride, int lstride,
+                                            const PauliGroupDev* __restrict__ groups, int n_groups,
+                                            const PauliTermDev* __restrict__ terms, const LutState& L,
+                                            const cx<double>* tabs, double& dot, double& nrm) {
+    constexpr int U = 4;
+    auto row = [&](uint64_t i, uint64_t it, cx<T> pi) {
+        uint64_t it_par[2];
+        lut_iter(L, it, lstride, it_par);
+        double ar, ai;
+        pauli_row<T>(psi, i, pi, groups, n_groups, terms, L, tabs, it_par, ar, ai);
+        if (WRITE) lam[i] = cx<T>{(T)ar, (T)ai};
+        dot += (double)pi.re * ar + (double)pi.im * ai;
+        if (NORM2) nrm += ar * ar + ai * ai;
+    };
+    uint64_t i = base0, it = 0;
+    for (; i + (U - 1) * stride < N; i += U * stride, it += U) {
+        cx<T> pv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) pv[u] = psi[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < U; ++u) row(i + u * stride, it + u, pv[u]);
+    }
+    for (; i < N; i += stride, ++it) row(i, it, psi[i]);
+}
+
 template <typename T, bool WRITE, bool NORM2>
 __global__ __launch_bounds__(256) void k_pauli(const cx<T>* __restrict__ psi, cx<T>* __restrict__ lam, uint64_t N,
                                                const PauliGroupDev* __restrict__ groups, int n_groups,
@@ -592,17 +745,7 @@ __global__ __launch_bounds__(256) void k_pauli(const cx<T>* __restrict__ psi, cx
     LutState L;
     lut_setup(L, groups, n_groups, aux, tabs, base0);
     double dot = 0.0, nrm = 0.0;
-    uint64_t it = 0;
-    for (uint64_t i = base0; i < N; i += stride, ++it) {
-        uint64_t it_par[2];
-        lut_iter(L, it, lstride, it_par);
-        const cx<T> pi = psi[i];
-        double ar, ai;
-        pauli_row<T>(psi, i, pi, groups, n_groups, terms, L, tabs, it_par, ar, ai);
-        if (WRITE) lam[i] = cx<T>{(T)ar, (T)ai};
-        dot += (double)pi.re * ar + (double)pi.im * ai;
-        if (NORM2) nrm += ar * ar + ai * ai;
-    }
+    pauli_sweep<T, WRITE, NORM2>(psi, lam, N, base0, stride, lstride, groups, n_groups, terms, L, tabs, dot, nrm);
     double tot = 0.0;
     block_add(dot, red, &tot, threadIdx.x, 256);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
@@ -636,8 +779,8 @@ hipError_t launch_pauli(hipStream_t s, bool write_lambda, bool norm2, const void
     return hipGetLastError();
 }
 
-// Batched Pauli sums: block b serves entry blk_entry[b] (one circuit), with
-// that circuit's byte tables (if any) in LDS.
+// Batched Pauli sums: block b serves entry blk_entry[2b] (one circuit) as its
+// block blk_entry[2b + 1], with that circuit's byte tables (if any) in LDS.
 template <typename T, bool WRITE>
 __global__ __launch_bounds__(256) void k_pauli_batch(const PauliEntry* __restrict__ entries,
                                                      const int32_t* __restrict__ blk_entry,
@@ -648,27 +791,18 @@ __global__ __launch_bounds__(256) void k_pauli_batch(const PauliEntry* __restric
     __shared__ double red[64];
     extern __shared__ __align__(16) unsigned char pauli_smem[];
     cx<double>* tabs = reinterpret_cast<cx<double>*>(pauli_smem);
-    const PauliEntry& en = entries[blk_entry[blockIdx.x]];
+    const PauliEntry& en = entries[blk_entry[2 * blockIdx.x]];
     const cx<T>* __restrict__ psi = (const cx<T>*)en.psi;
     cx<T>* __restrict__ lam = (cx<T>*)en.lam;
-    const uint64_t blk = blockIdx.x - en.blk0;
+    const uint64_t blk = (uint64_t)blk_entry[2 * blockIdx.x + 1];
     const PauliGroupDev* gp = groups + en.g0;
     const uint64_t base0 = blk * 256 + threadIdx.x;
     const uint64_t stride = (uint64_t)en.nblk * 256;  // a power of two
     const int lstride = __ffsll((unsigned long long)stride) - 1;
     LutState L;
     lut_setup(L, gp, en.ng, aux, tabs, base0);
-    double dot = 0.0;
-    uint64_t it = 0;
-    for (uint64_t i = base0; i < en.N; i += stride, ++it) {
-        uint64_t it_par[2];
-        lut_iter(L, it, lstride, it_par);
-        const cx<T> pi = psi[i];
-        double ar, ai;
-        pauli_row<T>(psi, i, pi, gp, en.ng, terms, L, tabs, it_par, ar, ai);
-        if (WRITE) lam[i] = cx<T>{(T)ar, (T)ai};
-        dot += (double)pi.re * ar + (double)pi.im * ai;
-    }
+    double dot = 0.0, nrm = 0.0;
+    pauli_sweep<T, WRITE, false>(psi, lam, en.N, base0, stride, lstride, gp, en.ng, terms, L, tabs, dot, nrm);
     double tot = 0.0;
     block_add(dot, red, &tot, threadIdx.x, 256);
     if (threadIdx.x == 0) partials[en.part_off + blk] = tot;
@@ -926,7 +1060,7 @@ hipError_t launch_reduce(hipStream_t s, const double* partials, int n_blocks, in
                                         const int32_t*, const void*, bool);                                     \
     template hipError_t launch_gatek_low<T>(hipStream_t, void*, uint64_t, const Expand&, uint64_t, int,         \
                                             const int32_t*, uint32_t, uint32_t, const void*, bool);             \
-    template hipError_t launch_dense<T>(hipStream_t, void*, const DenseArgs&, const void*, bool);              \
+    template hipError_t launch_dense<T>(hipStream_t, void*, const DenseArgs&, const void*, bool, bool);        \
     template hipError_t launch_tile<T>(hipStream_t, bool, bool, const void*, void*, void*, const TileArgs&, const TOp*,      \
                                        const void*, const uint64_t*, double*, int, int, int, size_t);           \
     template hipError_t launch_pauli<T>(hipStream_t, bool, bool, const void*, void*, uint64_t,                  \

@@ -102,26 +102,27 @@ struct DenseArgs {
     Expand outer;        // tile number -> base index (zeros at tile bits and controls)
     uint64_t setmask;    // control values
     uint64_t n_tiles;
-    uint64_t goff_hi[16];  // global offset of tile-local index r * 256
-    uint32_t coff_hi[16];  // compact index of tile-local index r * 256
+    uint64_t goff_hi[16];  // global offset of tile-local index r * (block size)
+    uint32_t coff_hi[16];  // compact index of tile-local index r * (block size)
     int32_t sb[12], cb[12];
     int32_t k, pad;
 };
 
-// One circuit's pass inside a batched launch (blocks blk0 .. blk0+nblk-1).
+// One circuit's pass inside a batched launch (nblk blocks; the launch's block
+// table maps each workgroup to (entry, local block)).
 struct TileEntry {
     const void* phi_src;
     void* phi;
     void* lam;
     int64_t part_off;  // first partial of this entry (slot-major, nblk per slot)
-    int32_t args, blk0, nblk, pad;
+    int32_t args, nblk, pad0, pad1;
 };
 struct PauliEntry {
     const void* psi;
     void* lam;
     uint64_t N;
     int64_t part_off;
-    int32_t g0, ng, blk0, nblk;
+    int32_t g0, ng, nblk, pad;
 };
 struct ReduceEntry {
     int64_t off;
@@ -178,8 +179,11 @@ template <typename T> hipError_t launch_gatek_low(hipStream_t s, void* psi, uint
 template <typename T> hipError_t launch_gatek(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex,
                                               uint64_t setmask, int k, const int32_t* tbits, const void* mat,
                                               bool nt);
-template <typename T> hipError_t launch_dense(hipStream_t s, void* psi, const DenseArgs& a, const void* mat, bool nt);
+// mfma: the 6-qubit complex128 case on the FP64 matrix cores (k_dense6_mfma)
+template <typename T> hipError_t launch_dense(hipStream_t s, void* psi, const DenseArgs& a, const void* mat, bool nt,
+                                              bool mfma);
 size_t dense_lds_bytes(int k, int elem_bytes);
+int dense_threads(int k);  // block size of the dense kernel for k targets
 template <typename T> hipError_t launch_tile(hipStream_t s, bool two, bool generic, const void* phi_src, void* phi,
                                              void* lam, const TileArgs& a,
                                              const TOp* ops, const void* coef, const uint64_t* words,

@@ -27,7 +27,7 @@ MAX_QUBITS = 34
 ADJ_INPLACE = 1
 OPT_FUSION, OPT_TILE_BITS, OPT_TILE_BITS_ADJ, OPT_LOW_BITS, OPT_PROFILE, OPT_NONTEMPORAL, OPT_LAYERS = 1, 2, 3, 4, 5, 6, 7
 OPT_TEST_ALLOC_LIMIT, OPT_TEST_FAIL_LAUNCH = 8, 9   # fault injection (tests of the error paths)
-OPT_TILE_WS = 10
+OPT_TILE_WS, OPT_DENSE_MFMA = 10, 11
 
 GATE_IDS = {
     "PauliX": 1, "PauliY": 2, "PauliZ": 3, "Hadamard": 4, "S": 5, "T": 6, "SX": 7, "Identity": 8,

@@ -12,6 +12,11 @@
       SHA-1 over every source file of the library (kernels, planner,
       lowering, gate tables), so that a change to any of them, and with it
       possibly the launched programs, retires the counters.
+
+  python -m paper_2403_02512_amd.rocprof_summary sweep-traffic <fetch csv> <write csv> <sweep log>
+      --reps R --cmd "<commands>"
+      counter bytes beside algorithmic bytes per case of a per-wire sweep
+      (bench.py --sweep --sweep-markers), calibrated by a state copy
 """
 from __future__ import annotations
 
@@ -99,6 +104,58 @@ def traffic(fetch_csv: str, write_csv: str, copy_bytes: float, cmd: str) -> str:
     return "\n".join(out) + "\n"
 
 
+def _dispatches(path: str, counter: str):
+    """(dispatch id, kernel name, bytes) of one counter, in dispatch order."""
+    out = []
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"]) * 1024.0))
+    out.sort()
+    return out
+
+
+def sweep_traffic(fetch_csv: str, write_csv: str, sweep_log: str, reps: int, cmd: str) -> str:
+    """Counter bytes per case of a per-wire sweep run with markers: the first
+    reps x (launches per apply) library dispatches after each case's marker
+    (a torch fill kernel) are that case's timed launches; each counter is scaled by the factor that
+    makes the state copy (the copy kernel before the first case) move exactly
+    the state's bytes; beside them, the algorithmic bytes of the case."""
+    import json
+    cases = [json.loads(x) for x in open(sweep_log) if x.startswith('{"case"')]
+    cols = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        d = _dispatches(path, counter)
+        cp = [v for _, k, v in d if "copyBuffer" in k]
+        if not cp or not cases:
+            raise SystemExit("no copy kernel or no cases: cannot calibrate")
+        n, dt = cases[0]["n_qubits"], cases[0]["dtype"]
+        state_bytes = float(1 << n) * (16 if dt == "c128" else 8)
+        scale = state_bytes / max(cp)
+        per_case, cur = [], None
+        for _, k, v in d:
+            if "FillFunctor" in k:
+                cur = []
+                per_case.append(cur)
+            elif cur is not None and "qsv::" in k:
+                cur.append(v * scale)
+        cols[counter] = (scale, per_case)
+    fs, fc = cols["FETCH_SIZE"]
+    ws, wc = cols["WRITE_SIZE"]
+    out = [f"commands: {cmd}",
+           f"calibration: the state copy reads and writes {state_bytes:.0f} B: fetch_scale={fs:.4f} "
+           f"write_scale={ws:.4f}", f"library_source_sha1={source_sha1()}", "",
+           "| case | alg GB | counter GB (fetch + write) | ratio | ms | counter GB/s |", "|---|---|---|---|---|---|"]
+    for c, f, w in zip(cases, fc, wc):
+        # the case's timed launches follow its marker; the next case's
+        # warm-up launch comes before the next marker
+        k = reps * sum(c["kernels"].values())
+        fb, wb = sum(f[:k]) / reps, sum(w[:k]) / reps
+        tot = (fb + wb) / 1e9
+        out.append(f"| {c['case']} | {c['alg_GB']:.3f} | {tot:.3f} ({fb / 1e9:.3f} + {wb / 1e9:.3f}) | "
+                   f"{tot / c['alg_GB']:.2f} | {c['ms']:.3f} | {tot / (c['ms'] / 1e3):.0f} |")
+    return "\n".join(out) + "\n"
+
+
 def read_traffic(path: str):
     """{kind: traffic bytes per dispatch} if the summary was taken on the
     current library sources, else None."""
@@ -127,9 +184,17 @@ def main(argv=None):
     b.add_argument("write_csv")
     b.add_argument("--copy-bytes", type=float, required=True)
     b.add_argument("--cmd", required=True)
+    c = sub.add_parser("sweep-traffic")
+    c.add_argument("fetch_csv")
+    c.add_argument("write_csv")
+    c.add_argument("sweep_log")
+    c.add_argument("--reps", type=int, default=3)
+    c.add_argument("--cmd", required=True)
     args = ap.parse_args(argv)
     if args.mode == "stats":
         sys.stdout.write(stats(args.csv, args.cmd))
+    elif args.mode == "sweep-traffic":
+        sys.stdout.write(sweep_traffic(args.fetch_csv, args.write_csv, args.sweep_log, args.reps, args.cmd))
     else:
         sys.stdout.write(traffic(args.fetch_csv, args.write_csv, args.copy_bytes, args.cmd))
 

@@ -44,8 +44,9 @@ def report(records, cmd: str) -> str:
            "their bound.", "",
            "| test | dtype | quantity | checks | max error | tolerance | max error / tolerance |",
            "|---|---|---|---|---|---|---|"]
+    esc = lambda x: x.replace("|", "\\|")  # a literal bar inside a table cell
     for (t, dt, q), d in sorted(rows.items(), key=lambda kv: (kv[0][1], kv[0][0], kv[0][2])):
-        out.append(f"| {t} | {dt} | {q} | {d['n']} | {d['err']:.2e} | {d['tol']:.0e} | {d['ratio']:.3f} |")
+        out.append(f"| {esc(t)} | {dt} | {esc(q)} | {d['n']} | {d['err']:.2e} | {d['tol']:.0e} | {d['ratio']:.3f} |")
     worst = {}
     for (t, dt, q), d in rows.items():
         worst[dt] = max(worst.get(dt, 0.0), d["ratio"])

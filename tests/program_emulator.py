@@ -56,20 +56,23 @@ def _dense(prog, st, psi):
     = tuple) from the padded LDS layout, and the outputs go back the same way."""
     k = st["k"]
     D = 1 << k
-    RW = D // 4
-    RL = (64 << k) // 256
+    NT = st["nthr"]
+    NW = NT // 64
+    LB = NT.bit_length() - 1
+    RW = D // NW
+    RL = (64 << k) // NT
     # the kernel's layout: (wave, column j, row q of the wave's RW rows)
-    Mt = _coef(prog, st["coff"], D * D).reshape(4, D, RW)
-    M = np.concatenate([Mt[w].T for w in range(4)], axis=0)
+    Mt = _coef(prog, st["coff"], D * D).reshape(NW, D, RW)
+    M = np.concatenate([Mt[w].T for w in range(NW)], axis=0)
     sb, cb = st["sb"], st["cb"]
     lds_size = (64 << k) * 65 // 64
     for tile in range(st["n_tiles"]):
         base = expand(tile, st["outer"]) | st["setmask"]
         lds = np.full(lds_size, np.nan + 0j)
         slots = []
-        for tid in range(256):
-            goff = sum(1 << sb[i] for i in range(8) if (tid >> i) & 1)
-            coff = sum(1 << cb[i] for i in range(8) if (tid >> i) & 1)
+        for tid in range(NT):
+            goff = sum(1 << sb[i] for i in range(LB) if (tid >> i) & 1)
+            coff = sum(1 << cb[i] for i in range(LB) if (tid >> i) & 1)
             for r in range(RL):
                 g = base | goff | st["goff_hi"][r]
                 c = coff | st["coff_hi"][r]
@@ -78,7 +81,7 @@ def _dense(prog, st, psi):
                 slots.append((g, c))
         assert len({g for g, _ in slots}) == 64 << k and len({c for _, c in slots}) == 64 << k
         out = lds.copy()
-        for wave in range(4):
+        for wave in range(NW):
             for lane in range(64):
                 x = np.array([lds[(j << 6) + lane + j] for j in range(D)])
                 for q in range(RW):

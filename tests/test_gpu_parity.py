@@ -333,7 +333,7 @@ def test_dense_unitaries_low_and_high_bits(ctx, n, dt):
         ops.append(W.op("RY", [int(rng.integers(n))], (0, 1.0)))
     params = np.array([0.37])
     psi0 = W.random_state(n, 3)
-    for opts in ({}, {qsv.OPT_TILE_BITS: 10}):
+    for opts in ({}, {qsv.OPT_TILE_BITS: 10}, {qsv.OPT_DENSE_MFMA: 1}):
         reset_options(ctx)
         got = gpu_run(ctx, n, ops, params, dt, psi0, opts)
         assert_state_close(got, oracle_state(n, ops, params, psi0), TOL[dt], f"n={n} opts={opts}", dt)

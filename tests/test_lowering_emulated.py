@@ -59,7 +59,7 @@ def test_layers_with_mixed_generators(opt):
         np.testing.assert_allclose(g, want[o], atol=1e-11)
 
 
-@pytest.mark.parametrize("k", [2, 3, 4, 5, 6])
+@pytest.mark.parametrize("k", [3, 4, 5, 6])
 @pytest.mark.parametrize("where", ["low", "high", "mixed", "controlled"])
 def test_dense_kernel_lowering(k, where):
     """Dense k-qubit unitaries through the LDS-staged kernel's index
@@ -79,9 +79,7 @@ def test_dense_kernel_lowering(k, where):
     psi0 = W.random_state(n, k)
     from paper_2403_02512_amd import qsv
     prog = qsv.plan_json(n, [o], [])
-    lowest = min(n - 1 - w for w in wires[nc:])
-    want = "dense" if k >= 3 or lowest < 2 else "gate2"
-    assert [st["type"] for st in prog["steps"]] == [want]
+    assert [st["type"] for st in prog["steps"]] == ["dense"]
     got = emulate_apply(n, [o], [], psi0)
     np.testing.assert_allclose(got, oracle.apply(n, [o], [], psi=psi0), atol=1e-12)
 

@@ -38,9 +38,9 @@ def test_small_register_is_one_tile():
                                         ("QubitUnitary", 4, True), ("QubitUnitary", 5, True),
                                         ("QubitUnitary", 6, False), ("QubitUnitary", 6, True)])
 def test_single_gate_kernel_choice(name, k, low):
-    """One pass per single gate: the pair kernel for k = 1, the quad kernel
-    for two-qubit gates away from the lowest two bits, the LDS-staged dense
-    kernel for two-qubit gates on them and for k = 3..6 (low or high bits)."""
+    """One pass per single gate: the pair and quad kernels for k = 1, 2 (the
+    LDS-staged dense kernel measured slower for two-qubit gates, also on the
+    lowest bits), the dense kernel for k = 3..6 (low or high bits)."""
     n = 20
     rng = np.random.default_rng(0)
     mat = W.random_unitary(k, rng) if name == "QubitUnitary" else None
@@ -50,7 +50,7 @@ def test_single_gate_kernel_choice(name, k, low):
     st = qsv.plan_stats(n, [o], [0.3])
     assert st["passes"] == 1 and st["tile_passes"] == 0
     kind = qsv.plan_json(n, [o], [0.3])["steps"][0]["type"]
-    assert kind == ("gate1" if k == 1 else "gate2" if k == 2 and not low else "dense")
+    assert kind == {1: "gate1", 2: "gate2"}.get(k, "dense")
 
 
 def test_non_commuting_gates_keep_order():

@@ -56,3 +56,34 @@ def test_source_hash_covers_every_library_source(tmp_path):
     h2 = rs.source_sha1(str(tmp_path))
     assert len({h0, h1, h2}) == 3
     assert rs.source_sha1() == rs.source_sha1(rs.CSRC)
+
+
+def test_sweep_traffic_splits_cases_at_markers(tmp_path):
+    import json
+    n, reps = 10, 2
+    state = float(1 << n) * 16
+    fill = "void at::native::vectorized_elementwise_kernel<4, at::native::FillFunctor<float> >(...)"
+    gate = "void qsv::k_diag1<double>(...)"
+    # dispatch order: warm-up launch, copy (calibration: fetch counter reads half), then per case
+    # a warm-up launch, the marker and `reps` timed launches
+    seq = [(gate, 1.0, 1.0), ("__amd_rocclr_copyBuffer", state / 2, state)]
+    per_case = [(0.5 * state, 0.5 * state), (2 * state, 2 * state)]
+    for f, w in per_case:
+        seq.append((gate, 7.0, 7.0))
+        seq.append((fill, 0.0, 256.0))
+        seq += [(gate, f / 2, w)] * reps
+    for counter, col, path in (("FETCH_SIZE", 1, tmp_path / "f.csv"), ("WRITE_SIZE", 2, tmp_path / "w.csv")):
+        with open(path, "w", newline="") as fh:
+            wr = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+            wr.writeheader()
+            for i, row in enumerate(seq):
+                wr.writerow({"Dispatch_Id": i + 1, "Kernel_Name": row[0], "Counter_Name": counter,
+                             "Counter_Value": row[col] / 1024})
+    log = tmp_path / "s.log"
+    log.write_text("\n".join(json.dumps({"case": f"c{i}", "n_qubits": n, "dtype": "c128", "alg_GB": state / 1e9,
+                                         "ms": 1.0, "kernels": {"diag1": 1}}) for i in range(2)) + "\n")
+    text = rs.sweep_traffic(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), str(log), reps, "cmd")
+    assert "fetch_scale=2.0000 write_scale=1.0000" in text
+    rows = [l for l in text.splitlines() if l.startswith("| c") and not l.startswith("| case")]
+    # case 0 moves its algorithmic bytes, case 1 four times them; warm-up launches are not counted
+    assert "| 1.00 |" in rows[0] and "| 4.00 |" in rows[1]
