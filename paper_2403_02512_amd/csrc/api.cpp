@@ -604,6 +604,7 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
             op.woff = (int64_t)P.words.size();
             for (auto x : pr.z) P.words.push_back(x);
             if (Q) {
+                op.tb[5] = a.n_zop++;  // its tile-parity slot in LDS
                 // per subcube: parity bits of the subcube's global offset;
                 // per element: of the element's offset inside the subcube
                 std::vector<int> nonq;
@@ -718,6 +719,7 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
             for (int t = 0; t < GB; ++t) gop.tb[t] = Q[t];
             gop.m = (int)(e - i);
             gop.slot = -1;
+            gop.tb[4] = gop.tb[5] = -1;  // set below: the first two Z-parity sub-ops
             // aux = 1: some sub-op needs the global index of each element
             for (size_t x = i; x < e; ++x)
                 if (protos[x].kind == Proto::DIAG || protos[x].kind == Proto::DOTDIAG) gop.aux = 1;
@@ -821,6 +823,13 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
                 flush_layer();
             }
             P.tops[gidx].m = (int)(P.tops.size() - gidx - 1);
+            {
+                int nz = 0;
+                for (int si = 0; si < P.tops[gidx].m && nz < 2; ++si) {
+                    const int k = P.tops[gidx + 1 + si].kind;
+                    if (k == OP_ZPHASE || k == OP_DOTZSUM) P.tops[gidx].tb[4 + nz++] = si;
+                }
+            }
             i = e;
         }
     }
@@ -834,7 +843,7 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
     }
     for (auto& x : ztab) P.coef.push_back(x);
     st.nslots = nslots;
-    st.lds = (size_t)tile_lds_bytes(b, two, (int)eb, nslots, a.zt_n);
+    st.lds = (size_t)tile_lds_bytes(b, two, (int)eb, nslots, a.zt_n, a.n_zop, a.n_outer);
     if (st.lds > (size_t)LDS_PER_CU)  // the planner's budget keeps passes below this
         fail(QSV_ERR_UNSUPPORTED, "tile pass needs more LDS than a CU has");
     {
@@ -1011,7 +1020,9 @@ PlanOptions plan_opts(int64_t tile_bits, int64_t low_bits, int64_t fusion, qsv_d
     o.layers = layers != 0;
     const int nthr = 1 << std::min(b, 8);
     o.slot_bytes = 8 * (nthr >= 64 ? nthr / 16 : 1);
-    o.ztab_bytes = 2 * eb;
+    // two phase-table entries, and (grouped) the op's tile-number columns
+    // and current tile parity
+    o.ztab_bytes = 2 * eb + 8 * (QSV_MAX_QUBITS + 1);
     o.lds_budget = LDS_PER_CU - tile_lds_bytes(b, two, eb, 0, 0) - 16;
     return o;
 }

@@ -31,6 +31,9 @@ struct TileCtx {
     const uint64_t* offhi;
     int n_outer;
     const cx<T>* ztab;  // the pass's phase tables, in LDS
+    // parity bits of the current tile's base index for each grouped Z-parity
+    // op (LDS, by the op's tb[5])
+    const uint64_t* zpar;
     int tid, nthr, nwaves;
     int nacc;  // slot accumulator entries per slot: one per 16-lane row (or 1)
 };
@@ -495,7 +498,9 @@ __device__ __forceinline__ void g_layer(cx<T>* a, cx<T>* l, const cx<T>* m, uint
     default: break;                                                                              \
     }
 
-template <typename T, bool TWO, int R, int GB>
+// ZP: the tile parities of the grouped Z-parity ops are in LDS (c.zpar);
+// otherwise they are formed from the columns at each use.
+template <typename T, bool TWO, int R, int GB, bool ZP = true>
 __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TOp& g, const TOp* __restrict__ subs,
                                            int b) {
     constexpr int E = 1 << GB;
@@ -529,7 +534,7 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
         v += row_shr<2>(v);
         v += row_shr<4>(v);
         v += row_shr<8>(v);
-        if ((c.tid & 15) == 15) c.sacc[slot * c.nacc + (c.tid >> 4)] += v;
+        if ((c.tid & 15) == 15) lds_add(&c.sacc[slot * c.nacc + (c.tid >> 4)], v);
     };
 #pragma unroll 1
     for (int sc = c.tid; sc < nsub; sc += c.nthr) {
@@ -543,6 +548,19 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
         if (need_gc)
             for (int j = 0; j < nq; ++j)
                 if ((sc >> j) & 1) gc |= 1ull << w[E + j];
+        // two vectors: the per-subcube parity word of the group's first
+        // Z-parity op (tb[4] of the group op) is loaded before the subcube, so
+        // its latency overlaps the LDS reads (one vector: no registers to spare)
+        uint64_t wz0 = 0;
+        if (TWO && g.tb[4] >= 0) wz0 = c.words[subs[g.tb[4]].woff + subs[g.tb[4]].m + sc];
+        auto zbits = [&](const TOp& s, int si) {
+            const uint64_t* z = c.words + s.woff;
+            const uint64_t w = (TWO && si == g.tb[4]) ? wz0 : z[s.m + sc];
+            uint64_t t;
+            if constexpr (ZP) t = c.zpar[s.tb[5]];
+            else t = tile_parity(c.tile, z + s.m + nsub + E, c.n_outer);
+            return t ^ w;
+        };
         const uint32_t stc = sw(tc);
         cx<T> a[E], l[TWO ? E : 1];
 #pragma unroll
@@ -648,7 +666,7 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
                 break;
             case OP_ZPHASE: {
                 const uint64_t* z = c.words + s.woff;
-                const uint64_t pc = tile_parity(c.tile, z + s.m + nsub + E, c.n_outer) ^ z[s.m + sc];
+                const uint64_t pc = zbits(s, si);
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const cx<T> d = c.ztab[s.aux + (int)__popcll(pc ^ z[s.m + nsub + e])];
@@ -698,7 +716,7 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
                         }
                     } else {  // OP_DOTZSUM
                         const uint64_t* z = c.words + s.woff;
-                        const uint64_t pc = tile_parity(c.tile, z + s.m + nsub + E, c.n_outer) ^ z[s.m + sc];
+                        const uint64_t pc = zbits(s, si);
 #pragma unroll
                         for (int e = 0; e < E; ++e)
                             v += (double)(s.m - 2 * (int)__popcll(pc ^ z[s.m + nsub + e])) * im_conj_mul(l[e], a[e]);
@@ -728,7 +746,7 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
                 v += row_shr<2>(v);
                 v += row_shr<4>(v);
                 v += row_shr<8>(v);
-                if ((c.tid & 15) == 15) c.sacc[slot * c.nacc + (c.tid >> 4)] += v;
+                if ((c.tid & 15) == 15) lds_add(&c.sacc[slot * c.nacc + (c.tid >> 4)], v);
             } else {
                 block_add(v, c.red, c.sacc + slot * c.nacc, c.tid, c.nthr);
             }
@@ -812,6 +830,28 @@ __device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
         for (int i = tid; i < a.zt_n; i += nthr) zt[i] = coef[a.zt_off + i];
         c.ztab = zt;
     }
+    // grouped Z-parity ops: their columns (tile-number bit j -> parity bits)
+    // in LDS once per block, then per tile the parity bits of its base index
+    uint64_t* zcol = reinterpret_cast<uint64_t*>(
+        (reinterpret_cast<uintptr_t>(c.ztab + a.zt_n) + 7) & ~(uintptr_t)7);
+    uint64_t* zpar = zcol + (size_t)a.n_zop * a.n_outer;
+    c.zpar = zpar;
+    if (a.n_zop > 0) {
+        constexpr int GBv = TWO ? GROUP_BITS_TWO : GROUP_BITS_ONE;
+        const int nsub = tsz >> GBv;
+        for (int oi = 0; oi < a.nops; ++oi) {
+            const TOp& op = ops[a.op0 + oi];
+            if (op.kind != OP_GROUP) continue;
+            for (int si = 0; si < op.m; ++si) {
+                const TOp& s = ops[a.op0 + oi + 1 + si];
+                if (s.kind != OP_ZPHASE && s.kind != OP_DOTZSUM) continue;
+                const uint64_t* cols = words + s.woff + s.m + nsub + (1 << GBv);
+                for (int j = tid; j < a.n_outer; j += nthr) zcol[(size_t)s.tb[5] * a.n_outer + j] = cols[j];
+            }
+            oi += op.m;
+        }
+        __syncthreads();
+    }
     uint64_t offlo = 0;
     for (int j = 0; j < a.nthr_log2; ++j) offlo |= (uint64_t)((tid >> j) & 1) << a.sb[j];
     c.offlo = offlo;
@@ -843,6 +883,13 @@ __device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
                 c.tp[stid + (r0 + r) * nthr] = vp[r];
                 if (TWO) c.tl[stid + (r0 + r) * nthr] = vl[r];
             }
+        }
+        for (int k = tid; k < a.n_zop; k += nthr) {
+            const uint64_t* col = zcol + (size_t)k * a.n_outer;
+            uint64_t p = 0;
+#pragma unroll 4
+            for (int j = 0; j < a.n_outer; ++j) p ^= ((tile >> j) & 1) ? col[j] : 0ull;
+            zpar[k] = p;
         }
         __syncthreads();
         for (int oi = 0; oi < a.nops; ++oi) {
@@ -938,6 +985,7 @@ __device__ __forceinline__ void tile_body_ws(const cx<T>* phi_src, cx<T>* phi, c
         for (int i = tid; i < a.zt_n; i += 2 * NT) zt[i] = coef[a.zt_off + i];
         c.ztab = zt;
     }
+    c.zpar = nullptr;  // tile parities from the columns per use (tile_group<..., false>)
     uint64_t offlo = 0;
     for (int j = 0; j < 8; ++j) offlo |= (uint64_t)((lt >> j) & 1) << a.sb[j];
     c.offlo = offlo;
@@ -994,7 +1042,8 @@ __device__ __forceinline__ void tile_body_ws(const cx<T>* phi_src, cx<T>* phi, c
             c.tl = c.tp + (TWO ? TSZ : 0);
             for (int oi = 0; oi < a.nops; ++oi) {
                 const TOp& op = ops[a.op0 + oi];
-                tile_group<T, TWO, R, TWO ? GROUP_BITS_TWO : GROUP_BITS_ONE>(c, op, ops + a.op0 + oi + 1, a.b);
+                tile_group<T, TWO, R, TWO ? GROUP_BITS_TWO : GROUP_BITS_ONE, false>(c, op, ops + a.op0 + oi + 1,
+                                                                                    a.b);
                 oi += op.m;
                 __syncthreads();
             }

@@ -94,6 +94,13 @@ __device__ __forceinline__ double wave_sum(double v) {
     return (lane_value(v, 15) + lane_value(v, 31)) + (lane_value(v, 47) + lane_value(v, 63));
 }
 
+// *p += v in LDS without waiting for the old value (ds_add_f64, no return):
+// one lane per accumulator adds in program order, so the sum keeps its
+// order and the result is reproducible; a barrier completes the adds.
+__device__ __forceinline__ void lds_add(double* p, double v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Adds the block-wide sum of v to *dst (one thread writes).  Every thread of
 // the block must call it; fixed summation order, so results are reproducible.
 __device__ __forceinline__ void block_add(double v, double* red, double* dst, int tid, int nthr) {

@@ -543,11 +543,14 @@ int dense_threads(int k) { return k == 6 ? 512 : 256; }
 
 // ------------------------------------------------------------------ tile passes (tile_*.hip)
 
-int tile_lds_bytes(int b, bool two, int elem_bytes, int nslots, int zt_n) {
+int tile_lds_bytes(int b, bool two, int elem_bytes, int nslots, int zt_n, int n_zop, int n_outer) {
     const int nthr = 1 << (b < 8 ? b : 8);
     const int nacc = nthr >= 64 ? nthr / 16 : 1;
     const int acc = ((64 + nslots * nacc) * 8 + 15) & ~15;
-    return (two ? 2 : 1) * (1 << b) * elem_bytes + acc + zt_n * elem_bytes;
+    // grouped Z-parity ops: per-op columns of the tile-number bits and the
+    // current tile's parity bits (8-byte words after the phase tables)
+    const int zt = (zt_n * elem_bytes + 7) & ~7;
+    return (two ? 2 : 1) * (1 << b) * elem_bytes + acc + zt + n_zop * (n_outer + 1) * 8;
 }
 
 template <typename T>

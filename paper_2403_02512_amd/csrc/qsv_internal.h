@@ -89,6 +89,8 @@ struct TileArgs {
     int32_t flags;          // TILE_SYNTH: phi tiles start as the basis state `basis`
     int32_t n_outer;        // index bits outside the tile (bits of the tile number)
     uint64_t basis;
+    int32_t n_zop;          // Z-parity ops inside register groups (their tb[5] numbers them)
+    int32_t pad_z;
 };
 constexpr int32_t TILE_SYNTH = 1;
 constexpr int32_t TILE_NT = 2;  // write back with non-temporal stores
@@ -226,7 +228,7 @@ hipError_t launch_reduce(hipStream_t s, const double* partials, int n_blocks, in
 constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)8 << 20;
 hipError_t noalloc_scratch_address(void** ptr);
 
-int tile_lds_bytes(int b, bool two, int elem_bytes, int nslots, int zt_n);
+int tile_lds_bytes(int b, bool two, int elem_bytes, int nslots, int zt_n, int n_zop = 0, int n_outer = 0);
 int pauli_grid(uint64_t N);
 
 // ------------------------------------------------------------------ host gate model (gates.cpp)

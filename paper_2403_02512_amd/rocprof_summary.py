@@ -17,6 +17,9 @@
       --reps R --cmd "<commands>"
       counter bytes beside algorithmic bytes per case of a per-wire sweep
       (bench.py --sweep --sweep-markers), calibrated by a state copy
+
+  python -m paper_2403_02512_amd.rocprof_summary sweep-table <sweep log> --cmd "<command>"
+      per-wire fractions of the HBM peak from a sweep's JSON lines
 """
 from __future__ import annotations
 
@@ -131,9 +134,11 @@ def sweep_traffic(fetch_csv: str, write_csv: str, sweep_log: str, reps: int, cmd
         n, dt = cases[0]["n_qubits"], cases[0]["dtype"]
         state_bytes = float(1 << n) * (16 if dt == "c128" else 8)
         scale = state_bytes / max(cp)
-        per_case, cur = [], None
+        per_case, cur, calibrated = [], None, False
         for _, k, v in d:
-            if "FillFunctor" in k:
+            if "copyBuffer" in k and v == max(cp):
+                calibrated = True  # markers follow the calibration copy
+            elif calibrated and "FillFunctor" in k:
                 cur = []
                 per_case.append(cur)
             elif cur is not None and "qsv::" in k:
@@ -153,6 +158,45 @@ def sweep_traffic(fetch_csv: str, write_csv: str, sweep_log: str, reps: int, cmd
         tot = (fb + wb) / 1e9
         out.append(f"| {c['case']} | {c['alg_GB']:.3f} | {tot:.3f} ({fb / 1e9:.3f} + {wb / 1e9:.3f}) | "
                    f"{tot / c['alg_GB']:.2f} | {c['ms']:.3f} | {tot / (c['ms'] / 1e3):.0f} |")
+    return "\n".join(out) + "\n"
+
+
+def sweep_table(sweep_log: str, cmd: str) -> str:
+    """Markdown tables of a per-wire sweep (bench.py --sweep): per gate the
+    fraction of the 8 TB/s HBM peak (algorithmic bytes / HIP-event time) on
+    every wire or wire pair, then the per-gate summary lines."""
+    import json
+    rows = [json.loads(x) for x in open(sweep_log) if x.startswith('{"case"')]
+    summ = [json.loads(x) for x in open(sweep_log) if x.startswith('{"summary"')]
+    if not rows:
+        raise SystemExit("no sweep cases in the log")
+    n, dt = rows[0]["n_qubits"], rows[0]["dtype"]
+    out = [f"command: {cmd}", "", f"{n} qubits, {dt}: fraction of 8 TB/s (algorithmic bytes / kernel time)", ""]
+    by = collections.OrderedDict()
+    for r in rows:
+        g, where = r["case"].split(" ", 1)
+        by.setdefault((r["class"], g), collections.OrderedDict())[where] = r
+    for cls, label in (("1q", "bit"), ("2q", "bits")):
+        gates = [g for (c, g) in by if c == cls]
+        if not gates:
+            continue
+        keys = list(by[(cls, gates[0])].keys())
+        out.append("| " + label + " | " + " | ".join(gates) + " |")
+        out.append("|---" * (len(gates) + 1) + "|")
+        for k in keys:
+            cells = [f"{by[(cls, g)][k]['frac_of_8TBs']:.3f}" if k in by[(cls, g)] else "" for g in gates]
+            out.append(f"| {k.replace(label, '')} | " + " | ".join(cells) + " |")
+        out.append("")
+    dense = [r for r in rows if r["class"] == "dense"]
+    if dense:
+        out += ["| dense unitary | kernel | ms | frac |", "|---|---|---|---|"]
+        for r in dense:
+            out.append(f"| {r['case']} | {','.join(r['kernels'])} | {r['ms']:.3f} | {r['frac_of_8TBs']:.3f} |")
+        out.append("")
+    out += ["| gate | cases | min | median | max |", "|---|---|---|---|---|"]
+    for s_ in summ:
+        out.append(f"| {s_['summary']} | {s_['cases']} | {s_['frac_min']:.3f} | {s_['frac_median']:.3f} | "
+                   f"{s_['frac_max']:.3f} |")
     return "\n".join(out) + "\n"
 
 
@@ -190,9 +234,14 @@ def main(argv=None):
     c.add_argument("sweep_log")
     c.add_argument("--reps", type=int, default=3)
     c.add_argument("--cmd", required=True)
+    t = sub.add_parser("sweep-table")
+    t.add_argument("sweep_log")
+    t.add_argument("--cmd", required=True)
     args = ap.parse_args(argv)
     if args.mode == "stats":
         sys.stdout.write(stats(args.csv, args.cmd))
+    elif args.mode == "sweep-table":
+        sys.stdout.write(sweep_table(args.sweep_log, args.cmd))
     elif args.mode == "sweep-traffic":
         sys.stdout.write(sweep_traffic(args.fetch_csv, args.write_csv, args.sweep_log, args.reps, args.cmd))
     else:

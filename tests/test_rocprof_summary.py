@@ -64,9 +64,10 @@ def test_sweep_traffic_splits_cases_at_markers(tmp_path):
     state = float(1 << n) * 16
     fill = "void at::native::vectorized_elementwise_kernel<4, at::native::FillFunctor<float> >(...)"
     gate = "void qsv::k_diag1<double>(...)"
-    # dispatch order: warm-up launch, copy (calibration: fetch counter reads half), then per case
+    # dispatch order: a fill (the marker tensor's creation), a launch, the copy (calibration: the
+    # fetch counter reads half), then per case
     # a warm-up launch, the marker and `reps` timed launches
-    seq = [(gate, 1.0, 1.0), ("__amd_rocclr_copyBuffer", state / 2, state)]
+    seq = [(fill, 0.0, 256.0), (gate, 1.0, 1.0), ("__amd_rocclr_copyBuffer", state / 2, state)]
     per_case = [(0.5 * state, 0.5 * state), (2 * state, 2 * state)]
     for f, w in per_case:
         seq.append((gate, 7.0, 7.0))
