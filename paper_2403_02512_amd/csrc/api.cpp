@@ -327,6 +327,8 @@ int classify1(const std::vector<cd>& m) {
 int classify_gen1(const std::vector<cd>& g) {
     if (g[0] == 0.0 && g[3] == 0.0 && g[1] == 1.0 && g[2] == 1.0) return MC_PX;
     if (g[0] == 0.0 && g[3] == 0.0 && g[1] == cd(0.0, -1.0) && g[2] == cd(0.0, 1.0)) return MC_PY;
+    // real diagonal (Z, the |1><1| projector of PhaseShift)
+    if (g[1] == 0.0 && g[2] == 0.0 && g[0].imag() == 0.0 && g[3].imag() == 0.0) return MC_DIAG;
     return MC_DENSE;
 }
 
@@ -672,7 +674,8 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
         } else {
             op.kind = f.k == 1 ? OP_APPLY1 : (f.k == 2 ? OP_APPLY2 : OP_APPLYK);
             op.cls = f.k == 1 ? classify1(mm) : (f.k == 2 ? classify2(mm) : MC_DENSE);
-            if (Q && op.cls == MC_DIAG) op.cls = MC_DENSE;  // grouped kernels: dense / anti / mid
+            // grouped kernels: dense / anti / mid, and diagonal for one qubit
+            if (Q && op.cls == MC_DIAG && f.k != 1) op.cls = MC_DENSE;
         }
         for (auto& x : mm) P.coef.push_back(x);
         P.tops.push_back(op);
@@ -753,8 +756,12 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
                 std::vector<size_t> run;
                 auto flush_layer = [&]() {
                     if (run.empty()) return;
-                    if (run.size() == 1) {
-                        emit(protos[run[0]], &Q, dslot);
+                    int npos = 0, only = -1;
+                    for (int p = 0; p < GB; ++p)
+                        if (lg[p] >= 0 || ld[p] >= 0) ++npos, only = p;
+                    if (npos == 1) {  // one position: its inner product and matrix as plain ops
+                        if (ld[only] >= 0) emit(protos[ld[only]], &Q, dslot);
+                        if (lg[only] >= 0) emit(protos[lg[only]], &Q, dslot);
                     } else {
                         TOp op;
                         std::memset(&op, 0, sizeof op);
@@ -762,7 +769,7 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
                         op.k = 1;
                         op.slot = -1;
                         op.aux = dslot;
-                        bool real = true, riri = true;
+                        bool real = true, riri = true, diag = true;
                         int gcls = LG_NONE;
                         std::vector<cd> mats[4], gens[4];
                         for (int p = 0; p < GB; ++p) {
@@ -777,12 +784,15 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
                                    m[3].imag() == 0;
                             riri = riri && m[0].imag() == 0 && m[3].imag() == 0 && m[1].real() == 0 &&
                                    m[2].real() == 0;
+                            diag = diag && m[1] == 0.0 && m[2] == 0.0;
                             gens[p] = {0.0, 0.0, 0.0, 0.0};
                             if (ld[p] >= 0) {
                                 const Factor& f = F[protos[ld[p]].f];
                                 gens[p] = f.g;
                                 const int cg = classify_gen1(f.g);
-                                const int c = cg == MC_PX ? LG_X : (cg == MC_PY ? LG_Y : LG_DENSE);
+                                const int c = cg == MC_PX ? LG_X
+                                            : cg == MC_PY ? LG_Y
+                                            : cg == MC_DIAG ? LG_DIAG : LG_DENSE;
                                 gcls = gcls == LG_NONE ? c : (gcls == c ? c : LG_DENSE);
                                 op.lcmask |= 1u << p;
                                 op.tb[p] = nslots++;
@@ -790,11 +800,11 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
                                 ++dslot;
                             }
                         }
-                        op.cls = real ? MC_REAL : (riri ? MC_RIRI : MC_DENSE);
+                        op.cls = real ? MC_REAL : (riri ? MC_RIRI : (diag ? MC_DIAG : MC_DENSE));
                         op.lcval = (uint32_t)gcls;
                         op.coff = (int64_t)P.coef.size();
                         for (int p = 0; p < GB; ++p) {
-                            if (gcls == LG_DENSE)
+                            if (gcls == LG_DENSE || gcls == LG_DIAG)
                                 for (auto x : gens[p]) P.coef.push_back(x);
                             for (auto x : mats[p]) P.coef.push_back(x);
                         }
@@ -803,24 +813,122 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
                     run.clear();
                     for (int p = 0; p < 4; ++p) lg[p] = ld[p] = -1;
                 };
+                // Layers by depth (as-soon-as-possible levels).  Each
+                // position's layer ops form units (an optional inner product,
+                // then an optional matrix); a unit's level is one above the
+                // level of the last op on its position, and any other op's
+                // level is one above the last ops on the positions it touches
+                // (all positions for diagonal and Z-parity ops).  Ops of one
+                // level touch disjoint positions and so commute, and an inner
+                // product on one position is unchanged by gates on others
+                // (they act on phi and lambda alike and commute with its
+                // generator), so emitting by level -- the level's units as one
+                // layer, then its other ops -- is exact.  U3 / Rot
+                // decompositions then give full PhaseShift, RY or RZ layers
+                // instead of one layer per gate, and a CNOT only orders the
+                // two positions it touches.
+                auto posmask = [&](uint32_t bits) {
+                    uint32_t m = 0;
+                    for (int t = 0; t < GB; ++t)
+                        if ((bits >> Q[t]) & 1) m |= 1u << t;
+                    return m;
+                };
+                std::vector<int> lvl(GB, -1), open_dot(GB, -1);
+                std::vector<std::pair<int, size_t>> order;  // (level, proto)
                 for (size_t x = i; x < e; ++x) {
                     const Proto& pr = protos[x];
-                    if (!layer_ok(pr)) {
-                        flush_layer();
-                        emit(pr, &Q, dslot);
-                        continue;
-                    }
-                    const int p = pos_of(pr);
-                    if (pr.kind == Proto::DOT) {
-                        if (lg[p] >= 0 || ld[p] >= 0) flush_layer();
-                        ld[p] = (int)x;
+                    int level;
+                    if (layer_ok(pr)) {
+                        const int p = pos_of(pr);
+                        if (pr.kind == Proto::APPLY && open_dot[p] >= 0) {
+                            level = lvl[p];  // the matrix after this unit's inner product
+                            open_dot[p] = -1;
+                        } else {
+                            level = lvl[p] + 1;
+                            lvl[p] = level;
+                            open_dot[p] = pr.kind == Proto::DOT ? (int)x : -1;
+                        }
                     } else {
-                        if (lg[p] >= 0) flush_layer();
-                        lg[p] = (int)x;
+                        const bool local = (pr.kind == Proto::APPLY || pr.kind == Proto::DOT) && pr.k <= 2;
+                        const uint32_t S = local ? posmask(pr.tbits | pr.dbits) : (1u << GB) - 1;
+                        level = 0;
+                        for (int p = 0; p < GB; ++p)
+                            if ((S >> p) & 1) level = std::max(level, lvl[p] + 1);
+                        for (int p = 0; p < GB; ++p)
+                            if ((S >> p) & 1) {
+                                lvl[p] = level;
+                                open_dot[p] = -1;
+                            }
                     }
-                    run.push_back(x);
+                    order.push_back({level, x});
                 }
-                flush_layer();
+                std::stable_sort(order.begin(), order.end(),
+                                 [](const std::pair<int, size_t>& u, const std::pair<int, size_t>& v) {
+                                     return u.first < v.first;
+                                 });
+                // matrix classes a unit's matrix fits (bit 0 real, 1 RIRI,
+                // 2 diagonal; all for no matrix) and its generator code
+                auto unit_fits = [&](int app) {
+                    if (app < 0) return 7u;
+                    const std::vector<cd> m = maybe_dag(F[protos[app].f].m, 2, dagger);
+                    uint32_t fl = 0;
+                    if (m[0].imag() == 0 && m[1].imag() == 0 && m[2].imag() == 0 && m[3].imag() == 0) fl |= 1;
+                    if (m[0].imag() == 0 && m[3].imag() == 0 && m[1].real() == 0 && m[2].real() == 0) fl |= 2;
+                    if (m[1] == 0.0 && m[2] == 0.0) fl |= 4;
+                    return fl;
+                };
+                auto unit_gen = [&](int dot) {
+                    if (dot < 0) return (int)LG_NONE;
+                    const int cg = classify_gen1(F[protos[dot].f].g);
+                    return cg == MC_PX ? (int)LG_X : cg == MC_PY ? (int)LG_Y : cg == MC_DIAG ? (int)LG_DIAG : (int)LG_DENSE;
+                };
+                // the class a layer gets from its fits (real, then RIRI, then diagonal)
+                auto fit_class = [](uint32_t fl) { return fl & 1 ? 1 : fl & 2 ? 2 : fl & 4 ? 4 : 0; };
+                for (size_t q = 0; q < order.size();) {
+                    size_t q1 = q;
+                    while (q1 < order.size() && order[q1].first == order[q].first) ++q1;
+                    int udot[4] = {-1, -1, -1, -1}, uapp[4] = {-1, -1, -1, -1};
+                    for (size_t r = q; r < q1; ++r) {
+                        const size_t x = order[r].second;
+                        if (!layer_ok(protos[x])) continue;
+                        const int p = pos_of(protos[x]);
+                        if (protos[x].kind == Proto::DOT) udot[p] = (int)x;
+                        else uapp[p] = (int)x;
+                    }
+                    // the level's units (distinct positions) as layers of one
+                    // matrix and generator class each; a unit joins a layer
+                    // when that keeps the layer's classes
+                    bool done[4] = {false, false, false, false};
+                    for (int p0 = 0; p0 < GB; ++p0) {
+                        if (done[p0] || (udot[p0] < 0 && uapp[p0] < 0)) continue;
+                        uint32_t fl = unit_fits(uapp[p0]);
+                        int gen = unit_gen(udot[p0]);
+                        for (int p = p0; p < GB; ++p) {
+                            if (done[p] || (udot[p] < 0 && uapp[p] < 0)) continue;
+                            const uint32_t nf = fl & unit_fits(uapp[p]);
+                            const int g = unit_gen(udot[p]);
+                            if (p != p0) {
+                                if (fit_class(nf) != fit_class(fl) && fit_class(fl) != 0) continue;
+                                if (gen != LG_NONE && g != LG_NONE && g != gen) continue;
+                            }
+                            fl = nf;
+                            if (gen == LG_NONE) gen = g;
+                            done[p] = true;
+                            if (udot[p] >= 0) {
+                                ld[p] = udot[p];
+                                run.push_back((size_t)udot[p]);
+                            }
+                            if (uapp[p] >= 0) {
+                                lg[p] = uapp[p];
+                                run.push_back((size_t)uapp[p]);
+                            }
+                        }
+                        flush_layer();
+                    }
+                    for (size_t r = q; r < q1; ++r)
+                        if (!layer_ok(protos[order[r].second])) emit(protos[order[r].second], &Q, dslot);
+                    q = q1;
+                }
             }
             P.tops[gidx].m = (int)(P.tops.size() - gidx - 1);
             {

@@ -325,6 +325,9 @@ __device__ __forceinline__ void bfly(const cx<T>* m, cx<T>& x0, cx<T>& x1) {
         const T m0 = m[0].re, m1 = m[1].re, m2 = m[2].re, m3 = m[3].re;
         x0 = {m0 * a0.re + m1 * a1.re, m0 * a0.im + m1 * a1.im};
         x1 = {m2 * a0.re + m3 * a1.re, m2 * a0.im + m3 * a1.im};
+    } else if (CLS == MC_DIAG) {
+        x0 = cmul(m[0], a0);
+        x1 = cmul(m[3], a1);
     } else if (CLS == MC_RIRI) {  // [[r0, i q1], [i q2, r3]]
         const T r0 = m[0].re, q1 = m[1].im, q2 = m[2].im, r3 = m[3].re;
         x0 = {r0 * a0.re - q1 * a1.im, r0 * a0.im + q1 * a1.re};
@@ -390,6 +393,8 @@ __device__ __forceinline__ double g_dot1(const cx<T>* a, const cx<T>* l, const c
         if (CTRL && ((tc | eo[e0]) & lcm) != lcv) continue;
         if (CLS == MC_PX) {         // G = X: Im(l0* p1) + Im(l1* p0)
             acc += im_conj_mul(l[e0], a[e1]) + im_conj_mul(l[e1], a[e0]);
+        } else if (CLS == MC_DIAG) {  // G = diag(g0, g3), real
+            acc += (double)g0.re * im_conj_mul(l[e0], a[e0]) + (double)g3.re * im_conj_mul(l[e1], a[e1]);
         } else if (CLS == MC_PY) {  // G = Y: Re(l1* p0) - Re(l0* p1)
             acc += (double)l[e1].re * a[e0].re + (double)l[e1].im * a[e0].im -
                    (double)l[e0].re * a[e1].re - (double)l[e0].im * a[e1].im;
@@ -456,10 +461,10 @@ struct DotAcc {
 // another, for the inner products), so the layer runs positions in a fixed
 // order as straight-line code: no per-gate dispatch, and the register arrays
 // flow through without merges.  Per position p the coefficients are
-// [generator (GCLS == DENSE only)] then the 2x2 matrix.
+// [generator (GCLS == DENSE or DIAG only)] then the 2x2 matrix.
 template <typename T, bool TWO, int GB, int CLS, int GCLS, int P, typename Sink>
 __device__ __forceinline__ void g_layer_pos(cx<T>* a, cx<T>* l, const cx<T>* m, uint32_t dmask, Sink& sink) {
-    constexpr int NC = GCLS == MC_DENSE ? 8 : 4;
+    constexpr int NC = (GCLS == MC_DENSE || GCLS == MC_DIAG) ? 8 : 4;
     const cx<T>* mp = m + P * NC;
     if constexpr (TWO && GCLS >= 0) {
         if (dmask & (1u << P)) sink(P, g_dot1<T, GB, P, GCLS, false>(a, l, mp, 0, nullptr, 0, 0));
@@ -467,7 +472,7 @@ __device__ __forceinline__ void g_layer_pos(cx<T>* a, cx<T>* l, const cx<T>* m, 
     // unconditional: positions without a gate hold the identity, which keeps
     // the layer branch-free (a skipped position would merge two versions of
     // the register arrays)
-    g_apply1<T, TWO, GB, P, CLS, false>(a, l, mp + (GCLS == MC_DENSE ? 4 : 0), 0, nullptr, 0, 0);
+    g_apply1<T, TWO, GB, P, CLS, false>(a, l, mp + NC - 4, 0, nullptr, 0, 0);
 }
 
 // sink(p, v) receives this thread's inner product at position p (where bit p
@@ -593,6 +598,10 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
 #define F(P) g_apply1<T, TWO, GB, P, MC_RIRI, false>(a, l, m, tc, eo, 0, 0)
                     QSV_P1_CASES(F)
 #undef F
+                } else if (s.cls == MC_DIAG) {
+#define F(P) g_apply1<T, TWO, GB, P, MC_DIAG, false>(a, l, m, tc, eo, 0, 0)
+                    QSV_P1_CASES(F)
+#undef F
                 } else {
 #define F(P) g_apply1<T, TWO, GB, P, MC_DENSE, false>(a, l, m, tc, eo, 0, 0)
                     QSV_P1_CASES(F)
@@ -634,6 +643,7 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
                 if (gcode == LG_NONE) {
                     if (s.cls == MC_REAL) L(MC_REAL, -1);
                     else if (s.cls == MC_RIRI) L(MC_RIRI, -1);
+                    else if (s.cls == MC_DIAG) L(MC_DIAG, -1);
                     else L(MC_DENSE, -1);
                 } else if constexpr (TWO) {
                     if (gcode == LG_X) {
@@ -644,9 +654,15 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
                         if (s.cls == MC_REAL) L(MC_REAL, MC_PY);
                         else if (s.cls == MC_RIRI) L(MC_RIRI, MC_PY);
                         else L(MC_DENSE, MC_PY);
+                    } else if (gcode == LG_DIAG) {
+                        if (s.cls == MC_REAL) L(MC_REAL, MC_DIAG);
+                        else if (s.cls == MC_RIRI) L(MC_RIRI, MC_DIAG);
+                        else if (s.cls == MC_DIAG) L(MC_DIAG, MC_DIAG);
+                        else L(MC_DENSE, MC_DIAG);
                     } else {
                         if (s.cls == MC_REAL) L(MC_REAL, MC_DENSE);
                         else if (s.cls == MC_RIRI) L(MC_RIRI, MC_DENSE);
+                        else if (s.cls == MC_DIAG) L(MC_DIAG, MC_DENSE);
                         else L(MC_DENSE, MC_DENSE);
                     }
                 }
@@ -688,6 +704,10 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
 #undef F
                         } else if (s.cls == MC_PY) {
 #define F(P) v = g_dot1<T, GB, P, MC_PY, false>(a, l, m, tc, eo, 0, 0)
+                            QSV_P1_CASES(F)
+#undef F
+                        } else if (s.cls == MC_DIAG) {
+#define F(P) v = g_dot1<T, GB, P, MC_DIAG, false>(a, l, m, tc, eo, 0, 0)
                             QSV_P1_CASES(F)
 #undef F
                         } else {

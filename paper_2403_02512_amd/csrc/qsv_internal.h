@@ -144,7 +144,7 @@ struct PauliGroupDev {
     int64_t col_off;  // first of the 64 per-index-bit parity columns in the aux array
 };
 // generator class code of a LAYER1 op (its lcval)
-enum LayerGen : uint32_t { LG_NONE = 0, LG_X = 1, LG_Y = 2, LG_DENSE = 3 };
+enum LayerGen : uint32_t { LG_NONE = 0, LG_X = 1, LG_Y = 2, LG_DENSE = 3, LG_DIAG = 4 };
 constexpr int PAULI_LUT_MIN_TERMS = 16;
 constexpr int PAULI_LUT_MAX_TABLES = 12;  // 12 x 256 x 16 B = 48 KiB of LDS
 struct PauliTermDev {

@@ -301,15 +301,17 @@ def _group(prog, st, g, subs, tp, tl, base, slots, T):
                 slots[st["slot_base"] + s["slot"]] += v.sum()
         elif kind == OP_LAYER1:
             # per position P ascending: optional inner product, then the 2x2
-            gcode = s["lcval"]  # 0 none, 1 X, 2 Y, 3 dense
-            assert gcode in (0, 1, 2, 3) and (gcode == 0) == (s["lcmask"] == 0)
-            nc = 8 if gcode == 3 else 4
+            gcode = s["lcval"]  # 0 none, 1 X, 2 Y, 3 dense, 4 real diagonal
+            assert gcode in (0, 1, 2, 3, 4) and (gcode == 0) == (s["lcmask"] == 0)
+            nc = 8 if gcode in (3, 4) else 4
             cf = _coef(prog, s["coff"], nc * GB)
             for P in range(GB):
                 mp = cf[P * nc:(P + 1) * nc]
-                M = mp[4:8] if gcode == 3 else mp[:4]
+                M = mp[4:8] if gcode in (3, 4) else mp[:4]
                 if s["cls"] == MC_REAL:
                     assert np.all(M.imag == 0)
+                elif s["cls"] == MC_DIAG:
+                    assert M[1] == 0 and M[2] == 0
                 elif s["cls"] == MC_RIRI:
                     assert M[0].imag == 0 and M[3].imag == 0 and M[1].real == 0 and M[2].real == 0
                 pairs = [(e0, e0 | (1 << P)) for e0 in range(E) if not e0 & (1 << P)]
@@ -317,6 +319,8 @@ def _group(prog, st, g, subs, tp, tl, base, slots, T):
                     assert l is not None
                     G = {1: np.array([0, 1, 1, 0], dtype=complex),
                          2: np.array([0, -1j, 1j, 0])}.get(gcode, mp[:4])
+                    if gcode == 4:
+                        assert G[1] == 0 and G[2] == 0 and G[0].imag == 0 and G[3].imag == 0
                     v = 0.0
                     for e0, e1 in pairs:
                         p0, p1 = a[:, e0], a[:, e1]
