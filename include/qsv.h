@@ -307,9 +307,14 @@ qsv_status qsv_batch_run(qsv_batch *b, const double *params, double *expval, dou
  * chosen per workload): the forward program (reset to |0..0> + ops) for
  * every width from 2^10 amplitudes up to the LDS limit, then, if obs and
  * parameters are given, the adjoint sweep for every two-vector width from
- * 2^9 up.  The fastest widths are set on the context and returned.  The
- * state's contents are overwritten (it ends as the circuit's output state).
- * On error the context options are left unchanged. */
+ * 2^9 up.  At the chosen widths it then times the whole program (forward,
+ * and the adjoint sweep when given) with one-qubit layers on and off
+ * (QSV_OPT_LAYERS) and with the default, one fewer and one more always-local
+ * low index bits (QSV_OPT_LOW_BITS).  The fastest widths are returned; all
+ * four choices are set on the context, where the single-circuit entry points
+ * and qsv_batch_run (which plans every circuit with the context's options)
+ * use them.  The state's contents are overwritten (it ends as the circuit's
+ * output state).  On error the context options are left unchanged. */
 qsv_status qsv_autotune(qsv_state *s, const qsv_op *ops, size_t n_ops, const double *params, size_t n_params,
                         const double *matrices, size_t n_matrix_elems, const qsv_pauli_sum *obs, size_t n_obs,
                         int32_t *tile_bits, int32_t *tile_bits_adj);

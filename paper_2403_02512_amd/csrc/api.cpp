@@ -449,6 +449,14 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
     if (R > (1 << TILE_MAX_R_LOG2)) fail(QSV_ERR_UNSUPPORTED, "tile too large");
     TileArgs& a = st.ta;
     std::memset(&a, 0, sizeof a);
+    a.out_scale = 1.0;
+    // Factored layers (classes RIRI_D/O, REAL_D/O) run a scaled copy of their
+    // matrices, so the tile holds the true amplitudes divided by tscale (the
+    // product of the factors applied so far in the pass, the same for every
+    // tile and for phi and lambda); an inner product taken at that point is
+    // tscale^2 times too small, which its slot coefficient undoes, and the
+    // write-back multiplies by the final tscale.
+    double tscale = 1.0;
     a.outer = make_expand(std::vector<int>(sb, sb + b));
     a.n_tiles = 1ull << (n - b);
     for (int r = 0; r < R; ++r) a.offhi[r] = deposit((uint64_t)r << nthr_log2, sb, b);
@@ -597,7 +605,7 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
         if (pr.is_dot()) {
             op.slot = nslots++;
             const Factor& f = F[pr.f];
-            P.slot_param.push_back({f.param, f.coef});
+            P.slot_param.push_back({f.param, f.coef * tscale * tscale});
             if (Q) op.aux = dslot++;
         }
         if (pr.kind == Proto::ZPHASE || pr.kind == Proto::DOTZSUM) {
@@ -801,6 +809,60 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
                             }
                         }
                         op.cls = real ? MC_REAL : (riri ? MC_RIRI : (diag ? MC_DIAG : MC_DENSE));
+                        // Factored form of an RX- or RY-like layer (every
+                        // position, identities included, with equal diagonal
+                        // entries): divide each position's matrix by its
+                        // diagonal entry (D form, |entry| >= 1/2) or by its
+                        // off-diagonal entry (O form, no identities), so that
+                        // one FMA per component applies it; the factors go
+                        // into the pass's scale.  Slot coefficients of the
+                        // layer's inner products get the scale before their
+                        // position's matrix.
+                        std::vector<double> fac(GB, 1.0);
+                        const bool fr = op.cls == MC_RIRI && (gcls == LG_NONE || gcls == LG_X);
+                        const bool fy = op.cls == MC_REAL && (gcls == LG_NONE || gcls == LG_Y);
+                        if (fr || fy) {
+                            bool dok = true, ook = true;
+                            double prod_d = 1.0, prod_o = 1.0;
+                            for (int p = 0; p < GB; ++p) {
+                                const auto& m = mats[p];
+                                const bool eqd = m[0] == m[3] && m[0].imag() == 0.0;
+                                dok = dok && eqd && std::abs(m[0].real()) >= 0.5;
+                                prod_d *= std::abs(m[0].real());
+                                // O: RIRI needs m01 == m10 = i q; REAL needs m01 == -m10
+                                const double off = fr ? m[2].imag() : m[2].real();
+                                const bool offok = fr ? (m[1] == m[2]) : (m[1] == -m[2]);
+                                ook = ook && eqd && offok && std::abs(off) >= 0.5;
+                                prod_o *= std::abs(off);
+                            }
+                            // keep the pass scale well inside both precisions' range
+                            dok = dok && tscale * prod_d >= 1e-18;
+                            ook = ook && tscale * prod_o >= 1e-18;
+                            if (dok || ook) {
+                                for (int p = 0; p < GB; ++p) {
+                                    auto& m = mats[p];
+                                    const cd f = dok ? m[0] : (fr ? cd(m[2].imag(), 0.0) : m[2]);
+                                    fac[p] = f.real();
+                                    for (auto& x : m) x /= f;
+                                    // exact unit entries (the kernel does not read them)
+                                    if (dok) m[0] = m[3] = 1.0;
+                                    else if (fr) m[1] = m[2] = cd(0.0, 1.0);
+                                    else m[1] = -1.0, m[2] = 1.0;
+                                }
+                                op.cls = fr ? (dok ? MC_RIRI_D : MC_RIRI_O) : (dok ? MC_REAL_D : MC_REAL_O);
+                            }
+                        }
+                        // the kernel takes each position's inner product, then
+                        // applies its matrix: slot scales in that order
+                        {
+                            size_t sp = P.slot_param.size();
+                            for (int p = 0; p < GB; ++p)
+                                if (ld[p] >= 0) --sp;
+                            for (int p = 0; p < GB; ++p) {
+                                if (ld[p] >= 0) P.slot_param[sp++].second *= tscale * tscale;
+                                tscale *= fac[p];
+                            }
+                        }
                         op.lcval = (uint32_t)gcls;
                         op.coff = (int64_t)P.coef.size();
                         for (int p = 0; p < GB; ++p) {
@@ -943,6 +1005,7 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
     }
     a.nops = (int)P.tops.size() - a.op0;
     a.nslots = nslots;
+    a.out_scale = tscale;
     a.zt_off = (int64_t)P.coef.size();
     a.zt_n = (int)ztab.size();
     for (auto& zp : zpatch) {
@@ -1874,9 +1937,10 @@ qsv_status qsv_plan_json(int n, qsv_dtype dt, const qsv_op* ops, size_t n_ops, c
             } else if (st.type == Step::TILE) {
                 const TileArgs& a = st.ta;
                 add(",\"b\":%d,\"nthr\":%d,\"R\":%d,\"grid\":%d,\"op0\":%d,\"nops\":%d,\"nslots\":%d,\"slot_base\":%d,"
-                    "\"generic\":%d,\"n_tiles\":%llu,\"n_outer\":%d,\"lds\":%zu,\"flags\":%d,\"sb\":[",
+                    "\"generic\":%d,\"n_tiles\":%llu,\"n_outer\":%d,\"lds\":%zu,\"flags\":%d,"
+                    "\"out_scale\":%.17g,\"sb\":[",
                     a.b, st.nthr, st.R, st.grid, a.op0, a.nops, a.nslots, st.slot_base, (int)st.generic,
-                    (unsigned long long)a.n_tiles, a.n_outer, st.lds, a.flags);
+                    (unsigned long long)a.n_tiles, a.n_outer, st.lds, a.flags, a.out_scale);
                 for (int j = 0; j < a.b; ++j) add(j ? ",%d" : "%d", a.sb[j]);
                 js += "],\"offhi\":[";
                 for (int r = 0; r < st.R; ++r) add(r ? ",%llu" : "%llu", (unsigned long long)a.offhi[r]);
@@ -2810,6 +2874,7 @@ extern "C" qsv_status qsv_autotune(qsv_state* s, const qsv_op* ops, size_t n_ops
             return best;
         };
         const int64_t keep_f = c->opt_tile_bits, keep_a = c->opt_tile_bits_adj;
+        const int64_t keep_layers = c->opt_layers, keep_low = c->opt_low_bits;
         // candidates: tiles from 2^10 amplitudes up to the LDS limit of two
         // blocks (one vector) or one block (two vectors) per CU, capped at n
         const int fmax = std::min(n, c128 ? 13 : 13), amax = std::min(n, c128 ? 12 : 13);
@@ -2839,9 +2904,35 @@ extern "C" qsv_status qsv_autotune(qsv_state* s, const qsv_op* ops, size_t n_ops
                     if (t < ta) ta = t, best_a = b;
                 }
             }
+            // then the fusion form at those widths: one-qubit layers on or
+            // off, and the number of lowest index bits every pass keeps in
+            // its tile (the default, one fewer, one more), timed on the whole
+            // program (forward, and the adjoint sweep when it is given)
+            c->opt_tile_bits_adj = best_a ? best_a : keep_a;
+            const int low_def = c128 ? 4 : 5;
+            double tbest = 1e300;
+            int64_t best_layers = 1, best_low = 0;
+            std::vector<double> jac2(n_obs * n_params), ev2(n_obs);
+            for (int64_t layers : {1, 0})
+                for (int64_t low : {(int64_t)0, (int64_t)low_def - 1, (int64_t)low_def + 1}) {
+                    c->opt_layers = layers;
+                    c->opt_low_bits = low;
+                    const double t = seconds([&] {
+                        check(qsv_state_reset(s, 0));
+                        check(qsv_apply(s, ops, n_ops, params, n_params, matrices, n_mat));
+                        if (n_obs && n_params)
+                            check(qsv_adjoint_jacobian(s, ops, n_ops, params, n_params, matrices, n_mat, obs,
+                                                       n_obs, jac2.data(), ev2.data(), 0));
+                    });
+                    if (t < tbest) tbest = t, best_layers = layers, best_low = low;
+                }
+            c->opt_layers = best_layers;
+            c->opt_low_bits = best_low;
         } catch (...) {
             c->opt_tile_bits = keep_f;
             c->opt_tile_bits_adj = keep_a;
+            c->opt_layers = keep_layers;
+            c->opt_low_bits = keep_low;
             throw;
         }
         c->opt_tile_bits = best_f;

@@ -328,6 +328,22 @@ __device__ __forceinline__ void bfly(const cx<T>* m, cx<T>& x0, cx<T>& x1) {
     } else if (CLS == MC_DIAG) {
         x0 = cmul(m[0], a0);
         x1 = cmul(m[3], a1);
+    } else if (CLS == MC_RIRI_D) {  // [[1, i p], [i q, 1]]: one FMA per component
+        const T p = m[1].im, q = m[2].im;
+        x0 = {a0.re - p * a1.im, a0.im + p * a1.re};
+        x1 = {a1.re - q * a0.im, a1.im + q * a0.re};
+    } else if (CLS == MC_RIRI_O) {  // [[u, i], [i, v]]
+        const T u = m[0].re, v = m[3].re;
+        x0 = {u * a0.re - a1.im, u * a0.im + a1.re};
+        x1 = {v * a1.re - a0.im, v * a1.im + a0.re};
+    } else if (CLS == MC_REAL_D) {  // [[1, p], [q, 1]]
+        const T p = m[1].re, q = m[2].re;
+        x0 = {a0.re + p * a1.re, a0.im + p * a1.im};
+        x1 = {a1.re + q * a0.re, a1.im + q * a0.im};
+    } else if (CLS == MC_REAL_O) {  // [[u, -1], [1, v]]
+        const T u = m[0].re, v = m[3].re;
+        x0 = {u * a0.re - a1.re, u * a0.im - a1.im};
+        x1 = {a0.re + v * a1.re, a0.im + v * a1.im};
     } else if (CLS == MC_RIRI) {  // [[r0, i q1], [i q2, r3]]
         const T r0 = m[0].re, q1 = m[1].im, q2 = m[2].im, r3 = m[3].re;
         x0 = {r0 * a0.re - q1 * a1.im, r0 * a0.im + q1 * a1.re};
@@ -641,17 +657,25 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
                 };
 #define L(C, G) g_layer<T, TWO, GB, C, G>(a, l, m, s.lcmask, sink)
                 if (gcode == LG_NONE) {
-                    if (s.cls == MC_REAL) L(MC_REAL, -1);
+                    if (s.cls == MC_RIRI_D) L(MC_RIRI_D, -1);
+                    else if (s.cls == MC_RIRI_O) L(MC_RIRI_O, -1);
+                    else if (s.cls == MC_REAL_D) L(MC_REAL_D, -1);
+                    else if (s.cls == MC_REAL_O) L(MC_REAL_O, -1);
+                    else if (s.cls == MC_REAL) L(MC_REAL, -1);
                     else if (s.cls == MC_RIRI) L(MC_RIRI, -1);
                     else if (s.cls == MC_DIAG) L(MC_DIAG, -1);
                     else L(MC_DENSE, -1);
                 } else if constexpr (TWO) {
                     if (gcode == LG_X) {
-                        if (s.cls == MC_REAL) L(MC_REAL, MC_PX);
+                        if (s.cls == MC_RIRI_D) L(MC_RIRI_D, MC_PX);
+                        else if (s.cls == MC_RIRI_O) L(MC_RIRI_O, MC_PX);
+                        else if (s.cls == MC_REAL) L(MC_REAL, MC_PX);
                         else if (s.cls == MC_RIRI) L(MC_RIRI, MC_PX);
                         else L(MC_DENSE, MC_PX);
                     } else if (gcode == LG_Y) {
-                        if (s.cls == MC_REAL) L(MC_REAL, MC_PY);
+                        if (s.cls == MC_REAL_D) L(MC_REAL_D, MC_PY);
+                        else if (s.cls == MC_REAL_O) L(MC_REAL_O, MC_PY);
+                        else if (s.cls == MC_REAL) L(MC_REAL, MC_PY);
                         else if (s.cls == MC_RIRI) L(MC_RIRI, MC_PY);
                         else L(MC_DENSE, MC_PY);
                     } else if (gcode == LG_DIAG) {
@@ -936,12 +960,20 @@ __device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
             __syncthreads();
         }
         const bool nt = (a.flags & TILE_NT) != 0;
+        const T osc = (T)a.out_scale;
+        const bool scaled = osc != T(1);  // factored layers in the pass
         for (int r0 = 0; r0 < R; r0 += LCH) {
 #pragma unroll
             for (int r = 0; r < LCH; ++r) {
                 const uint64_t g = base | offlo | a.offhi[r0 + r];
-                st_amp(phi + g, c.tp[stid + (r0 + r) * nthr], nt);
-                if (TWO) st_amp(lam + g, c.tl[stid + (r0 + r) * nthr], nt);
+                cx<T> vp = c.tp[stid + (r0 + r) * nthr];
+                if (scaled) vp = {vp.re * osc, vp.im * osc};
+                st_amp(phi + g, vp, nt);
+                if (TWO) {
+                    cx<T> vl = c.tl[stid + (r0 + r) * nthr];
+                    if (scaled) vl = {vl.re * osc, vl.im * osc};
+                    st_amp(lam + g, vl, nt);
+                }
             }
         }
         __syncthreads();
@@ -1067,11 +1099,19 @@ __device__ __forceinline__ void tile_body_ws(const cx<T>* phi_src, cx<T>* phi, c
                 oi += op.m;
                 __syncthreads();
             }
+            const T osc = (T)a.out_scale;
+            const bool scaled = osc != T(1);  // factored layers in the pass
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const uint64_t g = base | offlo | a.offhi[r];
-                st_amp(phi + g, c.tp[stid + r * NT], nt);
-                if (TWO) st_amp(lam + g, c.tl[stid + r * NT], nt);
+                cx<T> vp = c.tp[stid + r * NT];
+                if (scaled) vp = {vp.re * osc, vp.im * osc};
+                st_amp(phi + g, vp, nt);
+                if (TWO) {
+                    cx<T> vl = c.tl[stid + r * NT];
+                    if (scaled) vl = {vl.re * osc, vl.im * osc};
+                    st_amp(lam + g, vl, nt);
+                }
             }
             __syncthreads();
             cur ^= 1;

@@ -54,7 +54,11 @@ enum TOpKind : int32_t {
 // REAL = all entries real (H, RY), RIRI = real diagonal and imaginary
 // off-diagonal (RX), PX / PY = exactly Pauli X / Y (inner-product generators).
 enum MatClass : int32_t { MC_DENSE = 0, MC_DIAG = 1, MC_ANTI = 2, MC_MID = 3, MC_REAL = 4, MC_RIRI = 5, MC_PX = 6,
-                          MC_PY = 7 };
+                          MC_PY = 7,
+                          // factored layer classes (scaled so that one entry pair is exactly 1 or +-i; the
+                          // common factor is carried as a tile-wide scale): RIRI_D [[1, i p], [i q, 1]],
+                          // RIRI_O [[u, i], [i, v]], REAL_D [[1, p], [q, 1]], REAL_O [[u, -1], [1, v]]
+                          MC_RIRI_D = 8, MC_RIRI_O = 9, MC_REAL_D = 10, MC_REAL_O = 11 };
 
 struct TOp {
     int32_t kind, cls, k, slot;
@@ -91,6 +95,7 @@ struct TileArgs {
     uint64_t basis;
     int32_t n_zop;          // Z-parity ops inside register groups (their tb[5] numbers them)
     int32_t pad_z;
+    double out_scale;       // the pass's factored layers leave the tile scaled by 1 / out_scale
 };
 constexpr int32_t TILE_SYNTH = 1;
 constexpr int32_t TILE_NT = 2;  // write back with non-temporal stores

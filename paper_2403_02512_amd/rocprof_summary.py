@@ -18,6 +18,9 @@
       counter bytes beside algorithmic bytes per case of a per-wire sweep
       (bench.py --sweep --sweep-markers), calibrated by a state copy
 
+  python -m paper_2403_02512_amd.rocprof_summary counters <pmc csv>... --elements N --cmd "<commands>"
+      mean SQ counter values per dispatch and kernel, instructions per amplitude
+
   python -m paper_2403_02512_amd.rocprof_summary sweep-table <sweep log> --cmd "<command>"
       per-wire fractions of the HBM peak from a sweep's JSON lines
 """
@@ -200,6 +203,28 @@ def sweep_table(sweep_log: str, cmd: str) -> str:
     return "\n".join(out) + "\n"
 
 
+def counters(csvs, elements: float, cmd: str) -> str:
+    """Mean per dispatch of every SQ counter in the given --pmc runs, per
+    kernel kind, and per-amplitude instruction counts (wave instructions x 64
+    lanes / elements; elements = amplitude indices one dispatch covers)."""
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for path in csvs:
+        for r in csv.DictReader(open(path)):
+            vals[kind_of(r["Kernel_Name"]) + " " + short(r["Kernel_Name"]).replace(" ", "")][r["Counter_Name"]].append(
+                float(r["Counter_Value"]))
+    out = [f"commands: {cmd}", f"elements per dispatch: {elements:.0f}", "",
+           "| kernel | counter | dispatches | mean per dispatch | x64 / elements |", "|---|---|---|---|---|"]
+    for k in sorted(vals):
+        if not k.startswith(("tile", "pauli", "init")):
+            continue
+        for cn in sorted(vals[k]):
+            v = vals[k][cn]
+            m = sum(v) / len(v)
+            per = f"{m * 64 / elements:.2f}" if cn.startswith("SQ_INSTS") else ""
+            out.append(f"| {k} | {cn} | {len(v)} | {m:.4e} | {per} |")
+    return "\n".join(out) + "\n"
+
+
 def read_traffic(path: str):
     """{kind: traffic bytes per dispatch} if the summary was taken on the
     current library sources, else None."""
@@ -234,12 +259,18 @@ def main(argv=None):
     c.add_argument("sweep_log")
     c.add_argument("--reps", type=int, default=3)
     c.add_argument("--cmd", required=True)
+    q = sub.add_parser("counters")
+    q.add_argument("csv", nargs="+")
+    q.add_argument("--elements", type=float, required=True)
+    q.add_argument("--cmd", required=True)
     t = sub.add_parser("sweep-table")
     t.add_argument("sweep_log")
     t.add_argument("--cmd", required=True)
     args = ap.parse_args(argv)
     if args.mode == "stats":
         sys.stdout.write(stats(args.csv, args.cmd))
+    elif args.mode == "counters":
+        sys.stdout.write(counters(args.csv, args.elements, args.cmd))
     elif args.mode == "sweep-table":
         sys.stdout.write(sweep_table(args.sweep_log, args.cmd))
     elif args.mode == "sweep-traffic":

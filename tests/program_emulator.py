@@ -12,7 +12,7 @@ import numpy as np
 
 OP_APPLY1, OP_APPLY2, OP_APPLYK, OP_DIAG, OP_ZPHASE, OP_DOT1, OP_DOT2, OP_DOTK, OP_DOTDIAG, OP_DOTZSUM, OP_GROUP, \
     OP_LAYER1 = range(1, 13)
-MC_DENSE, MC_DIAG, MC_ANTI, MC_MID, MC_REAL, MC_RIRI, MC_PX, MC_PY = range(8)
+MC_DENSE, MC_DIAG, MC_ANTI, MC_MID, MC_REAL, MC_RIRI, MC_PX, MC_PY, MC_RIRI_D, MC_RIRI_O, MC_REAL_D, MC_REAL_O = range(12)
 
 
 def _coef(prog, off, cnt):
@@ -185,9 +185,11 @@ def _tile(prog, st, phi, lam, slots):
                 continue
             _standalone(prog, st, op, tp, tl, base, dep, slots, T)
             i += 1
-        phi[g] = tp
+        # factored layers leave the tile divided by the pass's scale
+        sc = st.get("out_scale", 1.0)
+        phi[g] = tp * sc
         if two:
-            lam[g] = tl
+            lam[g] = tl * sc
 
 
 def _tile_parity(w, off, n_outer, T):
@@ -312,6 +314,12 @@ def _group(prog, st, g, subs, tp, tl, base, slots, T):
                     assert np.all(M.imag == 0)
                 elif s["cls"] == MC_DIAG:
                     assert M[1] == 0 and M[2] == 0
+                elif s["cls"] in (MC_RIRI_D, MC_REAL_D):  # factored: unit diagonal
+                    assert M[0] == 1 and M[3] == 1
+                elif s["cls"] == MC_RIRI_O:
+                    assert M[1] == 1j and M[2] == 1j
+                elif s["cls"] == MC_REAL_O:
+                    assert M[1] == -1 and M[2] == 1
                 elif s["cls"] == MC_RIRI:
                     assert M[0].imag == 0 and M[3].imag == 0 and M[1].real == 0 and M[2].real == 0
                 pairs = [(e0, e0 | (1 << P)) for e0 in range(E) if not e0 & (1 << P)]

@@ -369,3 +369,34 @@ def test_deep_narrow_adjoint_many_slots(ctx, dt):
     assert_rel_close(jac, oracle.adjoint_jacobian(psi, ops, params, obs), jac_bound(ops, p, obs), dt, "jacobian")
     assert_rel_close(ev, oracle.expval(psi, obs), obs_scale(obs), dt, "expval")
     st.close()
+
+
+@pytest.mark.parametrize("gate", ["RX", "RY"])
+@pytest.mark.parametrize("dt", DTYPES)
+def test_factored_layers(ctx, gate, dt):
+    """RX / RY layers on the factored kernel classes (one FMA per component,
+    the factors carried as the pass's scale), at angles that need either form
+    (cos(a/2) = 0 at a = pi, sin = 0 at a = 0), with the default and with
+    narrow tiles; forward states and adjoint gradients against the oracle."""
+    n = 12
+    angles = [0.0, np.pi, 0.3, 2.5, 4.0, 5.9]
+    ops = []
+    for rep in range(4):
+        for q in range(n):
+            ops.append(W.op(gate, [q], ((q + rep) % len(angles), 1.0)))
+        ops.append(W.op("CNOT", [rep % n, (rep + 5) % n]))
+    params = np.array(angles)
+    obs = W.random_observables(n, np.random.default_rng(7), n_obs=1, n_terms=4)
+    psi = oracle.apply(n, ops, params)
+    want = oracle.adjoint_jacobian(psi, ops, params, obs)
+    for opts in ({}, {qsv.OPT_TILE_BITS: 7, qsv.OPT_TILE_BITS_ADJ: 7}):
+        reset_options(ctx)
+        for k, v in opts.items():
+            ctx.set_option(k, v)
+        st = qsv.State(ctx, n, dt)
+        qsv.apply(st, ops, params)
+        assert_state_close(st.to_numpy(), psi, TOL[dt], f"state opts={opts}", dt)
+        jac, ev = qsv.adjoint_jacobian(st, ops, params, obs)
+        assert_rel_close(jac, want, jac_bound(ops, len(angles), obs), dt, f"jacobian opts={opts}")
+        st.close()
+    reset_options(ctx)

@@ -97,3 +97,36 @@ def test_u3_brickwall_adjoint_program(opts):
     g, phi = emulate_adjoint(n, c.ops, c.params, psi, lam, **opts)
     np.testing.assert_allclose(g, oracle.adjoint_jacobian(psi, c.ops, c.params, c.observables)[0], atol=1e-11)
     np.testing.assert_allclose(phi, oracle.zero_state(n), atol=1e-12)
+
+
+@pytest.mark.parametrize("gate", ["RX", "RY"])
+def test_factored_layers(gate):
+    """RX / RY layers run in the factored classes (matrices divided by their
+    diagonal or off-diagonal entry, the factors carried as the pass's scale
+    and undone at write-back and in the slot coefficients), at angles where
+    either form is the one that applies (cos(a/2) = 0 at a = pi, sin = 0 at
+    a = 0), forward and adjoint."""
+    from paper_2403_02512_amd import qsv
+    n = 6
+    angles = [0.0, np.pi, 0.3, 2.5, 4.0, 5.9]
+    ops = []
+    for rep in range(3):
+        for q in range(n):
+            ops.append(W.op(gate, [q], ((q + rep) % len(angles), 1.0)))
+        ops.append(W.op("CNOT", [rep % n, (rep + 1) % n]))
+    params = np.array(angles)
+    obs = W.random_observables(n, np.random.default_rng(7), n_obs=1, n_terms=4)
+    psi0 = W.random_state(n, 4)
+    got = emulate_apply(n, ops, params, psi0, tile_bits=6, low_bits=2)
+    np.testing.assert_allclose(got, oracle.apply(n, ops, params, psi=psi0), atol=1e-12)
+    psi = oracle.apply(n, ops, params)
+    g, phi = emulate_adjoint(n, ops, params, psi, oracle.apply_pauli_sum(psi, obs[0]), tile_bits=6, low_bits=2)
+    np.testing.assert_allclose(g, oracle.adjoint_jacobian(psi, ops, params, obs)[0], atol=1e-11)
+    np.testing.assert_allclose(phi, oracle.zero_state(n), atol=1e-12)
+    # both factored forms occur in the lowered programs
+    classes = set()
+    for adj in (False, True):
+        pj = qsv.plan_json(n, ops, params, adjoint=adj, tile_bits=6, low_bits=2)
+        classes |= {o["cls"] for o in pj["tops"] if o["kind"] == 12}
+    d, o = (8, 9) if gate == "RX" else (10, 11)
+    assert d in classes and o in classes, classes
