@@ -407,13 +407,17 @@ __device__ __forceinline__ double g_dot1(const cx<T>* a, const cx<T>* l, const c
         if (e0 & (1 << P)) continue;
         const int e1 = e0 | (1 << P);
         if (CTRL && ((tc | eo[e0]) & lcm) != lcv) continue;
+        // the X, Y and diagonal classes accumulate in fused multiply-add chains
         if (CLS == MC_PX) {         // G = X: Im(l0* p1) + Im(l1* p0)
-            acc += im_conj_mul(l[e0], a[e1]) + im_conj_mul(l[e1], a[e0]);
+            acc = acc_im_conj_mul(acc_im_conj_mul(acc, l[e0], a[e1]), l[e1], a[e0]);
         } else if (CLS == MC_DIAG) {  // G = diag(g0, g3), real
-            acc += (double)g0.re * im_conj_mul(l[e0], a[e0]) + (double)g3.re * im_conj_mul(l[e1], a[e1]);
+            acc = __builtin_fma((double)g0.re, im_conj_mul(l[e0], a[e0]), acc);
+            acc = __builtin_fma((double)g3.re, im_conj_mul(l[e1], a[e1]), acc);
         } else if (CLS == MC_PY) {  // G = Y: Re(l1* p0) - Re(l0* p1)
-            acc += (double)l[e1].re * a[e0].re + (double)l[e1].im * a[e0].im -
-                   (double)l[e0].re * a[e1].re - (double)l[e0].im * a[e1].im;
+            acc = __builtin_fma((double)l[e1].re, (double)a[e0].re, acc);
+            acc = __builtin_fma((double)l[e1].im, (double)a[e0].im, acc);
+            acc = __builtin_fma(-(double)l[e0].re, (double)a[e1].re, acc);
+            acc = __builtin_fma(-(double)l[e0].im, (double)a[e1].im, acc);
         } else {
             acc += im_conj_mul(l[e0], cmad(g0, a[e0], cmul(g1, a[e1])));
             acc += im_conj_mul(l[e1], cmad(g2, a[e0], cmul(g3, a[e1])));
@@ -763,7 +767,8 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
                         const uint64_t pc = zbits(s, si);
 #pragma unroll
                         for (int e = 0; e < E; ++e)
-                            v += (double)(s.m - 2 * (int)__popcll(pc ^ z[s.m + nsub + e])) * im_conj_mul(l[e], a[e]);
+                            v = __builtin_fma((double)(s.m - 2 * (int)__popcll(pc ^ z[s.m + nsub + e])),
+                                              im_conj_mul(l[e], a[e]), v);
                     }
                     if (inloop) row_flush(v, s.slot);
                     else acc.add(s.aux, v);

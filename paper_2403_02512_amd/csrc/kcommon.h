@@ -43,6 +43,12 @@ __device__ __forceinline__ double im_conj_mul(cx<T> l, cx<T> v) {
     return (double)l.re * (double)v.im - (double)l.im * (double)v.re;
 }
 
+// acc + Im(conj(l) v) as two fused multiply-adds
+template <typename T>
+__device__ __forceinline__ double acc_im_conj_mul(double acc, cx<T> l, cx<T> v) {
+    return __builtin_fma((double)l.re, (double)v.im, __builtin_fma(-(double)l.im, (double)v.re, acc));
+}
+
 // Store of one amplitude.  nt: a non-temporal (streaming) store, which asks
 // the caches not to keep the line: the state is written once per pass and
 // not read again before it is evicted (the paper's streaming stores, Sec.
