@@ -684,6 +684,8 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
             op.cls = f.k == 1 ? classify1(mm) : (f.k == 2 ? classify2(mm) : MC_DENSE);
             // grouped kernels: dense / anti / mid, and diagonal for one qubit
             if (Q && op.cls == MC_DIAG && f.k != 1) op.cls = MC_DENSE;
+            // exactly X (a CNOT's target): a register swap in a group
+            if (Q && f.k == 1 && op.cls == MC_ANTI && mm[1] == 1.0 && mm[2] == 1.0) op.cls = MC_PX;
         }
         for (auto& x : mm) P.coef.push_back(x);
         P.tops.push_back(op);

@@ -318,7 +318,10 @@ __device__ __forceinline__ void tile_dot(const TileCtx<T, TWO, R>& c, const TOp&
 template <typename T, int CLS>
 __device__ __forceinline__ void bfly(const cx<T>* m, cx<T>& x0, cx<T>& x1) {
     const cx<T> a0 = x0, a1 = x1;
-    if (CLS == MC_ANTI) {
+    if (CLS == MC_PX) {  // exactly X: the pair trades places (no arithmetic)
+        x0 = a1;
+        x1 = a0;
+    } else if (CLS == MC_ANTI) {
         x0 = cmul(m[1], a1);
         x1 = cmul(m[2], a0);
     } else if (CLS == MC_REAL) {
@@ -602,8 +605,16 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
             switch (s.kind) {
             case OP_APPLY1: {
                 const bool ctrl = s.lcmask != 0;
-                if (ctrl) {
+                if (ctrl && s.cls == MC_PX) {
+#define F(P) g_apply1<T, TWO, GB, P, MC_PX, true>(a, l, m, tc, eo, s.lcmask, s.lcval)
+                    QSV_P1_CASES(F)
+#undef F
+                } else if (ctrl) {
 #define F(P) g_apply1<T, TWO, GB, P, MC_DENSE, true>(a, l, m, tc, eo, s.lcmask, s.lcval)
+                    QSV_P1_CASES(F)
+#undef F
+                } else if (s.cls == MC_PX) {
+#define F(P) g_apply1<T, TWO, GB, P, MC_PX, false>(a, l, m, tc, eo, 0, 0)
                     QSV_P1_CASES(F)
 #undef F
                 } else if (s.cls == MC_ANTI) {
