@@ -1230,7 +1230,7 @@ struct DevT {};
 // place for its first pass; nullptr: phi itself).  The first step must then be
 // a tile pass.
 void run_program(qsv_ctx* c, const Program& P, qsv_dtype dt, int n, void* phi, void* lam, double* slots,
-                 int slot_offset, const void* phi_src = nullptr) {
+                 int slot_offset, const void* phi_src = nullptr, double* lamz_ev = nullptr) {
     const bool c128 = dt == QSV_C128;
     const size_t cb = c128 ? 16 : 8;
     if (phi_src && (P.steps.empty() || P.steps[0].type != Step::TILE))
@@ -1252,6 +1252,11 @@ void run_program(qsv_ctx* c, const Program& P, qsv_dtype dt, int n, void* phi, v
                 Timed tr(c, KK_REDUCE, 8.0 * st.nslots * st.grid);
                 tr.done(launch_reduce(c->stream, (const double*)c->partials.p, st.grid, st.nslots,
                                       slots + slot_offset + st.slot_base));
+            }
+            if ((st.ta.flags & TILE_LAMZ) && lamz_ev) {  // <H> from the pass that formed lambda
+                Timed tr(c, KK_REDUCE, 8.0 * st.grid);
+                tr.done(launch_reduce(c->stream, (const double*)c->partials.p + (size_t)st.nslots * st.grid,
+                                      st.grid, 1, lamz_ev));
             }
             continue;
         }
@@ -1487,6 +1492,44 @@ void adjoint_impl(qsv_state* s, const qsv_op* ops, size_t n_ops, const double* p
     Program P = build_program(plan_opts(c, s->dt, true), F, items, n, s->dt, true, true);
     const size_t nslot = P.slot_param.size();
 
+    // An observable that is c times a sum of Z strings (a diagonal H with one
+    // coefficient, e.g. a MaxCut cost) needs no separate lambda = H psi pass:
+    // the first reverse pass forms lambda = c (m - 2 |odd parities|) phi from
+    // the tile it loads and sums <H> on the way (one full read and write of
+    // the state fewer).
+    bool lamz = false;
+    // (the kernel form exists for the default two-vector tiles: 8 or 16
+    // elements per thread, group-only passes)
+    if (!vjp && n_rows == 1 && !P.steps.empty() && P.steps[0].type == Step::TILE &&
+        !(P.steps[0].ta.flags & TILE_WS) && !P.steps[0].generic && (P.steps[0].R == 8 || P.steps[0].R == 16) &&
+        P.steps[0].nthr == 256) {
+        const qsv_pauli_sum* h = rows[0];
+        lamz = h->n_terms > 0 && h->n_terms <= 64;
+        for (int64_t t = 0; t < h->n_terms && lamz; ++t)
+            lamz = h->x_mask[t] == 0 && h->coeff[t] == h->coeff[0];
+        if (lamz) {
+            Step& s0 = P.steps[0];
+            TileArgs& a = s0.ta;
+            std::vector<uint64_t> zm(h->z_mask, h->z_mask + h->n_terms);
+            a.flags |= TILE_LAMZ;
+            a.lamz_m = (int32_t)h->n_terms;
+            a.lamz_c = h->coeff[0];
+            a.lamz_woff = (int64_t)P.words.size();
+            const int nthr = 1 << a.nthr_log2, R = 1 << (a.b - a.nthr_log2);
+            uint64_t S = 0;
+            for (int j = 0; j < a.b; ++j) S |= 1ull << a.sb[j];
+            for (int t = 0; t < nthr; ++t) P.words.push_back(parity_bits_host(deposit((uint64_t)t, a.sb, a.nthr_log2), zm));
+            for (int r = 0; r < R; ++r) P.words.push_back(parity_bits_host(a.offhi[r], zm));
+            for (int g = 0; g < n; ++g)
+                if (!((S >> g) & 1)) P.words.push_back(parity_bits_host(1ull << g, zm));
+            s0.bytes -= (double)N * eb;  // lambda is not read
+            P.max_partials = std::max(P.max_partials, (size_t)(s0.nslots + 1) * s0.grid);
+            // one more slot accumulator (the <H> sums) in LDS
+            s0.lds = (size_t)tile_lds_bytes(a.b, true, (int)eb, s0.nslots + 1, a.zt_n, a.n_zop, a.n_outer);
+            if (s0.lds > (size_t)LDS_PER_CU) fail(QSV_ERR_UNSUPPORTED, "tile pass needs more LDS than a CU has");
+        }
+    }
+
     PauliTables T;
     if (vjp) {
         // lambda = sum_o cot_o H_o psi: one table with scaled coefficients
@@ -1520,14 +1563,16 @@ void adjoint_impl(qsv_state* s, const qsv_op* ops, size_t n_ops, const double* p
     if (vjp && expv)
         for (size_t o = 0; o < rows.size(); ++o) run_pauli(c, s->dt, n, T, (int)(o + 1), s->ptr, nullptr, evslots + o);
     for (size_t r = 0; r < n_rows; ++r) {
-        run_pauli(c, s->dt, n, T, (int)r, s->ptr, lam, vjp ? slots + n_rows * nslot + rows.size() : evslots + r);
+        if (!lamz)
+            run_pauli(c, s->dt, n, T, (int)r, s->ptr, lam, vjp ? slots + n_rows * nslot + rows.size() : evslots + r);
         // out of place: the first pass reads the state and writes phi (no copy)
         const bool oop = !inplace && !P.steps.empty();
         if (!inplace && P.steps.empty()) {
             Timed t(c, KK_COPY, 2.0 * N * eb);
             t.done(hipMemcpyAsync(phi, s->ptr, N * eb, hipMemcpyDeviceToDevice, c->stream));
         }
-        run_program(c, P, s->dt, n, phi, lam, slots, (int)(r * nslot), oop ? s->ptr : nullptr);
+        run_program(c, P, s->dt, n, phi, lam, slots, (int)(r * nslot), oop ? s->ptr : nullptr,
+                    lamz ? evslots + r : nullptr);
     }
     std::vector<double> host(n_rows * nslot + n_ev + 1);
     HIPCHK(hipMemcpyAsync(host.data(), slots, host.size() * 8, hipMemcpyDeviceToHost, c->stream));

@@ -855,7 +855,9 @@ __device__ __forceinline__ void tile_to_lds(cx<T>* buf, uint32_t stid, const cx<
 // described by a.  phi_src is where phi is read from (phi itself, or the
 // post-circuit state for an out-of-place first adjoint pass); with
 // TILE_SYNTH the tile is synthesised as the basis state a.basis instead.
-template <typename T, bool TWO, int LR, bool GEN>
+// LAMZ: the first reverse pass of a diagonal, uniform-coefficient observable
+// (TILE_LAMZ), compiled separately so that the other passes carry none of it.
+template <typename T, bool TWO, int LR, bool GEN, bool LAMZ = false>
 __device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
                                           cx<T>* __restrict__ lam, const TileArgs& a, const TOp* __restrict__ ops,
                                           const cx<T>* __restrict__ coef, const uint64_t* __restrict__ words,
@@ -883,9 +885,11 @@ __device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
     c.nthr = nthr;
     c.nwaves = nthr >= 64 ? nthr >> 6 : 1;
     c.nacc = nthr >= 64 ? nthr >> 4 : 1;
+    constexpr bool lamz = TWO && LAMZ;
+    const int nsl = a.nslots + (lamz ? 1 : 0);  // slot accumulators, with <H> last
     {
         // phase tables after the per-wave slot accumulators, 16-byte aligned
-        const size_t off = (64 + (size_t)a.nslots * c.nacc) * sizeof(double);
+        const size_t off = (64 + (size_t)nsl * c.nacc) * sizeof(double);
         cx<T>* zt = reinterpret_cast<cx<T>*>(reinterpret_cast<unsigned char*>(c.red) + ((off + 15) & ~(size_t)15));
         for (int i = tid; i < a.zt_n; i += nthr) zt[i] = coef[a.zt_off + i];
         c.ztab = zt;
@@ -915,13 +919,23 @@ __device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
     uint64_t offlo = 0;
     for (int j = 0; j < a.nthr_log2; ++j) offlo |= (uint64_t)((tid >> j) & 1) << a.sb[j];
     c.offlo = offlo;
-    for (int s = tid; s < a.nslots * c.nacc; s += nthr) c.sacc[s] = 0.0;
+    for (int s = tid; s < nsl * c.nacc; s += nthr) c.sacc[s] = 0.0;
+    if constexpr (lamz) __syncthreads();  // the <H> slot is added to before the first barrier of the tile loop
     const bool synth = (a.flags & TILE_SYNTH) != 0;
+
+    // TILE_LAMZ: lambda_g = c (m - 2 |odd parities of g|) phi_g and <H> = sum
+    // of conj(phi_g) lambda_g; the parity bits of g are the XOR of the tile's,
+    // the thread's and the register slot's parts (linear over GF(2)).  Each
+    // tile's <H> share goes to slot accumulator a.nslots (reduced per row like
+    // the inner products), so nothing stays live across the groups.
+    const uint64_t* lw = words + a.lamz_woff;
 
     for (uint64_t tile = blk; tile < a.n_tiles; tile += nblk) {
         const uint64_t base = expand_idx(tile, a.outer);
         c.base = base;
         c.tile = tile;
+        const uint64_t lam_par = lamz ? tile_parity(tile, lw + nthr + R, a.n_outer) ^ lw[tid] : 0;
+        double ev = 0.0;
         // global -> LDS in chunks of LCH elements per thread: LCH loads in
         // flight per thread without keeping all R values live in registers
         constexpr int LCH = R < 8 ? R : 8;
@@ -936,13 +950,31 @@ __device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
                 } else {
                     vp[r] = phi_src[g];
                 }
-                if (TWO) vl[r] = lam[g];
+                if (TWO && !lamz) vl[r] = lam[g];
+            }
+            if (lamz) {
+#pragma unroll
+                for (int r = 0; r < LCH; ++r) {
+                    const int w = a.lamz_m - 2 * (int)__popcll(lam_par ^ lw[nthr + r0 + r]);
+                    const T s = (T)(a.lamz_c * (double)w);
+                    vl[r] = {s * vp[r].re, s * vp[r].im};
+                    ev = __builtin_fma((double)w, (double)vp[r].re * vp[r].re + (double)vp[r].im * vp[r].im, ev);
+                }
             }
 #pragma unroll
             for (int r = 0; r < LCH; ++r) {
                 c.tp[stid + (r0 + r) * nthr] = vp[r];
                 if (TWO) c.tl[stid + (r0 + r) * nthr] = vl[r];
             }
+        }
+        if (lamz && nthr >= 64) {  // this tile's <H> share, per 16-lane row
+            ev += row_shr<1>(ev);
+            ev += row_shr<2>(ev);
+            ev += row_shr<4>(ev);
+            ev += row_shr<8>(ev);
+            if ((tid & 15) == 15) lds_add(&c.sacc[a.nslots * c.nacc + (tid >> 4)], ev * a.lamz_c);
+        } else if (lamz) {
+            block_add(ev * a.lamz_c, c.red, c.sacc + a.nslots * c.nacc, tid, nthr);
         }
         for (int k = tid; k < a.n_zop; k += nthr) {
             const uint64_t* col = zcol + (size_t)k * a.n_outer;
@@ -1000,6 +1032,11 @@ __device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
         for (int w = 0; w < c.nacc; ++w) v += c.sacc[s * c.nacc + w];
         partials[(uint64_t)s * nblk + blk] = v;
     }
+    if (lamz && tid == 0) {  // <H>: partial row nslots
+        double v = 0.0;
+        for (int w = 0; w < c.nacc; ++w) v += c.sacc[a.nslots * c.nacc + w];
+        partials[(uint64_t)a.nslots * nblk + blk] = v;
+    }
 }
 
 template <typename T, bool TWO, int LR, bool GEN>
@@ -1008,6 +1045,16 @@ __global__ __launch_bounds__(256, 2) void k_tile(const cx<T>* phi_src, cx<T>* ph
                                                  const cx<T>* __restrict__ coef, const uint64_t* __restrict__ words,
                                                  double* __restrict__ partials) {
     tile_body<T, TWO, LR, GEN>(phi_src, phi, lam, a, ops, coef, words, partials, blockIdx.x, gridDim.x);
+}
+
+// The first reverse pass with lambda formed from phi (TILE_LAMZ).
+template <typename T, int LR>
+__global__ __launch_bounds__(256, 2) void k_tile_lamz(const cx<T>* phi_src, cx<T>* phi, cx<T>* __restrict__ lam,
+                                                      const TileArgs a, const TOp* __restrict__ ops,
+                                                      const cx<T>* __restrict__ coef,
+                                                      const uint64_t* __restrict__ words,
+                                                      double* __restrict__ partials) {
+    tile_body<T, true, LR, false, true>(phi_src, phi, lam, a, ops, coef, words, partials, blockIdx.x, gridDim.x);
 }
 
 // Warp-specialised form of a group-only pass (every top-level op is a
@@ -1170,6 +1217,18 @@ template <typename T, bool TWO, int LR, bool GEN>
 static hipError_t launch_tile_lr(hipStream_t s, const void* phi_src, void* phi, void* lam, const TileArgs& a,
                                  const TOp* ops, const void* coef, const uint64_t* words, double* partials, int grid,
                                  int nthr, size_t lds) {
+    if constexpr (TWO && (LR == 3 || LR == 4) && !GEN) {
+        if (a.flags & TILE_LAMZ) {
+            static std::atomic<uint64_t> lz_raised{0};
+            if (lds > 65536) {
+                hipError_t e = allow_big_lds((const void*)k_tile_lamz<T, LR>, lz_raised);
+                if (e != hipSuccess) return e;
+            }
+            hipLaunchKernelGGL((k_tile_lamz<T, LR>), dim3(grid), dim3(nthr), lds, s, (const cx<T>*)phi_src,
+                               (cx<T>*)phi, (cx<T>*)lam, a, ops, (const cx<T>*)coef, words, partials);
+            return hipGetLastError();
+        }
+    }
     if constexpr (LR >= 3 && !GEN) {
         if (a.flags & TILE_WS) {
             // warp-specialised form (the host sized the grid and the LDS for it)

@@ -94,12 +94,19 @@ struct TileArgs {
     int32_t n_outer;        // index bits outside the tile (bits of the tile number)
     uint64_t basis;
     int32_t n_zop;          // Z-parity ops inside register groups (their tb[5] numbers them)
-    int32_t pad_z;
+    int32_t lamz_m;         // TILE_LAMZ: number of Z strings of the observable
     double out_scale;       // the pass's factored layers leave the tile scaled by 1 / out_scale
+    // TILE_LAMZ (first reverse pass, observable = c * sum of lamz_m Z strings):
+    // lambda is formed from the loaded phi instead of read, and <H> goes to
+    // partial row nslots.  Words at lamz_woff: per thread, per register slot
+    // and per tile-number bit, the parity bits of the observable's masks.
+    int64_t lamz_woff;
+    double lamz_c;
 };
 constexpr int32_t TILE_SYNTH = 1;
 constexpr int32_t TILE_NT = 2;  // write back with non-temporal stores
 constexpr int32_t TILE_WS = 4;  // warp-specialised kernel form (two tile buffers, 512 threads)
+constexpr int32_t TILE_LAMZ = 8;  // lambda = H phi formed in the load (diagonal, uniform-coefficient H)
 
 // A dense k-qubit matrix on a tile of 2^(k+6) amplitudes: the k targets and
 // six lane bits (the lowest index bits that are neither targets nor

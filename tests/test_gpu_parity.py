@@ -400,3 +400,33 @@ def test_factored_layers(ctx, gate, dt):
         assert_rel_close(jac, want, jac_bound(ops, len(angles), obs), dt, f"jacobian opts={opts}")
         st.close()
     reset_options(ctx)
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("inplace", [False, True])
+def test_uniform_z_sum_lambda_in_first_pass(ctx, dt, inplace):
+    """An observable that is c times a sum of Z strings (diagonal, one
+    coefficient) takes the path where the first reverse pass forms lambda
+    from the loaded phi and sums <H> itself; gradients and <H> against the
+    oracle, with and without the in-place sweep, plus a non-uniform sum (the
+    separate lambda pass) on the same circuit."""
+    n = 14
+    c = W.random_circuit(n, 60, seed=21, n_params=6)
+    rng = np.random.default_rng(3)
+    words = []
+    for _ in range(9):
+        q = rng.choice(n, size=int(rng.integers(1, 4)), replace=False)
+        words.append(W.pauli_word(n, {int(x): "Z" for x in q}))
+    for coeffs in (np.full(9, -0.7), rng.normal(size=9)):
+        obs = [W.PauliSum(coeffs, words)]
+        reset_options(ctx)
+        st = qsv.State(ctx, n, dt)
+        qsv.apply(st, c.ops, c.params)
+        psi = oracle.apply(n, c.ops, c.params)
+        jac, ev = qsv.adjoint_jacobian(st, c.ops, c.params, obs, inplace=inplace)
+        assert_rel_close(jac, oracle.adjoint_jacobian(psi, c.ops, c.params, obs),
+                         jac_bound(c.ops, c.n_params, obs), dt, f"jacobian uniform={coeffs[0] == coeffs[1]}")
+        assert_rel_close(ev, oracle.expval(psi, obs), obs_scale(obs), dt, f"expval uniform={coeffs[0] == coeffs[1]}")
+        if inplace:  # the in-place sweep hands back the initial state
+            assert_state_close(st.to_numpy(), oracle.zero_state(n), TOL[dt], "initial state", dt)
+        st.close()
