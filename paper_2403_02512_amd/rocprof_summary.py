@@ -35,7 +35,8 @@ import sys
 
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
-KINDS = [("k_tile<double, true", "tile2"), ("k_tile<double, false", "tile1"), ("k_tile<float, true", "tile2_c64"),
+KINDS = [("k_tile<double, true", "tile2"), ("k_tile_lamz<double", "tile2"), ("k_tile_lamz<float", "tile2_c64"),
+         ("k_tile<double, false", "tile1"), ("k_tile<float, true", "tile2_c64"),
          ("k_tile<float, false", "tile1_c64"), ("k_pauli<double, true", "pauli_lambda"),
          ("k_pauli<double, false", "pauli"), ("__amd_rocclr_copyBuffer", "copy"), ("k_init", "init"),
          ("k_reduce", "reduce"), ("k_gate1", "gate1"), ("k_diag1", "diag1"), ("k_gate2", "gate2"),
@@ -230,16 +231,20 @@ def read_traffic(path: str):
     current library sources, else None."""
     if not os.path.exists(path):
         return None
-    kv, sha = {}, None
+    tot, cnt, sha = collections.defaultdict(float), collections.defaultdict(int), None
     for line in open(path):
         if line.startswith("library_source_sha1="):
             sha = line.strip().split("=", 1)[1]
         elif line.startswith("kind="):
+            # one line per kernel; a kind with several kernels (the first
+            # reverse pass's form) averages over all their dispatches
             d = dict(x.split("=", 1) for x in line.split())
-            kv.setdefault(d["kind"], float(d["traffic_bytes"]))
+            k = int(d.get("dispatches", 1))
+            tot[d["kind"]] += float(d["traffic_bytes"]) * k
+            cnt[d["kind"]] += k
     if sha != source_sha1():
         return None
-    return kv
+    return {k: tot[k] / cnt[k] for k in tot}
 
 
 def main(argv=None):
