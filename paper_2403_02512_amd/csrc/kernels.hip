@@ -134,11 +134,20 @@ hipError_t launch_diag1(hipStream_t s, void* psi, uint64_t n_items, const Expand
 // ------------------------------------------------------------------ two-qubit streaming kernel
 
 template <typename T, int CLS>
+__device__ __forceinline__ void gate2_quad(cx<T>* __restrict__ psi, uint64_t i, uint64_t b0, uint64_t b1,
+                                           const Mat4& mat, int nt);
+
+template <typename T, int CLS>
 __global__ __launch_bounds__(256) void k_gate2(cx<T>* __restrict__ psi, uint64_t n_items, Expand ex,
                                                uint64_t setmask, uint64_t b0, uint64_t b1, Mat4 mat, int nt) {
-    const uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k >= n_items) return;
-    const uint64_t i = expand_idx(k, ex) | setmask;
+    // grid-stride: a launch holds fewer than 2^32 threads
+    for (uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x; k < n_items; k += (uint64_t)gridDim.x * 256)
+        gate2_quad<T, CLS>(psi, expand_idx(k, ex) | setmask, b0, b1, mat, nt);
+}
+
+template <typename T, int CLS>
+__device__ __forceinline__ void gate2_quad(cx<T>* __restrict__ psi, uint64_t i, uint64_t b0, uint64_t b1,
+                                           const Mat4& mat, int nt) {
     const uint64_t idx[4] = {i, i | b1, i | b0, i | b0 | b1};
     if (CLS == MC_MID) {  // only |01>, |10> mix; |00>, |11> untouched
         const cx<T> x1 = psi[idx[1]], x2 = psi[idx[2]];
@@ -165,11 +174,82 @@ __global__ __launch_bounds__(256) void k_gate2(cx<T>* __restrict__ psi, uint64_t
     }
 }
 
+// A matrix entry of the by-value kernel argument as a wave-uniform register
+// value.  Selecting between such values per lane stays a register select; a
+// select between the argument's own elements is turned into an indexed access,
+// which copies the whole matrix to per-lane scratch memory.
+__device__ __forceinline__ double uniform_value(double x) {
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double select4(int q, double a, double b, double c, double d) {
+    const double lo = (q & 1) ? b : a, hi = (q & 1) ? d : c;
+    return (q & 2) ? hi : lo;
+}
+
+// The same 4x4 update with one lane per amplitude: the four lanes of a DPP
+// quad hold one quad's amplitudes (lane q: index bits b0 b1 = q >> 1, q & 1)
+// and exchange them by quad_perm broadcasts.  For targets among the lowest
+// index bits the quad-per-lane form strides its loads by the quad size
+// (several passes over each cache line per instruction); here consecutive
+// lanes read consecutive amplitudes.
+template <typename T, int CLS>
+__global__ __launch_bounds__(256) void k_gate2_lanes(cx<T>* __restrict__ psi, uint64_t n_items, Expand ex,
+                                                     uint64_t setmask, uint64_t b0, uint64_t b1, Mat4 mat, int nt) {
+    const int q = (int)(threadIdx.x & 3);
+    // this lane's row of the matrix (row q; the diagonal entry only for a
+    // diagonal matrix), built once
+    constexpr int NJ = CLS == MC_DIAG ? 1 : 4;
+    cx<T> row[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int c0 = CLS == MC_DIAG ? 0 : j, st = CLS == MC_DIAG ? 5 : 4;
+        row[j] = {(T)select4(q, uniform_value(mat.re[c0]), uniform_value(mat.re[st + c0]),
+                             uniform_value(mat.re[2 * st + c0]), uniform_value(mat.re[3 * st + c0])),
+                  (T)select4(q, uniform_value(mat.im[c0]), uniform_value(mat.im[st + c0]),
+                             uniform_value(mat.im[2 * st + c0]), uniform_value(mat.im[3 * st + c0]))};
+    }
+    // grid-stride (a launch holds fewer than 2^32 threads); the stride is a
+    // multiple of 4, so a quad's four lanes share the item and leave together
+    for (uint64_t gid = (uint64_t)blockIdx.x * 256 + threadIdx.x; (gid >> 2) < n_items;
+         gid += (uint64_t)gridDim.x * 256) {
+        const uint64_t i = expand_idx(gid >> 2, ex) | setmask | ((q & 2) ? b0 : 0) | ((q & 1) ? b1 : 0);
+        const cx<T> v = psi[i];
+        if constexpr (CLS == MC_DIAG) {
+            st_amp(psi + i, cmul(row[0], v), nt);
+        } else {
+            // the quad's four amplitudes, broadcast from their lanes
+            cx<T> acc = cmul(row[0], cx<T>{quad_lane<0>(v.re), quad_lane<0>(v.im)});
+            acc = cmad(row[1], cx<T>{quad_lane<1>(v.re), quad_lane<1>(v.im)}, acc);
+            acc = cmad(row[2], cx<T>{quad_lane<2>(v.re), quad_lane<2>(v.im)}, acc);
+            acc = cmad(row[3], cx<T>{quad_lane<3>(v.re), quad_lane<3>(v.im)}, acc);
+            st_amp(psi + i, acc, nt);
+        }
+    }
+}
+
 template <typename T>
 hipError_t launch_gate2(hipStream_t s, void* psi, uint64_t n_items, const Expand& ex, uint64_t setmask, uint64_t b0,
                         uint64_t b1, int cls, const Mat4& m, bool nt) {
-    const uint64_t blocks = (n_items + 255) / 256;
+    const uint64_t blocks = std::min<uint64_t>((n_items + 255) / 256, 1u << 22);
     dim3 g((unsigned)blocks), b(256);
+    // a target among the three lowest index bits (one cache line holds 8
+    // complex128 amplitudes): one lane per amplitude
+    const bool low = ((b0 | b1) & 7) != 0 && cls != MC_MID;
+    if (low) {
+        const uint64_t lanes = 4 * n_items;
+        dim3 gl((unsigned)std::min<uint64_t>((lanes + 255) / 256, 1u << 22));
+        if (cls == MC_DIAG)
+            hipLaunchKernelGGL((k_gate2_lanes<T, MC_DIAG>), gl, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, b0, b1,
+                               m, (int)nt);
+        else
+            hipLaunchKernelGGL((k_gate2_lanes<T, MC_DENSE>), gl, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, b0, b1,
+                               m, (int)nt);
+        return hipGetLastError();
+    }
     if (cls == MC_MID)
         hipLaunchKernelGGL((k_gate2<T, MC_MID>), g, b, 0, s, (cx<T>*)psi, n_items, ex, setmask, b0, b1, m, (int)nt);
     else if (cls == MC_DIAG)

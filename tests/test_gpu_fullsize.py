@@ -192,3 +192,39 @@ def test_u3_brickwall_32q_adjoint_vs_gpu_shift_rule(ctx):
                abs(jac[0, p] - ps), 1e-11)
     st.close()
     ctx.release_workspace()
+
+
+@pytest.mark.parametrize("n,dt", [(32, qsv.C128), (33, qsv.C64)])
+def test_two_qubit_streaming_low_bits_full_size(ctx, n, dt):
+    """One kernel per gate (no tile fusion): two-qubit gates of every kernel
+    class with targets among the three lowest index bits (the one lane per
+    amplitude kernel, whose 2^n lanes exceed one launch's thread limit and
+    run grid-stride), then their inverses in reverse order: the state
+    returns to |0..0>."""
+    w = lambda bit: n - 1 - bit
+    pairs = [(0, 1), (1, 2), (2, 0), (0, n - 1), (n - 2, 1)]
+    ops = [W.op("Hadamard", [w(b)]) for b in (0, 1, 2, n - 1, n - 2)]
+    k = 0
+    for g in ("IsingXX", "IsingYY", "SingleExcitation", "IsingZZ", "CRX", "CNOT"):
+        for a, b in pairs:
+            par = () if g == "CNOT" else ((k, 1.0),)
+            ops.append(W.op(g, [w(a), w(b)], *par))
+            k += 1
+    params = np.random.default_rng(3).uniform(-math.pi, math.pi, k)
+    mirror = ops + [W.Op(o.name, o.wires, o.param, o.scale, not o.inverse) for o in reversed(ops)]
+    st = qsv.State(ctx, n, dt)
+    ctx.set_option(qsv.OPT_FUSION, 0)
+    try:
+        qsv.apply(st, mirror, params)
+    finally:
+        ctx.set_option(qsv.OPT_FUSION, 1)
+    allz = W.PauliSum(np.ones(n) / n, [W.pauli_word(n, {x: "Z"}) for x in range(n)])
+    norm = W.PauliSum(np.array([1.0]), ["I" * n])
+    ev = qsv.expval(st, [allz, norm])
+    tol = 1e-12 if dt == qsv.C128 else 1e-5
+    dname = "c128" if dt == qsv.C128 else "c64"
+    _report("gate2-low", n=n, err_z=abs(ev[0] - 1), err_norm=abs(ev[1] - 1))
+    _check(f"{n}q two-qubit gates on low bits, one kernel each, mirrored", "mean <Z_w> abs", dname,
+           abs(ev[0] - 1), tol)
+    _check(f"{n}q two-qubit gates on low bits, one kernel each, mirrored", "norm abs", dname, abs(ev[1] - 1), tol)
+    st.close()
