@@ -597,6 +597,17 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
     // targets of local ops are positions in Q and Z-parity tables are indexed
     // by subcube and element; standalone ops use the per-thread / per-r layout.
     auto emit = [&](const Proto& pr, const std::vector<int>* Q, int& dslot) {
+        // a Z-parity rotation right after the inner product of the same Z
+        // strings in a group joins it (one parity count per element)
+        if (Q && pr.kind == Proto::ZPHASE && P.tops.back().kind == OP_DOTZSUM &&
+            P.tops.back().m == (int)pr.z.size() &&
+            std::equal(pr.z.begin(), pr.z.end(), P.words.begin() + P.tops.back().woff)) {
+            const int m = (int)pr.z.size();
+            P.tops.back().kind = OP_ZPHDOT;
+            zpatch.push_back({P.tops.size() - 1, (int)ztab.size()});
+            for (int cnt = 0; cnt <= m; ++cnt) ztab.push_back(std::exp(cd(0.0, -0.5 * pr.angle * (m - 2 * cnt))));
+            return;
+        }
         TOp op;
         std::memset(&op, 0, sizeof op);
         op.k = pr.k;
@@ -999,7 +1010,7 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
                 int nz = 0;
                 for (int si = 0; si < P.tops[gidx].m && nz < 2; ++si) {
                     const int k = P.tops[gidx + 1 + si].kind;
-                    if (k == OP_ZPHASE || k == OP_DOTZSUM) P.tops[gidx].tb[4 + nz++] = si;
+                    if (k == OP_ZPHASE || k == OP_DOTZSUM || k == OP_ZPHDOT) P.tops[gidx].tb[4 + nz++] = si;
                 }
             }
             i = e;
@@ -1011,8 +1022,10 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
     a.zt_off = (int64_t)P.coef.size();
     a.zt_n = (int)ztab.size();
     for (auto& zp : zpatch) {
-        P.tops[zp.first].coff = a.zt_off + zp.second;
-        P.tops[zp.first].aux = zp.second;
+        TOp& t = P.tops[zp.first];
+        t.coff = a.zt_off + zp.second;
+        if (t.kind == OP_ZPHDOT) t.lcval = (uint32_t)zp.second;  // aux is its inner-product index
+        else t.aux = zp.second;
     }
     for (auto& x : ztab) P.coef.push_back(x);
     st.nslots = nslots;
@@ -1985,9 +1998,10 @@ qsv_status qsv_plan_json(int n, qsv_dtype dt, const qsv_op* ops, size_t n_ops, c
                 const TileArgs& a = st.ta;
                 add(",\"b\":%d,\"nthr\":%d,\"R\":%d,\"grid\":%d,\"op0\":%d,\"nops\":%d,\"nslots\":%d,\"slot_base\":%d,"
                     "\"generic\":%d,\"n_tiles\":%llu,\"n_outer\":%d,\"lds\":%zu,\"flags\":%d,"
-                    "\"out_scale\":%.17g,\"sb\":[",
+                    "\"out_scale\":%.17g,\"zt_off\":%lld,\"zt_n\":%d,\"sb\":[",
                     a.b, st.nthr, st.R, st.grid, a.op0, a.nops, a.nslots, st.slot_base, (int)st.generic,
-                    (unsigned long long)a.n_tiles, a.n_outer, st.lds, a.flags, a.out_scale);
+                    (unsigned long long)a.n_tiles, a.n_outer, st.lds, a.flags, a.out_scale, (long long)a.zt_off,
+                    a.zt_n);
                 for (int j = 0; j < a.b; ++j) add(j ? ",%d" : "%d", a.sb[j]);
                 js += "],\"offhi\":[";
                 for (int r = 0; r < st.R; ++r) add(r ? ",%llu" : "%llu", (unsigned long long)a.offhi[r]);

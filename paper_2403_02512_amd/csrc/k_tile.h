@@ -729,6 +729,23 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
                     if (TWO) l[e] = cmul(d, l[e]);
                 }
             } break;
+            case OP_ZPHDOT:
+                if constexpr (TWO) {
+                    const uint64_t* z = c.words + s.woff;
+                    const uint64_t pc = zbits(s, si);
+                    double v = 0.0;
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        const int cnt = (int)__popcll(pc ^ z[s.m + nsub + e]);
+                        v = __builtin_fma((double)(s.m - 2 * cnt), im_conj_mul(l[e], a[e]), v);
+                        const cx<T> d = c.ztab[s.lcval + cnt];
+                        a[e] = cmul(d, a[e]);
+                        l[e] = cmul(d, l[e]);
+                    }
+                    if (inloop) row_flush(v, s.slot);
+                    else acc.add(s.aux, v);
+                }
+                break;
             default:
                 if constexpr (TWO) {
                     double v = 0.0;
@@ -820,7 +837,7 @@ __device__ __forceinline__ void tile_group(const TileCtx<T, TWO, R>& c, const TO
                     if (s.lcmask & (1u << p)) flush(ai++, s.tb[p]);
                 continue;
             }
-            if (s.kind < OP_DOT1 || s.kind == OP_DOTK || s.kind > OP_DOTZSUM) continue;
+            if ((s.kind < OP_DOT1 || s.kind == OP_DOTK || s.kind > OP_DOTZSUM) && s.kind != OP_ZPHDOT) continue;
             if (inloop) continue;  // reduced inside the loop
             flush(s.aux, s.slot);
         }
@@ -908,7 +925,7 @@ __device__ __forceinline__ void tile_body(const cx<T>* phi_src, cx<T>* phi,
             if (op.kind != OP_GROUP) continue;
             for (int si = 0; si < op.m; ++si) {
                 const TOp& s = ops[a.op0 + oi + 1 + si];
-                if (s.kind != OP_ZPHASE && s.kind != OP_DOTZSUM) continue;
+                if (s.kind != OP_ZPHASE && s.kind != OP_DOTZSUM && s.kind != OP_ZPHDOT) continue;
                 const uint64_t* cols = words + s.woff + s.m + nsub + (1 << GBv);
                 for (int j = tid; j < a.n_outer; j += nthr) zcol[(size_t)s.tb[5] * a.n_outer + j] = cols[j];
             }

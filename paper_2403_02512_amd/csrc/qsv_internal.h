@@ -42,11 +42,16 @@ enum TOpKind : int32_t {
     OP_DOTDIAG,     // slot += Im <lam|D|phi> for diagonal D on global bits
     OP_DOTZSUM,     // slot += Im <lam| sum_j Z^{z_j} |phi>
     OP_GROUP,       // the next m ops act inside register subcubes over the k tile bits tb[0..k-1]
-    OP_LAYER1       // in a group: for each group position p ascending, an optional inner
+    OP_LAYER1,      // in a group: for each group position p ascending, an optional inner
                     // product with a one-qubit generator on p (bit p of lcmask; slot tb[p];
                     // generator class code lcval, LayerGen), then the 2x2 matrix of class cls on p
                     // (bit p of m: the layer has a gate on p; elsewhere the table
                     // holds the identity)
+    OP_ZPHDOT       // in a group: DOTZSUM then ZPHASE over the same Z strings, one parity
+                    // count per element (slot, aux and the parity words as DOTZSUM; phase
+                    // table at coff, at lcval inside the pass's table in LDS).  The inner
+                    // product is the same before and after the phase, which multiplies
+                    // phi and lambda alike by a unit-modulus diagonal
 };
 
 // Matrix classes.  DENSE/DIAG/ANTI/MID are used by every kernel; the finer

@@ -11,7 +11,7 @@ The streaming single-gate passes are modelled by their index sets.
 import numpy as np
 
 OP_APPLY1, OP_APPLY2, OP_APPLYK, OP_DIAG, OP_ZPHASE, OP_DOT1, OP_DOT2, OP_DOTK, OP_DOTDIAG, OP_DOTZSUM, OP_GROUP, \
-    OP_LAYER1 = range(1, 13)
+    OP_LAYER1, OP_ZPHDOT = range(1, 14)
 MC_DENSE, MC_DIAG, MC_ANTI, MC_MID, MC_REAL, MC_RIRI, MC_PX, MC_PY, MC_RIRI_D, MC_RIRI_O, MC_REAL_D, MC_REAL_O = range(12)
 
 
@@ -285,7 +285,7 @@ def _group(prog, st, g, subs, tp, tl, base, slots, T):
             else:
                 v = np.where(on, np.conj(l) * d[j] * a, 0)
                 slots[st["slot_base"] + s["slot"]] += v.imag.sum()
-        elif kind in (OP_ZPHASE, OP_DOTZSUM):
+        elif kind in (OP_ZPHASE, OP_DOTZSUM, OP_ZPHDOT):
             mz = s["m"]
             z = w[s["woff"]:s["woff"] + mz]
             pb = _tile_parity(w, s["woff"] + mz + nsub + E, st["n_outer"], T)
@@ -293,14 +293,18 @@ def _group(prog, st, g, subs, tp, tl, base, slots, T):
             pcs = np.array(w[s["woff"] + mz:s["woff"] + mz + nsub], dtype=np.int64)
             pes = np.array(w[s["woff"] + mz + nsub:s["woff"] + mz + nsub + E], dtype=np.int64)
             cnt = np.vectorize(popc)(pb ^ pcs[:, None] ^ pes[None, :])
-            if kind == OP_ZPHASE:
+            if kind in (OP_DOTZSUM, OP_ZPHDOT):
+                v = (mz - 2 * cnt) * (np.conj(l) * a).imag
+                slots[st["slot_base"] + s["slot"]] += v.sum()
+            if kind in (OP_ZPHASE, OP_ZPHDOT):
+                if kind == OP_ZPHDOT:  # the kernel reads the pass's LDS copy of the tables at lcval
+                    assert s["coff"] == st["zt_off"] + s["lcval"] and s["lcval"] + mz + 1 <= st["zt_n"]
+                else:
+                    assert s["coff"] == st["zt_off"] + s["aux"] and s["aux"] + mz + 1 <= st["zt_n"]
                 d = _coef(prog, s["coff"], mz + 1)[cnt]
                 a *= d
                 if l is not None:
                     l *= d
-            else:
-                v = (mz - 2 * cnt) * (np.conj(l) * a).imag
-                slots[st["slot_base"] + s["slot"]] += v.sum()
         elif kind == OP_LAYER1:
             # per position P ascending: optional inner product, then the 2x2
             gcode = s["lcval"]  # 0 none, 1 X, 2 Y, 3 dense, 4 real diagonal
