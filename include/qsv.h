@@ -107,9 +107,11 @@ const char *qsv_thread_last_error(void);
 int qsv_device_count(void);
 
 /* ---------------------------------------------------------------- context */
-/* Create a context on `device`.  hip_stream: a hipStream_t to issue all work
- * on (borrowed, e.g. torch's current stream), or NULL for a library-owned
- * stream.  *out is owned by the caller and released by qsv_ctx_destroy. */
+/* Create a context on `device` (paper Sec. 2.2: the GPU device selects its
+ * GPU at run time and manages that GPU's memory and transfers).  hip_stream: a
+ * hipStream_t to issue all work on (borrowed, e.g. torch's current stream), or
+ * NULL for a library-owned stream.  *out is owned by the caller and released
+ * by qsv_ctx_destroy. */
 qsv_status qsv_ctx_create(int device, void *hip_stream, qsv_ctx **out);
 void qsv_ctx_destroy(qsv_ctx *ctx);
 const char *qsv_last_error(const qsv_ctx *ctx);
@@ -156,7 +158,10 @@ qsv_status qsv_ctx_kernel_stats(qsv_ctx *ctx, int kind, int64_t *launches, doubl
 qsv_status qsv_ctx_reset_stats(qsv_ctx *ctx);
 
 /* ---------------------------------------------------------------- states */
-/* Allocate an owned state of n_qubits (1..QSV_MAX_QUBITS) in |0..0>. */
+/* Allocate an owned state of n_qubits (1..QSV_MAX_QUBITS) in |0..0>, resident
+ * in device memory (paper Sec. 2.2: gates, observables and the adjoint method
+ * work directly on the GPU-resident state vector; Sec. 2: complex64 or
+ * complex128 by dtype). */
 qsv_status qsv_state_create(qsv_ctx *ctx, int n_qubits, qsv_dtype dtype, qsv_state **out);
 /* Wrap caller-owned device memory of 2^n amplitudes (e.g. a torch tensor's
  * storage, 16-byte aligned for C128, 8 for C64).  The library never frees it;
