@@ -8,7 +8,9 @@
 //            fixed: PhaseShift/Z/S/T and their controlled forms scale only
 //            the |1> amplitudes, so they read and write half the vector
 //            (Sec. 2.1.1, Listing 1)
-//  k_gate2   4x4 on amplitude quads (Ising gates, SWAP, Givens rotations)
+//  k_gate2   4x4 on amplitude quads (Ising gates, SWAP, Givens rotations);
+//            k_gate2_lanes: one lane per amplitude when a target is among
+//            the lowest index bits (quad exchange by DPP)
 //  k_gatek   2^k x 2^k on 2^k-tuples, k = 3..5, one tuple per thread
 //  k_tile    (k_tile.h, instantiated in tile_*.hip) LDS-staged pass: a tile
 //            of 2^b amplitudes spanning b index bits (always including the
