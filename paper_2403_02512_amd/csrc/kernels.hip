@@ -671,11 +671,17 @@ hipError_t launch_tile_batch(hipStream_t s, bool two, bool generic, const TileEn
 
 // Table state of one block: LDS offsets, parity columns and the thread's
 // constant parity part of (up to) two table groups.
+// Two table slots, as named fields: the slot of a group is a runtime value,
+// and an array indexed by it would live in per-lane scratch memory.
 struct LutState {
     int nslot;
-    int toff[2];
-    const uint64_t* cols[2];
-    uint64_t pthr[2];
+    int toff0, toff1;                   // the slots' table offsets in LDS
+    const uint64_t* cols0;              // per index bit: its parity part
+    const uint64_t* cols1;
+    uint64_t pthr0, pthr1;              // this thread's parity parts
+};
+struct LutIter {
+    uint64_t p0, p1;  // the iteration's parity parts of slots 0 and 1
 };
 
 // Copy the observable's byte tables into LDS and set up the parity parts for
@@ -684,9 +690,9 @@ struct LutState {
 __device__ __forceinline__ void lut_setup(LutState& L, const PauliGroupDev* __restrict__ groups, int n_groups,
                                           const uint64_t* __restrict__ aux, cx<double>* tabs, uint64_t base0) {
     L.nslot = 0;
-    L.toff[0] = L.toff[1] = 0;
-    L.cols[0] = L.cols[1] = nullptr;
-    L.pthr[0] = L.pthr[1] = 0;
+    L.toff0 = L.toff1 = 0;
+    L.cols0 = L.cols1 = nullptr;
+    L.pthr0 = L.pthr1 = 0;
     int tot = 0;
     for (int g = 0; g < n_groups; ++g) {
         const PauliGroupDev gr = groups[g];
@@ -698,10 +704,15 @@ __device__ __forceinline__ void lut_setup(LutState& L, const PauliGroupDev* __re
         const uint64_t s0 = base0 ^ gr.x;  // the source index without the iteration's bits
         for (int k = 0; k < 64; ++k)
             if ((s0 >> k) & 1) p ^= cl[k];
-        const int sl = gr.lut & 1;
-        L.toff[sl] = tot * 256;
-        L.cols[sl] = cl;
-        L.pthr[sl] = p;
+        if (gr.lut & 1) {
+            L.toff1 = tot * 256;
+            L.cols1 = cl;
+            L.pthr1 = p;
+        } else {
+            L.toff0 = tot * 256;
+            L.cols0 = cl;
+            L.pthr0 = p;
+        }
         tot += gr.nb;
         ++L.nslot;
     }
@@ -709,18 +720,18 @@ __device__ __forceinline__ void lut_setup(LutState& L, const PauliGroupDev* __re
 }
 
 // Weight sum_t w_t (-1)^{parity(src & z_t)} of one group at source index src
-// (it_par: the iteration's parity parts of the table groups).
+// (it: the iteration's parity parts of the table groups).
 template <typename T>
 __device__ __forceinline__ void group_weight(const PauliGroupDev& gr, uint64_t src,
                                              const PauliTermDev* __restrict__ terms, const LutState& L,
-                                             const cx<double>* tabs, const uint64_t* it_par, double& sr,
+                                             const cx<double>* tabs, const LutIter& it, double& sr,
                                              double& si) {
     sr = 0.0;
     si = 0.0;
     if (gr.lut >= 0) {
-        const int sl = gr.lut & 1;
-        const uint64_t p = L.pthr[sl] ^ it_par[sl];
-        const cx<double>* tb = tabs + L.toff[sl];
+        const bool s1 = gr.lut & 1;
+        const uint64_t p = s1 ? (L.pthr1 ^ it.p1) : (L.pthr0 ^ it.p0);
+        const cx<double>* tb = tabs + (s1 ? L.toff1 : L.toff0);
         for (int b = 0; b < gr.nb; ++b) {
             const cx<double> e = tb[b * 256 + (int)((p >> (8 * b)) & 255)];
             sr += e.re;
@@ -743,7 +754,7 @@ template <typename T>
 __device__ __forceinline__ void pauli_row(const cx<T>* __restrict__ psi, uint64_t i, cx<T> pi,
                                           const PauliGroupDev* __restrict__ groups, int n_groups,
                                           const PauliTermDev* __restrict__ terms, const LutState& L,
-                                          const cx<double>* tabs, const uint64_t* it_par, double& ar, double& ai) {
+                                          const cx<double>* tabs, const LutIter& it, double& ar, double& ai) {
     ar = 0.0;
     ai = 0.0;
     constexpr int U = 4;
@@ -759,7 +770,7 @@ __device__ __forceinline__ void pauli_row(const cx<T>* __restrict__ psi, uint64_
         for (int u = 0; u < U; ++u) {
             const PauliGroupDev gr = groups[g + u];
             double sr, si;
-            group_weight<T>(gr, i ^ gr.x, terms, L, tabs, it_par, sr, si);
+            group_weight<T>(gr, i ^ gr.x, terms, L, tabs, it, sr, si);
             ar += sr * (double)ps[u].re - si * (double)ps[u].im;
             ai += sr * (double)ps[u].im + si * (double)ps[u].re;
         }
@@ -768,21 +779,20 @@ __device__ __forceinline__ void pauli_row(const cx<T>* __restrict__ psi, uint64_
         const PauliGroupDev gr = groups[g];
         const cx<T> ps = gr.x ? psi[i ^ gr.x] : pi;
         double sr, si;
-        group_weight<T>(gr, i ^ gr.x, terms, L, tabs, it_par, sr, si);
+        group_weight<T>(gr, i ^ gr.x, terms, L, tabs, it, sr, si);
         ar += sr * (double)ps.re - si * (double)ps.im;
         ai += sr * (double)ps.im + si * (double)ps.re;
     }
 }
 
 // the iteration's uniform parity parts: columns of the iteration's bits
-__device__ __forceinline__ void lut_iter(const LutState& L, uint64_t it, int lstride, uint64_t* it_par) {
-    it_par[0] = it_par[1] = 0;
-    for (int sl = 0; sl < 2; ++sl) {
-        if (!L.cols[sl]) continue;
-        uint64_t p = 0;
-        for (uint64_t r = it; r; r &= r - 1) p ^= L.cols[sl][lstride + __ffsll((unsigned long long)r) - 1];
-        it_par[sl] = p;
-    }
+__device__ __forceinline__ LutIter lut_iter(const LutState& L, uint64_t it, int lstride) {
+    LutIter o = {0, 0};
+    if (L.cols0)
+        for (uint64_t r = it; r; r &= r - 1) o.p0 ^= L.cols0[lstride + __ffsll((unsigned long long)r) - 1];
+    if (L.cols1)
+        for (uint64_t r = it; r; r &= r - 1) o.p1 ^= L.cols1[lstride + __ffsll((unsigned long long)r) - 1];
+    return o;
 }
 
 // One thread's share of an observable sweep: indices base0, base0 + stride,
@@ -797,10 +807,9 @@ __device__ __forceinline__ void pauli_sweep(const cx<T>* __restrict__ psi, cx<T>
                                             const cx<double>* tabs, double& dot, double& nrm) {
     constexpr int U = 4;
     auto row = [&](uint64_t i, uint64_t it, cx<T> pi) {
-        uint64_t it_par[2];
-        lut_iter(L, it, lstride, it_par);
+        const LutIter itp = lut_iter(L, it, lstride);
         double ar, ai;
-        pauli_row<T>(psi, i, pi, groups, n_groups, terms, L, tabs, it_par, ar, ai);
+        pauli_row<T>(psi, i, pi, groups, n_groups, terms, L, tabs, itp, ar, ai);
         if (WRITE) lam[i] = cx<T>{(T)ar, (T)ai};
         dot += (double)pi.re * ar + (double)pi.im * ai;
         if (NORM2) nrm += ar * ar + ai * ai;
