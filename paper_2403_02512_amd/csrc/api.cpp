@@ -599,7 +599,7 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
     auto emit = [&](const Proto& pr, const std::vector<int>* Q, int& dslot) {
         // a Z-parity rotation right after the inner product of the same Z
         // strings in a group joins it (one parity count per element)
-        if (Q && pr.kind == Proto::ZPHASE && P.tops.back().kind == OP_DOTZSUM &&
+        if (Q && pr.kind == Proto::ZPHASE && !P.tops.empty() && P.tops.back().kind == OP_DOTZSUM &&
             P.tops.back().m == (int)pr.z.size() &&
             std::equal(pr.z.begin(), pr.z.end(), P.words.begin() + P.tops.back().woff)) {
             const int m = (int)pr.z.size();
