@@ -687,6 +687,23 @@ void lower_tile(Program& P, const std::vector<Factor>& F, const std::vector<Item
         } else {
             for (int i = 0; i < f.k; ++i) op.tb[i] = rank[n - 1 - f.tw[i]];
         }
+        if (!dot && Q && f.k == 1 && P.tops.back().kind == OP_APPLY1) {
+            // right after a one-qubit matrix on the same position with the same
+            // controls (in this group: the group op precedes its sub-ops): one
+            // matrix, the product (the earlier one acts first)
+            TOp& pv = P.tops.back();
+            if (pv.tb[0] == op.tb[0] && pv.lcmask == op.lcmask && pv.lcval == op.lcval && pv.gcmask == op.gcmask &&
+                pv.gcval == op.gcval) {
+                cd* m0 = &P.coef[(size_t)pv.coff];
+                const cd p[4] = {mm[0] * m0[0] + mm[1] * m0[2], mm[0] * m0[1] + mm[1] * m0[3],
+                                 mm[2] * m0[0] + mm[3] * m0[2], mm[2] * m0[1] + mm[3] * m0[3]};
+                const std::vector<cd> pm(p, p + 4);
+                for (int j = 0; j < 4; ++j) m0[j] = p[j];
+                pv.cls = classify1(pm);
+                if (pv.cls == MC_ANTI && p[1] == 1.0 && p[2] == 1.0) pv.cls = MC_PX;
+                return;
+            }
+        }
         if (dot) {
             op.kind = f.k == 1 ? OP_DOT1 : (f.k == 2 ? OP_DOT2 : OP_DOTK);
             if (Q && f.k == 1) op.cls = classify_gen1(mm);

@@ -46,6 +46,7 @@ def reset_options(ctx):
     ctx.set_option(qsv.OPT_LOW_BITS, 0)
     ctx.set_option(qsv.OPT_TILE_WS, 0)
     ctx.set_option(qsv.OPT_DENSE_MFMA, 0)
+    ctx.set_option(qsv.OPT_LAYERS, 1)
 
 
 def obs_scale(observables):

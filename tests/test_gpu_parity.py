@@ -216,6 +216,40 @@ def test_qaoa_reduced_width(ctx, n, dt):
     assert_rel_close(ev, oracle.expval(psi, c.observables), obs_scale(c.observables), dt, "expval")
 
 
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("layers", [1, 0])
+@pytest.mark.parametrize("n", [8, 13])
+def test_adjacent_one_qubit_matrices(ctx, n, layers, dt):
+    """Runs of one-qubit gates on one wire (RY, then H S T, a CNOT brick
+    between layers): in a register group the matrices that follow each other
+    on one position run as their product; state and Jacobian against the
+    oracle, with and without one-qubit layers."""
+    rng = np.random.default_rng(n)
+    ops, k = [], 0
+    for _ in range(3):
+        for w in range(n):
+            ops.append(W.op("RY", [w], (k, 1.0)))
+            k += 1
+            ops += [W.op("Hadamard", [w]), W.op("S", [w]), W.op("T", [w])]
+        for w in range(0, n - 1, 2):
+            ops.append(W.op("CNOT", [w, w + 1]))
+    params = rng.uniform(-np.pi, np.pi, k)
+    obs = [W.PauliSum(np.array([0.7, -0.4]), [W.pauli_word(n, {0: "Z", n - 3: "X"}), W.pauli_word(n, {3: "Y"})])]
+    reset_options(ctx)
+    ctx.set_option(qsv.OPT_LAYERS, layers)
+    try:
+        st = qsv.State(ctx, n, dt)
+        qsv.apply(st, ops, params)
+        psi = oracle.apply(n, ops, params)
+        assert_state_close(st.to_numpy(), psi, TOL[dt], "state", dt)
+        jac, ev = qsv.adjoint_jacobian(st, ops, params, obs)
+        ref = oracle.adjoint_jacobian(psi, ops, params, obs)
+        assert_rel_close(jac, ref, jac_bound(ops, k, obs), dt, "jacobian")
+        st.close()
+    finally:
+        reset_options(ctx)
+
+
 @pytest.mark.parametrize("n", [6, 11])
 def test_u3_brickwall_reduced_width(ctx, n):
     c = W.config5(n=n, layers=6)

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
+from paper_2403_02512_amd import qsv
 from paper_2403_02512_amd import workloads as W
 from tests.program_emulator import emulate_adjoint, emulate_apply
 
@@ -130,3 +131,38 @@ def test_factored_layers(gate):
         classes |= {o["cls"] for o in pj["tops"] if o["kind"] == 12}
     d, o = (8, 9) if gate == "RX" else (10, 11)
     assert d in classes and o in classes, classes
+
+
+def _same_wire_runs(n=8, layers=3, seed=7):
+    rng = np.random.default_rng(seed)
+    ops, k = [], 0
+    for _ in range(layers):
+        for w in range(n):
+            ops.append(W.op("RY", [w], (k, 1.0)))
+            k += 1
+            ops += [W.op("Hadamard", [w]), W.op("S", [w]), W.op("T", [w])]
+        for w in range(0, n - 1, 2):
+            ops.append(W.op("CNOT", [w, w + 1]))
+    return ops, rng.uniform(-np.pi, np.pi, k)
+
+
+@pytest.mark.parametrize("opts", [{}, {"tile_bits": 6, "low_bits": 2}, {"fusion": 2}])
+def test_adjacent_one_qubit_matrices_merge(opts):
+    """One-qubit matrices that follow each other on one position of a
+    register group, with the same controls and nothing between them, are
+    lowered as one matrix (their product, the earlier acting first)."""
+    n = 8
+    ops, params = _same_wire_runs(n)
+    obs = [W.PauliSum(np.array([0.7, -0.4]), [W.pauli_word(n, {0: "Z", 5: "X"}), W.pauli_word(n, {3: "Y"})])]
+    psi = oracle.apply(n, ops, params)
+    np.testing.assert_allclose(emulate_apply(n, ops, params, oracle.zero_state(n), **opts), psi, atol=1e-12)
+    lam = oracle.apply_pauli_sum(psi, obs[0])
+    g, phi = emulate_adjoint(n, ops, params, psi, lam, **opts)
+    np.testing.assert_allclose(g, oracle.adjoint_jacobian(psi, ops, params, obs)[0], atol=1e-11)
+    np.testing.assert_allclose(phi, oracle.zero_state(n), atol=1e-12)
+    if opts.get("fusion") == 2:
+        # without layers every one-qubit gate would be its own sub-op: the
+        # runs H S T of each wire become one matrix (with RY before them)
+        fwd = qsv.plan_json(n, ops, params, **opts)
+        n1 = sum(t["kind"] == 1 for t in fwd["tops"])
+        assert n1 < sum(o.name in ("Hadamard", "S", "T") for o in ops)
