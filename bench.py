@@ -450,7 +450,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU state-vector "
-              f"sharding is a design note, not part of this build", file=sys.stderr)
+              f"sharding is described in the design notes and not implemented here", file=sys.stderr)
         sys.exit(2)
 
     if args.batch:
